@@ -1,0 +1,175 @@
+/*
+ * dbie.h - C ABI of the MI355X (gfx950) library for the hot path of direct boundary integral
+ * equation (DBIE) nonlinear force-free field extrapolation (Wang, Yan & Tan, arXiv:1306.1122).
+ *
+ * What it computes (Section 2.1 of the paper):
+ *   For every evaluation point i above the boundary z = 0 and every component p in {x, y, z},
+ *     B_p(i) = sum_k h^2 K(lambda_pi; x_k - x_i, y_k - y_i, z_i) B0_p(k)                (Eq. 16)
+ *     K(lambda; dx, dy, z) = z [lambda r sin(lambda r) + cos(lambda r)] / (2 pi r^3)       (Eq. 6)
+ *   with r^2 = dx^2 + dy^2 + z^2 and the sum over the pixel centres k of the magnetogram (the field
+ *   outside the magnetogram is zero, Eq. 3 and the text around it). The gradient of B_p with respect
+ *   to the point is taken at frozen lambda (the zeroth-order expansion of lambda around the point,
+ *   Eq. 13, in its exact delta -> 0 limit). From B and grad B follow J = curl B (Eq. 14) and the two
+ *   residuals f_i = |J x B| / (|J||B|) (Eq. 8) and g_i = |div B| dV / (|B| dSigma) (Eq. 9). The
+ *   lambda search drives them below a threshold (Eq. 12).
+ *
+ * Conventions for every call:
+ *   - Every device buffer is CALLER-OWNED (e.g. allocated as a PyTorch tensor) unless stated. The
+ *     library owns only the opaque context and the device memory it allocates in dbie_init.
+ *   - All arrays are structure-of-arrays, component-major, C order. "[3][N]" means 3 rows of N.
+ *   - Lengths are in one physical unit (pixels or any other); lambda is in inverse length units.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls enqueue work on
+ *     it and return without synchronising, except where stated (dbie_init, dbie_solve_lambda).
+ *   - Return codes: DBIE_OK, or a negative DBIE_E_* code with a message in dbie_last_error(ctx).
+ *     Argument checks run on the host before anything is enqueued. No call aborts or throws.
+ *     Per-point outcomes go into per-point status arrays, never into the return code.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef DBIE_H
+#define DBIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBIE_API __attribute__((visibility("default")))
+
+typedef struct dbie_ctx dbie_ctx;
+
+/* return codes */
+enum {
+    DBIE_OK = 0,
+    DBIE_E_INVAL = -1,       /* invalid argument (message says which) */
+    DBIE_E_DEVICE = -2,      /* a HIP call failed */
+    DBIE_E_WORKSPACE = -3,   /* device memory could not be allocated */
+    DBIE_E_UNSUPPORTED = -4  /* valid request this build does not support */
+};
+
+/* precision of the bulk pixel sum */
+enum {
+    DBIE_FP64 = 0,   /* every pair in FP64 */
+    DBIE_FP32C = 1   /* far pairs in FP32 with compensated (cascaded FP64) accumulation; pairs with
+                        r < nearfield_radius * h in FP64; residuals in FP64 */
+};
+
+/* lambda-update method of dbie_solve_lambda */
+enum {
+    DBIE_NELDER_MEAD = 0,          /* derivative-free downhill simplex on Phi = f^2 + g^2 (Section 2.1) */
+    DBIE_LEVENBERG_MARQUARDT = 1   /* gradient form: LM in mu = lambda^2 with the mu-tangents */
+};
+
+/* per-point status */
+enum {
+    DBIE_ST_CONVERGED = 0,   /* max(f, g) <= eps (Eq. 12) at the returned lambda */
+    DBIE_ST_BUDGET = 1,      /* trial budget spent; the best lambda found is returned */
+    DBIE_ST_DEGENERATE = 2,  /* |B| = 0: f and g undefined */
+    DBIE_ST_J_ZERO = 3,      /* |J| = 0: f set to 0 (only reported by evaluation, not by a solve) */
+    DBIE_ST_NONFINITE = 4    /* a non-finite value appeared (input lambda or overflow) */
+};
+
+/* One magnetogram: pixel (a, b) has centre (x0 + a h, y0 + b h, 0), a in [0, nx), b in [0, ny).
+ * B0 is a DEVICE pointer to double [3][ny][nx] (Bx, By, Bz planes, x fastest). It is copied in
+ * dbie_init; the caller may free it afterwards. */
+typedef struct {
+    int32_t nx, ny;
+    double x0, y0, h;
+    const double* B0;
+} dbie_boundary;
+
+/* The problem: n_boundaries magnetograms (host array `boundaries`) and n_points evaluation points.
+ * xyz is a DEVICE pointer to double [3][n_points] (x, y, z rows) with z > 0; it is copied in
+ * dbie_init. seg is a HOST array of n_boundaries + 1 non-decreasing offsets with seg[0] = 0 and
+ * seg[n_boundaries] = n_points: points [seg[b], seg[b+1]) belong to boundary b. seg may be NULL
+ * when n_boundaries == 1. */
+typedef struct {
+    int32_t n_boundaries;
+    const dbie_boundary* boundaries;
+    int64_t n_points;
+    const double* xyz;
+    const int64_t* seg;
+} dbie_problem;
+
+typedef struct {
+    int32_t precision;           /* DBIE_FP64 or DBIE_FP32C */
+    double nearfield_radius_h;   /* FP32C only: pairs with r < this * h are summed in FP64; in [0, 2] */
+    double dv_over_dsigma_h;     /* dV / dSigma of Eq. 9 in units of h (1/6: cube of side h) */
+    int32_t tune;                /* 1: choose FP32C tile shapes by timing candidates at init */
+    const char* tune_cache;      /* optional path of a text cache of tuned shapes (NULL: none) */
+} dbie_options;
+
+typedef struct {
+    int32_t method;       /* DBIE_NELDER_MEAD or DBIE_LEVENBERG_MARQUARDT */
+    int32_t max_trials;   /* budget of evaluations per point (>= 1) */
+    double eps;           /* convergence: max(f, g) <= eps (Eq. 12) */
+    double init_step;     /* simplex edge (Nelder-Mead); <= 0 means 1 / (longer side of the magnetogram) */
+    double lambda_cap;    /* |lambda| <= cap; <= 0 means pi / h */
+    int32_t fp64_accept;  /* FP32C contexts: re-evaluate the result in FP64 and set status from it */
+} dbie_solve_opts;
+
+/* Fill defaults: FP32C, radius 2, dV/dSigma = 1/6, no tuning / Nelder-Mead, 50 trials, eps 1e-4,
+ * default step and cap, FP64 acceptance on. Return DBIE_OK, or DBIE_E_INVAL for NULL. */
+DBIE_API int dbie_default_options(dbie_options* opt);
+DBIE_API int dbie_default_solve_opts(dbie_solve_opts* opt);
+
+/* Create a context on the current HIP device: copy B0 and xyz into library-owned device memory,
+ * validate the points (z > 0 and finite; checked on the device, then synchronised), classify the
+ * near-field pairs and build the tile schedule. `opt` may be NULL (defaults). On failure *out is
+ * NULL. Synchronises `stream`. */
+DBIE_API int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt, void* stream);
+
+/* Evaluate L lambda trials at every point (Eqs. 6, 13, 14, 8, 9).
+ *   lambda : device double [L][3][N]            (input)
+ *   B      : device double [L][3][N]            (output, required)
+ *   dB     : device double [L][9][N] or NULL    (dB[3p+q] = d B_p / d x_q at frozen lambda)
+ *   fg     : device double [L][2][N] or NULL    (f_i, g_i; NaN for a DEGENERATE point)
+ *   tan    : device double [L][12][N] or NULL   (d/d mu_p, mu = lambda^2, of the rows B_p and
+ *                                                dB_p/dx_q: tan[p] and tan[3 + 3p + q])
+ * L >= 1. A non-finite lambda gives non-finite outputs for that point only. */
+DBIE_API int dbie_eval_field(dbie_ctx* ctx, const double* lambda, int32_t L, double* B, double* dB,
+                             double* fg, double* tan, void* stream);
+
+/* Per-point lambda search (Section 2.1, Eqs. 8-12), all points at once, device resident.
+ *   lambda_inout : device double [3][N]; start values in, |lambda*| out
+ *   B, fg        : device double [3][N] / [2][N] or NULL: field and (f, g) at lambda*
+ *   status       : device int32 [N] (DBIE_ST_*), required
+ *   trials       : device int32 [N] evaluations used per point, required
+ * One trial is one evaluation of (B, grad B) at one lambda triple for one point. Nelder-Mead uses the
+ * simplex {lambda0, lambda0 + step e_p}, coefficients 1, 2, 1/2, 1/2; a proposal outside the cap
+ * costs a trial and counts as Phi = +inf. LM starts at mu = lambda0^2. The host reads one active-point
+ * count per few rounds (synchronising `stream`) and returns when every point is done. */
+DBIE_API int dbie_solve_lambda(dbie_ctx* ctx, double* lambda_inout, const dbie_solve_opts* opt,
+                               double* B, double* fg, int32_t* status, int32_t* trials, void* stream);
+
+/* Adjoint of dbie_eval_field at one lambda triple per point (L = 1), for a loss with gradients
+ * gB = dLoss/dB [3][N] and gdB = dLoss/d(dB) [9][N] (either may be NULL = zero):
+ *   glambda   : device double [3][N] or NULL   dLoss/dlambda at frozen B0
+ *   gB0       : device double, concatenation over boundaries of [3][ny][nx], or NULL
+ *               dLoss/dB0 (the transpose of Eq. 16 and its gradient rows); overwritten
+ *   resid_jac : device double [4][3][N] or NULL  d(u)/d(mu), u = (J x B / (|J||B|), sign(div B) g)
+ * Deterministic: no floating-point atomics. */
+DBIE_API int dbie_grad(dbie_ctx* ctx, const double* lambda, const double* gB, const double* gdB,
+                       double* glambda, double* gB0, double* resid_jac, void* stream);
+
+/* Kernel timing with HIP events on the caller's stream (for benchmarks). enable != 0 starts
+ * recording around every bulk field-sum launch; dbie_timing_read synchronises, returns the summed
+ * milliseconds and the launch count since the last read, and clears them. */
+DBIE_API int dbie_timing(dbie_ctx* ctx, int32_t enable);
+DBIE_API int dbie_timing_read(dbie_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Sizes the context was built with: n_points, total pixels, FP32C tile shape (points per lane,
+ * waves per workgroup, pixels per LDS tile) as chosen by defaults or the tuner. Any pointer may be
+ * NULL. */
+DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixels, int32_t* ppl,
+                        int32_t* waves, int32_t* tile_pixels);
+
+DBIE_API void dbie_destroy(dbie_ctx* ctx);
+
+/* Message of the last failure on ctx (or of the last failed dbie_init when ctx is NULL). */
+DBIE_API const char* dbie_last_error(const dbie_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DBIE_H */

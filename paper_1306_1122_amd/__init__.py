@@ -1,0 +1,14 @@
+"""MI355X (gfx950) library for the hot path of DBIE nonlinear force-free field extrapolation
+(Wang, Yan & Tan, arXiv:1306.1122): the lambda-dependent half-space kernel sum against the boundary
+magnetogram, its frozen-lambda gradient, the residuals f_i and g_i, the per-point lambda search and
+the adjoint. The computation lives in libdbie.so (HIP, C ABI in include/dbie.h); this package is its
+binding.
+"""
+from . import _lib
+from .dbie import (Context, DbieError, dbie_default_options, dbie_default_solve_opts, dbie_destroy,
+                   dbie_eval_field, dbie_grad, dbie_init, dbie_last_error, dbie_query, dbie_solve_lambda,
+                   dbie_timing, dbie_timing_read, split_gB0)
+
+__all__ = ["Context", "DbieError", "dbie_init", "dbie_eval_field", "dbie_solve_lambda", "dbie_grad",
+           "dbie_timing", "dbie_timing_read", "dbie_query", "dbie_destroy", "dbie_last_error",
+           "dbie_default_options", "dbie_default_solve_opts", "split_gB0"]

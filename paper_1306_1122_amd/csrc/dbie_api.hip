@@ -1,0 +1,420 @@
+// Host side of the C ABI declared in include/dbie.h: argument validation, the context (library-owned
+// device copies of the problem, per-point geometry, the tile schedules) and the dispatch of the
+// kernels onto the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dbie.h"
+#include "dbie_internal.h"
+#include "dbie_solver.h"
+
+using namespace dbie;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kTile64 = 256;         // points per workgroup of the FP64 kernels
+constexpr int kPixPad = 512;         // FP32 pixel planes are padded to a multiple of this
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    return hipMalloc((void**)p, n * sizeof(T));
+}
+
+}  // namespace
+
+struct dbie_ctx {
+    int device = 0;
+    dbie_options opt{};
+    int32_t nb = 0;
+    int64_t N = 0;
+    int64_t npix_total = 0;
+    std::vector<BoundaryDev> bnd_h;
+    std::vector<int64_t> seg;
+    BoundaryDev* bnd_d = nullptr;
+    double* B0d = nullptr;      // FP64 planes, concatenated per boundary
+    float* pixf = nullptr;      // FP32 planes (a, b, Bx, By, Bz), padded, FP32C only
+    double* xyz = nullptr;
+    Geo geo{};
+    void* geo_block = nullptr;  // one allocation holding every geometry array
+    Tile* tiles64 = nullptr;
+    int64_t n_tiles64 = 0;
+    Tile* tiles32 = nullptr;
+    int64_t n_tiles32 = 0;
+    F32Shape shape{2, 4, 256};
+    double* acc = nullptr;      // [L][kAcc][N]
+    int64_t acc_L = 0;
+    SolverState solver{};
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<hipEvent_t> ev_pool;
+    std::string err;
+};
+
+namespace {
+
+int fail(dbie_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+int hip_fail(dbie_ctx* c, hipError_t e, const char* where) {
+    return fail(c, DBIE_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define DBIE_HIP(c, call)                                  \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+    } while (0)
+
+std::vector<Tile> build_schedule(const std::vector<int64_t>& seg, int32_t per_tile) {
+    std::vector<Tile> t;
+    for (size_t b = 0; b + 1 < seg.size(); ++b) {
+        for (int64_t s = seg[b]; s < seg[b + 1]; s += per_tile) {
+            Tile x;
+            x.start = s;
+            x.count = (int32_t)std::min<int64_t>(per_tile, seg[b + 1] - s);
+            x.b = (int32_t)b;
+            t.push_back(x);
+        }
+    }
+    while (t.size() % 8 != 0 || t.empty()) t.push_back(Tile{0, 0, 0});
+    return t;
+}
+
+hipEvent_t pool_event(dbie_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void free_ctx(dbie_ctx* c) {
+    if (!c) return;
+    (void)hipFree(c->bnd_d);
+    (void)hipFree(c->B0d);
+    (void)hipFree(c->pixf);
+    (void)hipFree(c->xyz);
+    (void)hipFree(c->geo_block);
+    (void)hipFree(c->tiles64);
+    (void)hipFree(c->tiles32);
+    (void)hipFree(c->acc);
+    solver_free(c->solver);
+    for (auto& p : c->ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int set_tiles32(dbie_ctx* c, F32Shape s) {
+    const int32_t per = s.ppl * s.waves * 64;
+    std::vector<Tile> t = build_schedule(c->seg, per);
+    Tile* d = nullptr;
+    DBIE_HIP(c, dalloc(&d, t.size()));
+    DBIE_HIP(c, hipMemcpy(d, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    (void)hipFree(c->tiles32);
+    c->tiles32 = d;
+    c->n_tiles32 = (int64_t)t.size();
+    c->shape = s;
+    return DBIE_OK;
+}
+
+}  // namespace
+
+namespace dbie {
+
+int ensure_acc(dbie_ctx* c, int64_t L) {
+    if (c->acc && c->acc_L >= L) return DBIE_OK;
+    (void)hipFree(c->acc);
+    c->acc = nullptr;
+    c->acc_L = 0;
+    hipError_t e = dalloc(&c->acc, (size_t)(L * kAcc * std::max<int64_t>(c->N, 1)));
+    if (e != hipSuccess) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the accumulator workspace");
+    c->acc_L = L;
+    return DBIE_OK;
+}
+
+// Bulk sum + finalize for L trials on the given lambda; the building block of every call.
+int eval_internal(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const int32_t* idx,
+                  int64_t n_idx, double* B, double* dB, double* fg, double* tn, hipStream_t s) {
+    int rc = ensure_acc(c, L);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        e0 = pool_event(c);
+        e1 = pool_event(c);
+        if (e0 && e1) DBIE_HIP(c, hipEventRecord(e0, s));
+    }
+    if (fp64)
+        DBIE_HIP(c, launch_field64(c->tiles64, c->n_tiles64, c->bnd_d, c->B0d, c->geo, lam, c->N, L, tan,
+                                   c->acc, s));
+    else
+        DBIE_HIP(c, launch_field32c(c->tiles32, c->n_tiles32, c->bnd_d, c->pixf, c->geo, lam, c->N, L,
+                                    tan, c->shape, c->acc, s));
+    if (c->timing && e0 && e1) {
+        DBIE_HIP(c, hipEventRecord(e1, s));
+        c->ev.emplace_back(e0, e1);
+    }
+    const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
+    DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->geo, lam, idx, idx ? n_idx : c->N, c->N, L, c->acc,
+                                near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
+    return DBIE_OK;
+}
+
+const Geo& ctx_geo(const dbie_ctx* c) { return c->geo; }
+const BoundaryDev* ctx_bnd(const dbie_ctx* c) { return c->bnd_d; }
+const BoundaryDev& ctx_bnd_host(const dbie_ctx* c, int b) { return c->bnd_h[b]; }
+int64_t ctx_n(const dbie_ctx* c) { return c->N; }
+int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
+const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
+const double* ctx_xyz(const dbie_ctx* c) { return c->xyz; }
+int ctx_precision(const dbie_ctx* c) { return c->opt.precision; }
+double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
+SolverState& ctx_solver(dbie_ctx* c) { return c->solver; }
+int ctx_fail(dbie_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+
+}  // namespace dbie
+
+extern "C" {
+
+int dbie_default_options(dbie_options* o) {
+    if (!o) return DBIE_E_INVAL;
+    o->precision = DBIE_FP32C;
+    o->nearfield_radius_h = 2.0;
+    o->dv_over_dsigma_h = 1.0 / 6.0;
+    o->tune = 0;
+    o->tune_cache = nullptr;
+    return DBIE_OK;
+}
+
+int dbie_default_solve_opts(dbie_solve_opts* o) {
+    if (!o) return DBIE_E_INVAL;
+    o->method = DBIE_NELDER_MEAD;
+    o->max_trials = 50;
+    o->eps = 1e-4;
+    o->init_step = 0.0;
+    o->lambda_cap = 0.0;
+    o->fp64_accept = 1;
+    return DBIE_OK;
+}
+
+int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt, void* stream) {
+    if (!out) return fail(nullptr, DBIE_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!prob) return fail(nullptr, DBIE_E_INVAL, "problem is NULL");
+    dbie_options o;
+    dbie_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != DBIE_FP64 && o.precision != DBIE_FP32C)
+        return fail(nullptr, DBIE_E_INVAL, "precision must be DBIE_FP64 or DBIE_FP32C");
+    if (!(o.nearfield_radius_h >= 0.0 && o.nearfield_radius_h <= 2.0))
+        return fail(nullptr, DBIE_E_INVAL, "nearfield_radius_h must lie in [0, 2]");
+    if (!(o.dv_over_dsigma_h > 0.0) || !std::isfinite(o.dv_over_dsigma_h))
+        return fail(nullptr, DBIE_E_INVAL, "dv_over_dsigma_h must be positive and finite");
+    const int32_t nb = prob->n_boundaries;
+    if (nb < 1 || !prob->boundaries) return fail(nullptr, DBIE_E_INVAL, "need at least one boundary");
+    if (prob->n_points < 0) return fail(nullptr, DBIE_E_INVAL, "n_points < 0");
+    if (prob->n_points > ((int64_t)1 << 31) - 1)
+        return fail(nullptr, DBIE_E_INVAL, "n_points exceeds 2^31 - 1");
+    if (prob->n_points > 0 && !prob->xyz) return fail(nullptr, DBIE_E_INVAL, "xyz is NULL");
+    if (nb > 1 && !prob->seg) return fail(nullptr, DBIE_E_INVAL, "seg is required when n_boundaries > 1");
+    std::vector<int64_t> seg(nb + 1);
+    if (prob->seg) {
+        for (int32_t b = 0; b <= nb; ++b) seg[b] = prob->seg[b];
+        if (seg[0] != 0 || seg[nb] != prob->n_points)
+            return fail(nullptr, DBIE_E_INVAL, "seg must start at 0 and end at n_points");
+        for (int32_t b = 0; b < nb; ++b)
+            if (seg[b + 1] < seg[b]) return fail(nullptr, DBIE_E_INVAL, "seg is not non-decreasing");
+    } else {
+        seg[0] = 0;
+        seg[1] = prob->n_points;
+    }
+    for (int32_t b = 0; b < nb; ++b) {
+        const dbie_boundary& bd = prob->boundaries[b];
+        if (bd.nx < 1 || bd.ny < 1) return fail(nullptr, DBIE_E_INVAL, "boundary with nx or ny < 1");
+        if ((int64_t)bd.nx * bd.ny > ((int64_t)1 << 30))
+            return fail(nullptr, DBIE_E_INVAL, "boundary larger than 2^30 pixels");
+        if (!(bd.h > 0.0) || !std::isfinite(bd.h) || !std::isfinite(bd.x0) || !std::isfinite(bd.y0))
+            return fail(nullptr, DBIE_E_INVAL, "boundary h must be positive; x0, y0, h finite");
+        if (!bd.B0) return fail(nullptr, DBIE_E_INVAL, "boundary B0 is NULL");
+    }
+
+    dbie_ctx* c = new dbie_ctx();
+    c->opt = o;
+    c->opt.tune_cache = nullptr;
+    c->nb = nb;
+    c->N = prob->n_points;
+    c->seg = seg;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetDevice(&c->device);
+    int64_t off = 0, offf = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const dbie_boundary& bd = prob->boundaries[b];
+        BoundaryDev d{};
+        d.nx = bd.nx;
+        d.ny = bd.ny;
+        d.npix = bd.nx * bd.ny;
+        d.npix_pad = (d.npix + kPixPad - 1) / kPixPad * kPixPad;
+        d.pix_off = off;
+        d.pixf_off = offf;
+        d.x0 = bd.x0;
+        d.y0 = bd.y0;
+        d.h = bd.h;
+        off += 3 * (int64_t)d.npix;
+        offf += 5 * (int64_t)d.npix_pad;
+        c->bnd_h.push_back(d);
+    }
+    c->npix_total = off / 3;
+    auto bail = [&](int rc) {
+        std::string m = c->err;
+        free_ctx(c);
+        g_init_error = m;
+        return rc;
+    };
+    int rc;
+#define DBIE_INIT_HIP(call)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return bail(hip_fail(c, e_, #call)); \
+    } while (0)
+    DBIE_INIT_HIP(dalloc(&c->bnd_d, nb));
+    DBIE_INIT_HIP(hipMemcpy(c->bnd_d, c->bnd_h.data(), nb * sizeof(BoundaryDev), hipMemcpyHostToDevice));
+    DBIE_INIT_HIP(dalloc(&c->B0d, (size_t)off));
+    for (int32_t b = 0; b < nb; ++b)
+        DBIE_INIT_HIP(hipMemcpyAsync(c->B0d + c->bnd_h[b].pix_off, prob->boundaries[b].B0,
+                                     3 * (size_t)c->bnd_h[b].npix * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+    if (o.precision == DBIE_FP32C) DBIE_INIT_HIP(dalloc(&c->pixf, (size_t)offf));
+    const int64_t N = c->N;
+    const size_t Nn = (size_t)std::max<int64_t>(N, 1);
+    DBIE_INIT_HIP(dalloc(&c->xyz, 3 * Nn));
+    if (N > 0)
+        DBIE_INIT_HIP(hipMemcpyAsync(c->xyz, prob->xyz, 3 * (size_t)N * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+    // geometry: 3 double + 5 float + 4 int arrays of N, each 256-byte aligned
+    const size_t al = 256;
+    auto up = [&](size_t b) { return (b + al - 1) / al * al; };
+    const size_t szd = up(Nn * 8), szf = up(Nn * 4);
+    DBIE_INIT_HIP(hipMalloc(&c->geo_block, 3 * szd + 9 * szf));
+    char* gp = (char*)c->geo_block;
+    c->geo.u = (double*)gp; gp += szd;
+    c->geo.v = (double*)gp; gp += szd;
+    c->geo.w = (double*)gp; gp += szd;
+    c->geo.xi_int = (float*)gp; gp += szf;
+    c->geo.xi_frac = (float*)gp; gp += szf;
+    c->geo.yi_int = (float*)gp; gp += szf;
+    c->geo.yi_frac = (float*)gp; gp += szf;
+    c->geo.wf = (float*)gp; gp += szf;
+    c->geo.win_a = (int32_t*)gp; gp += szf;
+    c->geo.win_b = (int32_t*)gp; gp += szf;
+    c->geo.near_mask = (uint32_t*)gp; gp += szf;
+    c->geo.bidx = (int32_t*)gp; gp += szf;
+    {
+        std::vector<Tile> t = build_schedule(seg, kTile64);
+        DBIE_INIT_HIP(dalloc(&c->tiles64, t.size()));
+        DBIE_INIT_HIP(hipMemcpy(c->tiles64, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
+        c->n_tiles64 = (int64_t)t.size();
+    }
+    if (o.precision == DBIE_FP32C) {
+        rc = set_tiles32(c, F32Shape{2, 4, 256});
+        if (rc) return bail(rc);
+    }
+    int32_t* bad = nullptr;
+    DBIE_INIT_HIP(dalloc(&bad, 1));
+    DBIE_INIT_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+    const double r = (o.precision == DBIE_FP32C) ? o.nearfield_radius_h : 0.0;
+    DBIE_INIT_HIP(launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->B0d, c->xyz, N, c->geo, r * r,
+                              o.precision != DBIE_FP32C, bad, c->pixf, c->bnd_h.data(), nb, s));
+    int32_t bad_h = 0;
+    DBIE_INIT_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DBIE_INIT_HIP(hipStreamSynchronize(s));
+    (void)hipFree(bad);
+    if (bad_h) return bail(fail(c, DBIE_E_INVAL, "a point has z <= 0, a non-finite coordinate, or lies "
+                                                 "more than 4e6 pixels away"));
+    if (o.precision == DBIE_FP32C && o.tune) {
+        rc = tune_shapes(c, opt ? opt->tune_cache : nullptr, s);
+        if (rc) return bail(rc);
+    }
+    *out = c;
+    return DBIE_OK;
+#undef DBIE_INIT_HIP
+}
+
+int dbie_eval_field(dbie_ctx* c, const double* lambda, int32_t L, double* B, double* dB, double* fg,
+                    double* tan, void* stream) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    if (L < 1) return fail(c, DBIE_E_INVAL, "L must be >= 1");
+    if (c->N > 0 && (!lambda || !B)) return fail(c, DBIE_E_INVAL, "lambda and B are required");
+    if ((int64_t)L * c->N > ((int64_t)1 << 31) - 1)
+        return fail(c, DBIE_E_INVAL, "L * n_points exceeds 2^31 - 1");
+    if (c->N == 0) return DBIE_OK;
+    return eval_internal(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, 0, B, dB,
+                         fg, tan, (hipStream_t)stream);
+}
+
+int dbie_timing(dbie_ctx* c, int32_t enable) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    return DBIE_OK;
+}
+
+int dbie_timing_read(dbie_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    double tot = 0.0;
+    for (auto& p : c->ev) {
+        DBIE_HIP(c, hipEventSynchronize(p.second));
+        float ms = 0.0f;
+        DBIE_HIP(c, hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+        c->ev_pool.push_back(p.first);
+        c->ev_pool.push_back(p.second);
+    }
+    if (launches) *launches = (int64_t)c->ev.size();
+    c->ev.clear();
+    if (total_ms) *total_ms = tot;
+    return DBIE_OK;
+}
+
+int dbie_query(const dbie_ctx* c, int64_t* n_points, int64_t* n_pixels, int32_t* ppl, int32_t* waves,
+               int32_t* tile_pixels) {
+    if (!c) return DBIE_E_INVAL;
+    if (n_points) *n_points = c->N;
+    if (n_pixels) *n_pixels = c->npix_total;
+    if (ppl) *ppl = c->shape.ppl;
+    if (waves) *waves = c->shape.waves;
+    if (tile_pixels) *tile_pixels = c->shape.tp;
+    return DBIE_OK;
+}
+
+void dbie_destroy(dbie_ctx* c) { free_ctx(c); }
+
+const char* dbie_last_error(const dbie_ctx* c) {
+    if (!c) return g_init_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"
+
+namespace dbie {
+int set_shape(dbie_ctx* c, F32Shape s) {
+    if (!field32c_shape_supported(s)) return fail(c, DBIE_E_UNSUPPORTED, "tile shape not instantiated");
+    return set_tiles32(c, s);
+}
+F32Shape get_shape(const dbie_ctx* c) { return c->shape; }
+}  // namespace dbie

@@ -1,0 +1,204 @@
+// Internal declarations of the DBIE library (gfx950). Not part of the public ABI.
+//
+// Units inside the kernels: every length is in pixels of the point's own magnetogram (u = (x-x0)/h,
+// v = (y-y0)/h, w = z/h) and lambda is Lambda = lambda h. In these units the Eq. (16) nodal sum of
+// the Eq. (6) kernel is scale free:
+//   B_p      = (w / 2pi) A0_p,            A0 = sum_k N(t) rho^-3 B0_pk
+//   dB_p/dx  = -(w / 2pi h) A1_p,          A1 = sum_k H rho^-5 (a_k - u) B0_pk,   H = t^2 cos t - 3 N(t)
+//   dB_p/dy  = -(w / 2pi h) A2_p,          A2 = sum_k H rho^-5 (b_k - v) B0_pk
+//   dB_p/dz  = (A0_p + w^2 A3_p)/(2pi h),  A3 = sum_k H rho^-5 B0_pk
+// with rho the pixel-unit distance, t = Lambda rho, N(t) = t sin t + cos t (frozen-lambda gradient,
+// Eq. 13 in the delta -> 0 limit). The derivatives with respect to mu = lambda^2 need three more sums
+//   T0 = sum_k cos(t) rho^-1 B0_pk,  T1 = sum_k N rho^-3 (a_k - u) B0_pk,  T2 = ... (b_k - v) ...
+// because dA3/dmu_px = -A0/2:
+//   dB_p/dmu = (w h^2 / 4pi) T0,   d(dB_p/dx)/dmu = (w h / 4pi) T1,   d(dB_p/dy)/dmu = (w h / 4pi) T2,
+//   d(dB_p/dz)/dmu = (h / 4pi)(T0 - w^2 A0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dbie {
+
+constexpr int kAccField = 12;   // rows 4p + j: A0, A1, A2, A3 of component p
+constexpr int kAccTan = 9;      // rows 12 + 3p + j: T0, T1, T2 of component p
+constexpr int kAcc = kAccField + kAccTan;
+constexpr int kNearWin = 2;     // near-field window half-width in pixels (radius <= 2 h)
+constexpr int kNearSide = 2 * kNearWin + 1;
+
+struct BoundaryDev {
+    int32_t nx, ny;
+    int32_t npix;       // nx * ny
+    int32_t npix_pad;   // FP32 planes padded to a multiple of the largest pixel tile
+    int64_t pix_off;    // offset of this boundary in the FP64 planes (3 planes of npix each)
+    int64_t pixf_off;   // offset of this boundary in the FP32 planes (5 planes of npix_pad each)
+    double x0, y0, h;
+};
+
+// A run of consecutive points of one boundary (entries of the schedule).
+struct Tile {
+    int64_t start;
+    int32_t count;
+    int32_t b;
+};
+
+// Per-point geometry, computed once in dbie_init (device SoA arrays of length N).
+struct Geo {
+    double* u;
+    double* v;
+    double* w;
+    float* xi_int;     // floor(u) as float (exact integer)
+    float* xi_frac;    // u - floor(u) rounded once to FP32
+    float* yi_int;
+    float* yi_frac;
+    float* wf;         // (float) w
+    int32_t* win_a;    // round(u): centre of the near-field window
+    int32_t* win_b;
+    uint32_t* near_mask;  // bit (i + 2) + 5 (j + 2): pixel (win_a + i, win_b + j) is near (FP64 test)
+    int32_t* bidx;
+};
+
+// One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
+// dx = a_k - u, dy = b_k - v, w2 = w^2, all in pixels. Shared by the FP64 bulk kernel and the
+// FP64 near-field pass of the FP32C path so that both use identical arithmetic.
+template <bool TAN>
+__device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const double lam[3],
+                                          double b0x, double b0y, double b0z, double* acc) {
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
+    const double ri = rsqrt(r2);
+    const double r = r2 * ri;
+    const double ri2 = ri * ri;
+    const double ri3 = ri2 * ri;
+    const double ri5 = ri3 * ri2;
+    const double b0[3] = {b0x, b0y, b0z};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const double t = lam[p] * r;
+        double s, c;
+        sincos(t, &s, &c);
+        const double n = __builtin_fma(t, s, c);
+        const double hh = __builtin_fma(t, t * c, -3.0 * n);
+        const double nb = n * (ri3 * b0[p]);
+        const double hb = hh * (ri5 * b0[p]);
+        acc[4 * p + 0] += nb;
+        acc[4 * p + 1] = __builtin_fma(hb, dx, acc[4 * p + 1]);
+        acc[4 * p + 2] = __builtin_fma(hb, dy, acc[4 * p + 2]);
+        acc[4 * p + 3] += hb;
+        if (TAN) {
+            acc[12 + 3 * p + 0] = __builtin_fma(c * ri, b0[p], acc[12 + 3 * p + 0]);
+            acc[12 + 3 * p + 1] = __builtin_fma(nb, dx, acc[12 + 3 * p + 1]);
+            acc[12 + 3 * p + 2] = __builtin_fma(nb, dy, acc[12 + 3 * p + 2]);
+        }
+    }
+}
+
+// ---- residuals (Eqs. 8, 9, 14) in FP64 -------------------------------------------------------
+enum : int32_t { kStConverged = 0, kStBudget = 1, kStDegenerate = 2, kStJZero = 3, kStNonfinite = 4 };
+
+struct Resid {
+    double f, g, Phi, rho;
+    double u[4];   // (J x B / (|J||B|), sign(div B) g): |u|^2 = Phi
+    int32_t status;
+};
+
+// J = curl B (Eq. 14), f = |J x B| / (|J||B|) (Eq. 8), g = |div B| c / |B| with c = dV/dSigma
+// (Eq. 9). |J| = 0 gives f = 0 (J_ZERO); |B| = 0 is DEGENERATE; non-finite input is NONFINITE;
+// both of the latter get Phi = rho = +inf and f = g = NaN.
+__device__ __forceinline__ Resid residual_fp64(const double B[3], const double dB[9], double c) {
+    Resid R;
+    const double J0 = dB[7] - dB[5], J1 = dB[2] - dB[6], J2 = dB[3] - dB[1];
+    const double D = dB[0] + dB[4] + dB[8];
+    bool fin = isfinite(B[0]) && isfinite(B[1]) && isfinite(B[2]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fin = fin && isfinite(dB[k]);
+    const double nB = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    const double nJ = sqrt(J0 * J0 + J1 * J1 + J2 * J2);
+    R.status = kStBudget;
+    if (!fin || nB == 0.0) {
+        R.status = fin ? kStDegenerate : kStNonfinite;
+        R.f = R.g = __builtin_nan("");
+        R.Phi = R.rho = __builtin_inf();
+        R.u[0] = R.u[1] = R.u[2] = R.u[3] = 0.0;
+        return R;
+    }
+    if (nJ == 0.0) {
+        R.status = kStJZero;
+        R.u[0] = R.u[1] = R.u[2] = 0.0;
+    } else {
+        const double den = nJ * nB;
+        R.u[0] = (J1 * B[2] - J2 * B[1]) / den;
+        R.u[1] = (J2 * B[0] - J0 * B[2]) / den;
+        R.u[2] = (J0 * B[1] - J1 * B[0]) / den;
+    }
+    R.u[3] = c * D / nB;
+    R.f = sqrt(R.u[0] * R.u[0] + R.u[1] * R.u[1] + R.u[2] * R.u[2]);
+    R.g = fabs(R.u[3]);
+    R.Phi = R.f * R.f + R.g * R.g;
+    R.rho = fmax(R.f, R.g);
+    return R;
+}
+
+// d u / d mu_p (jac[4][3], row-major) by the chain rule: only B_p and the row dB_p/dx_q depend on
+// mu_p, and their mu-derivatives are the tangent rows tan[p] and tan[3 + 3p + q].
+__device__ __forceinline__ void residual_jacobian_fp64(const double B[3], const double dB[9],
+                                                       const double tan[12], double c,
+                                                       double jac[12]) {
+    const double J[3] = {dB[7] - dB[5], dB[2] - dB[6], dB[3] - dB[1]};
+    const double D = dB[0] + dB[4] + dB[8];
+    const double nB = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    const double nJ = sqrt(J[0] * J[0] + J[1] * J[1] + J[2] * J[2]);
+    const double w[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2], J[0] * B[1] - J[1] * B[0]};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        double Bd[3] = {0.0, 0.0, 0.0};
+        Bd[p] = tan[p];
+        double dBd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        dBd[3 * p + 0] = tan[3 + 3 * p + 0];
+        dBd[3 * p + 1] = tan[3 + 3 * p + 1];
+        dBd[3 * p + 2] = tan[3 + 3 * p + 2];
+        const double Jd[3] = {dBd[7] - dBd[5], dBd[2] - dBd[6], dBd[3] - dBd[1]};
+        const double Dd = dBd[0] + dBd[4] + dBd[8];
+        const double wd[3] = {Jd[1] * B[2] - Jd[2] * B[1] + J[1] * Bd[2] - J[2] * Bd[1],
+                              Jd[2] * B[0] - Jd[0] * B[2] + J[2] * Bd[0] - J[0] * Bd[2],
+                              Jd[0] * B[1] - Jd[1] * B[0] + J[0] * Bd[1] - J[1] * Bd[0]};
+        const double db = (B[0] * Bd[0] + B[1] * Bd[1] + B[2] * Bd[2]) / nB;
+        if (nJ == 0.0) {
+            jac[0 * 3 + p] = jac[1 * 3 + p] = jac[2 * 3 + p] = 0.0;
+        } else {
+            const double da = (J[0] * Jd[0] + J[1] * Jd[1] + J[2] * Jd[2]) / nJ;
+            const double den = nJ * nB;
+            const double k = (da / nJ + db / nB) / den;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) jac[q * 3 + p] = wd[q] / den - w[q] * k;
+        }
+        jac[3 * 3 + p] = c * Dd / nB - c * D * db / (nB * nB);
+    }
+}
+
+// ---- launchers (each defined next to its kernels) ---------------------------------------------
+hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
+                       const double* xyz, int64_t N, Geo geo, double near_r2, int check_only_fp64,
+                       int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,
+                       hipStream_t s);
+
+hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
+                          const double* B0d, Geo geo, const double* lam, int64_t N, int32_t L,
+                          bool tan, double* acc, hipStream_t s);
+
+struct F32Shape {
+    int32_t ppl;     // points per lane
+    int32_t waves;   // waves per workgroup
+    int32_t tp;      // pixels per LDS tile
+};
+
+hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
+                           const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
+                           bool tan, F32Shape shape, double* acc, hipStream_t s);
+bool field32c_shape_supported(F32Shape shape);
+
+hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, const double* lam,
+                           const int32_t* idx, int64_t n_idx, int64_t N, int32_t L, const double* acc,
+                           bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
+                           double* tanout, hipStream_t s);
+
+}  // namespace dbie

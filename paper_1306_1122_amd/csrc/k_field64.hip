@@ -1,0 +1,78 @@
+// FP64 bulk kernel sum (every pair in FP64): the Eq. (16) nodal sum of the Eq. (6) kernel and its
+// frozen-lambda gradient rows (Eq. 13 limit), optionally with the mu-tangent rows.
+//
+// Grid: one workgroup per schedule tile (a run of <= tile points of one magnetogram) and one
+// grid row per lambda trial. Each lane owns one point; the magnetogram streams through LDS in
+// tiles of kTP64 pixels that all lanes read at the same address (LDS broadcast). Sums are cascaded:
+// a per-tile partial in FP64, then added to the running FP64 total.
+#include "dbie_internal.h"
+
+namespace dbie {
+
+constexpr int kTP64 = 128;
+
+template <bool TAN>
+__global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
+                                                 const BoundaryDev* __restrict__ bnd,
+                                                 const double* __restrict__ B0d, Geo geo,
+                                                 const double* __restrict__ lam, int64_t N,
+                                                 double* __restrict__ acc) {
+    constexpr int NA = TAN ? kAcc : kAccField;
+    __shared__ double sa[kTP64], sb[kTP64], sx[kTP64], sy[kTP64], sz[kTP64];
+    const Tile t = tiles[blockIdx.x];
+    const int trial = blockIdx.y;
+    const BoundaryDev bd = bnd[t.b];
+    const double* B0 = B0d + bd.pix_off;
+    const int32_t npix = bd.npix;
+    for (int c0 = 0; c0 < t.count; c0 += blockDim.x) {
+        const int j = c0 + (int)threadIdx.x;
+        const bool live = j < t.count;
+        const int64_t i = t.start + (live ? j : 0);
+        const double u = geo.u[i], v = geo.v[i], w = geo.w[i];
+        const double w2 = w * w;
+        double lm[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) lm[p] = lam[((int64_t)trial * 3 + p) * N + i] * bd.h;
+        double tot[NA];
+#pragma unroll
+        for (int r = 0; r < NA; ++r) tot[r] = 0.0;
+        for (int k0 = 0; k0 < npix; k0 += kTP64) {
+            const int kn = min(kTP64, npix - k0);
+            __syncthreads();
+            for (int k = threadIdx.x; k < kn; k += blockDim.x) {
+                const int kk = k0 + k;
+                sa[k] = (double)(kk % bd.nx);
+                sb[k] = (double)(kk / bd.nx);
+                sx[k] = B0[kk];
+                sy[k] = B0[npix + kk];
+                sz[k] = B0[2 * npix + kk];
+            }
+            __syncthreads();
+            double part[NA];
+#pragma unroll
+            for (int r = 0; r < NA; ++r) part[r] = 0.0;
+            for (int k = 0; k < kn; ++k)
+                pair_fp64<TAN>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
+#pragma unroll
+            for (int r = 0; r < NA; ++r) tot[r] += part[r];
+        }
+        if (live) {
+#pragma unroll
+            for (int r = 0; r < NA; ++r) acc[((int64_t)trial * kAcc + r) * N + i] = tot[r];
+        }
+    }
+}
+
+hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
+                          const double* B0d, Geo geo, const double* lam, int64_t N, int32_t L,
+                          bool tan, double* acc, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    const dim3 grid((unsigned)n_tiles, (unsigned)L);
+    if (tan)
+        hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, acc);
+    else
+        hipLaunchKernelGGL(k_field64<false>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, acc);
+    return hipGetLastError();
+}
+
+}  // namespace dbie

@@ -1,0 +1,101 @@
+// Set-up kernels run once by dbie_init: per-point geometry in pixel units, the FP64 near-field
+// classification, point validation, and the FP32 pixel planes of the FP32C path.
+#include "dbie_internal.h"
+
+namespace dbie {
+
+// One thread per point of the schedule. Computes u, v, w (FP64), the split FP32 coordinates
+// (exact integer part + fraction rounded once, so that a_k - u is formed with one rounding in
+// FP32), and the near mask: pixel (a, b) of the 5x5 window around (round(u), round(v)) is "near"
+// when it exists and rho^2 = (a-u)^2 + (b-v)^2 + w^2 < near_r2, tested here in FP64 once. The FP32
+// bulk pass skips exactly these pairs and the FP64 near pass sums exactly these pairs.
+__global__ void k_prep_points(const Tile* __restrict__ tiles, const BoundaryDev* __restrict__ bnd,
+                              const double* __restrict__ xyz, int64_t N, Geo geo, double near_r2,
+                              int32_t* __restrict__ bad_flag) {
+    const Tile t = tiles[blockIdx.x];
+    for (int j = threadIdx.x; j < t.count; j += blockDim.x) {
+        const int64_t i = t.start + j;
+        const BoundaryDev bd = bnd[t.b];
+        const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
+        const double u = (x - bd.x0) / bd.h;
+        const double v = (y - bd.y0) / bd.h;
+        const double w = z / bd.h;
+        const bool ok = (z > 0.0) && isfinite(x) && isfinite(y) && isfinite(z) && fabs(u) < 4.0e6 &&
+                        fabs(v) < 4.0e6 && w < 4.0e6;
+        if (!ok) atomicOr(bad_flag, 1);
+        const double uu = ok ? u : 0.0, vv = ok ? v : 0.0, ww = ok ? w : 1.0;
+        geo.u[i] = uu;
+        geo.v[i] = vv;
+        geo.w[i] = ww;
+        const double fu = floor(uu), fv = floor(vv);
+        geo.xi_int[i] = (float)fu;
+        geo.xi_frac[i] = (float)(uu - fu);
+        geo.yi_int[i] = (float)fv;
+        geo.yi_frac[i] = (float)(vv - fv);
+        geo.wf[i] = (float)ww;
+        const int32_t wa = (int32_t)rint(uu), wb = (int32_t)rint(vv);
+        geo.win_a[i] = wa;
+        geo.win_b[i] = wb;
+        geo.bidx[i] = t.b;
+        uint32_t mask = 0u;
+        if (ww * ww < near_r2) {
+            for (int jj = -kNearWin; jj <= kNearWin; ++jj) {
+                for (int ii = -kNearWin; ii <= kNearWin; ++ii) {
+                    const int32_t a = wa + ii, b = wb + jj;
+                    if (a < 0 || a >= bd.nx || b < 0 || b >= bd.ny) continue;
+                    const double dx = (double)a - uu, dy = (double)b - vv;
+                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, ww * ww));
+                    if (r2 < near_r2) mask |= 1u << ((ii + kNearWin) + kNearSide * (jj + kNearWin));
+                }
+            }
+        }
+        geo.near_mask[i] = mask;
+    }
+}
+
+// FP32 pixel planes of one boundary: a, b (pixel indices as exact floats), Bx, By, Bz, each padded
+// to npix_pad with zero field at a far-away position (zero terms, finite distance).
+__global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, float* __restrict__ pixf) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= bd.npix_pad) return;
+    float* base = pixf + bd.pixf_off;
+    const int64_t P = bd.npix_pad;
+    if (k < bd.npix) {
+        const int32_t a = (int32_t)(k % bd.nx), b = (int32_t)(k / bd.nx);
+        base[k] = (float)a;
+        base[P + k] = (float)b;
+        base[2 * P + k] = (float)B0d[bd.pix_off + k];
+        base[3 * P + k] = (float)B0d[bd.pix_off + bd.npix + k];
+        base[4 * P + k] = (float)B0d[bd.pix_off + 2 * (int64_t)bd.npix + k];
+    } else {
+        base[k] = -65536.0f;
+        base[P + k] = -65536.0f;
+        base[2 * P + k] = 0.0f;
+        base[3 * P + k] = 0.0f;
+        base[4 * P + k] = 0.0f;
+    }
+}
+
+hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
+                       const double* xyz, int64_t N, Geo geo, double near_r2, int fp64_only,
+                       int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,
+                       hipStream_t s) {
+    if (n_tiles > 0) {
+        hipLaunchKernelGGL(k_prep_points, dim3((unsigned)n_tiles), dim3(256), 0, s, tiles, bnd, xyz, N,
+                           geo, near_r2, bad_flag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (!fp64_only) {
+        for (int32_t b = 0; b < nb; ++b) {
+            const int64_t P = bnd_host[b].npix_pad;
+            hipLaunchKernelGGL(k_fill_pixf, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
+                               bnd_host[b], B0d, pixf);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace dbie

@@ -1,0 +1,121 @@
+// Per-point finish of an evaluation, in FP64: add the near-field pairs (FP32C path), scale the
+// pixel-unit sums to B, grad B and the mu-tangents, and compute the residuals f_i (Eq. 8) and
+// g_i (Eq. 9) from J = curl B (Eq. 14).
+#include "dbie_internal.h"
+
+namespace dbie {
+
+constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr double kInv4Pi = 0.07957747154594766788;
+
+// acc rows -> (B[3], dB[9], tan[12]) in physical units (see the scale relations at the top of
+// dbie_internal.h).
+template <bool TAN>
+__device__ __forceinline__ void scale_sums(const double* a, double w, double h, double B[3],
+                                           double dB[9], double tn[12]) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const double A0 = a[4 * p + 0], A1 = a[4 * p + 1], A2 = a[4 * p + 2], A3 = a[4 * p + 3];
+        B[p] = w * kInv2Pi * A0;
+        dB[3 * p + 0] = -w * kInv2Pi / h * A1;
+        dB[3 * p + 1] = -w * kInv2Pi / h * A2;
+        dB[3 * p + 2] = kInv2Pi / h * __builtin_fma(w * w, A3, A0);
+        if (TAN) {
+            const double T0 = a[12 + 3 * p + 0], T1 = a[12 + 3 * p + 1], T2 = a[12 + 3 * p + 2];
+            tn[p] = w * h * h * kInv4Pi * T0;
+            tn[3 + 3 * p + 0] = w * h * kInv4Pi * T1;
+            tn[3 + 3 * p + 1] = w * h * kInv4Pi * T2;
+            tn[3 + 3 * p + 2] = h * kInv4Pi * (T0 - w * w * A0);
+        }
+    }
+}
+
+// FP64 pairs of the near-field window (the bits set in dbie_init's classification).
+template <bool TAN>
+__device__ __forceinline__ void add_near(const BoundaryDev& bd, const double* B0, uint32_t mask,
+                                         int32_t wa, int32_t wb, double u, double v, double w2,
+                                         const double lm[3], double* a) {
+    while (mask) {
+        const int bit = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const int ii = bit % kNearSide - kNearWin, jj = bit / kNearSide - kNearWin;
+        const int32_t pa = wa + ii, pb = wb + jj;
+        const int64_t k = (int64_t)pb * bd.nx + pa;
+        pair_fp64<TAN>((double)pa - u, (double)pb - v, w2, lm, B0[k], B0[bd.npix + k],
+                       B0[2 * (int64_t)bd.npix + k], a);
+    }
+}
+
+template <bool TAN, bool NEAR>
+__global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict__ bnd,
+                                                  const double* __restrict__ B0d, Geo geo,
+                                                  const double* __restrict__ lam,
+                                                  const int32_t* __restrict__ idx, int64_t n_idx,
+                                                  int64_t N, const double* __restrict__ acc, double dvds,
+                                                  double* __restrict__ Bo, double* __restrict__ dBo,
+                                                  double* __restrict__ fgo, double* __restrict__ tno) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_idx) return;
+    const int64_t i = idx ? (int64_t)idx[j] : j;
+    const int64_t trial = blockIdx.y;
+    const BoundaryDev bd = bnd[geo.bidx[i]];
+    constexpr int NA = TAN ? kAcc : kAccField;
+    double a[NA];
+#pragma unroll
+    for (int r = 0; r < NA; ++r) a[r] = acc[(trial * kAcc + r) * N + i];
+    const double w = geo.w[i];
+    if (NEAR) {
+        const uint32_t mask = geo.near_mask[i];
+        if (mask) {
+            double lm[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) lm[p] = lam[(trial * 3 + p) * N + i] * bd.h;
+            double nr[NA];
+#pragma unroll
+            for (int r = 0; r < NA; ++r) nr[r] = 0.0;
+            add_near<TAN>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
+                          w * w, lm, nr);
+#pragma unroll
+            for (int r = 0; r < NA; ++r) a[r] += nr[r];
+        }
+    }
+    double B[3], dB[9], tn[12];
+    scale_sums<TAN>(a, w, bd.h, B, dB, tn);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) Bo[(trial * 3 + p) * N + i] = B[p];
+    if (dBo) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) dBo[(trial * 9 + r) * N + i] = dB[r];
+    }
+    if (TAN && tno) {
+#pragma unroll
+        for (int r = 0; r < 12; ++r) tno[(trial * 12 + r) * N + i] = tn[r];
+    }
+    if (fgo) {
+        const Resid R = residual_fp64(B, dB, dvds * bd.h);
+        fgo[(trial * 2 + 0) * N + i] = R.f;
+        fgo[(trial * 2 + 1) * N + i] = R.g;
+    }
+}
+
+hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, const double* lam,
+                           const int32_t* idx, int64_t n_idx, int64_t N, int32_t L, const double* acc,
+                           bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
+                           double* tanout, hipStream_t s) {
+    if (n_idx == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_idx + 255) / 256), (unsigned)L);
+#define DBIE_FIN(T, NR)                                                                            \
+    hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, geo, lam, idx, n_idx, N, \
+                       acc, dvds, B, dB, fg, tanout)
+    if (tan) {
+        if (add_near) DBIE_FIN(true, true);
+        else DBIE_FIN(true, false);
+    } else {
+        if (add_near) DBIE_FIN(false, true);
+        else DBIE_FIN(false, false);
+    }
+#undef DBIE_FIN
+    return hipGetLastError();
+}
+
+}  // namespace dbie

@@ -1,0 +1,246 @@
+"""Thin Python binding of the C ABI (include/dbie.h), with the same function names.
+
+Argument marshalling only: every step of the computation runs in the HIP library. Tensors must be
+CUDA (ROCm) tensors, contiguous, float64 (int32 for status/trials). Outputs left as None are allocated
+here with torch and returned. Streams default to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+class DbieError(RuntimeError):
+    pass
+
+
+def _lib():
+    return L.load()
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, name: str, shape: Sequence[int], dtype=torch.float64):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Context:
+    """Owns a dbie_ctx handle (destroyed with the object)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n_points: int, shapes: List[tuple], precision: int,
+                 device: torch.device):
+        self.handle = handle
+        self.n_points = n_points
+        self.shapes = shapes
+        self.precision = precision
+        self.device = device
+
+    @property
+    def n_pixels(self) -> int:
+        return sum(nx * ny for nx, ny in self.shapes)
+
+    def close(self):
+        if self.handle:
+            _lib().dbie_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check(rc: int, ctx: Optional[Context], what: str):
+    if rc != L.DBIE_OK:
+        msg = _lib().dbie_last_error(ctx.handle if ctx is not None else None)
+        raise DbieError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+def dbie_default_options() -> L.dbie_options:
+    o = L.dbie_options()
+    _lib().dbie_default_options(ctypes.byref(o))
+    return o
+
+
+def dbie_default_solve_opts() -> L.dbie_solve_opts:
+    o = L.dbie_solve_opts()
+    _lib().dbie_default_solve_opts(ctypes.byref(o))
+    return o
+
+
+def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[int]] = None,
+              precision: str = "fp32c", nearfield_radius_h: float = 2.0,
+              dv_over_dsigma_h: float = 1.0 / 6.0, tune: bool = False,
+              tune_cache: Optional[str] = None, stream=None) -> Context:
+    """boundaries: list of dict(B0=[3, ny, nx] float64 CUDA tensor, x0=, y0=, h=); xyz: [3, N]."""
+    lib = _lib()
+    nb = len(boundaries)
+    arr = (L.dbie_boundary * nb)()
+    shapes = []
+    for b, bd in enumerate(boundaries):
+        B0 = bd["B0"]
+        if B0.dim() != 3 or B0.shape[0] != 3:
+            raise ValueError("B0 must have shape [3, ny, nx]")
+        _need(B0, "B0", tuple(B0.shape))
+        arr[b].nx, arr[b].ny = int(B0.shape[2]), int(B0.shape[1])
+        arr[b].x0, arr[b].y0, arr[b].h = float(bd.get("x0", 0.0)), float(bd.get("y0", 0.0)), float(bd.get("h", 1.0))
+        arr[b].B0 = B0.data_ptr()
+        shapes.append((int(B0.shape[2]), int(B0.shape[1])))
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("xyz must have shape [3, N]")
+    _need(xyz, "xyz", tuple(xyz.shape))
+    N = int(xyz.shape[1])
+    prob = L.dbie_problem()
+    prob.n_boundaries = nb
+    prob.boundaries = arr
+    prob.n_points = N
+    prob.xyz = xyz.data_ptr()
+    segarr = None
+    if seg is not None:
+        segarr = (ctypes.c_int64 * len(seg))(*[int(s) for s in seg])
+        prob.seg = segarr
+    opt = dbie_default_options()
+    opt.precision = {"fp64": L.DBIE_FP64, "fp32c": L.DBIE_FP32C}[precision]
+    opt.nearfield_radius_h = float(nearfield_radius_h)
+    opt.dv_over_dsigma_h = float(dv_over_dsigma_h)
+    opt.tune = int(bool(tune))
+    opt.tune_cache = tune_cache.encode() if tune_cache else None
+    h = ctypes.c_void_p()
+    rc = lib.dbie_init(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), _stream(stream))
+    if rc != L.DBIE_OK:
+        msg = lib.dbie_last_error(None)
+        raise DbieError(f"dbie_init failed ({rc}): {msg.decode() if msg else ''}")
+    return Context(h, N, shapes, opt.precision, xyz.device)
+
+
+def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, tan=None,
+                    want_dB: bool = True, want_fg: bool = True, want_tan: bool = False, stream=None):
+    """lam: [3, N] or [L, 3, N]. Returns dict(B, dB, fg, tan) with a leading L axis only if lam has one."""
+    N = ctx.n_points
+    squeeze = lam.dim() == 2
+    lam3 = lam.unsqueeze(0) if squeeze else lam
+    Lt = int(lam3.shape[0])
+    _need(lam3, "lambda", (Lt, 3, N))
+    dev = lam.device
+    z = lambda *s: torch.empty(*s, dtype=torch.float64, device=dev)  # noqa: E731
+    B = z(Lt, 3, N) if B is None else B
+    dB = (z(Lt, 9, N) if want_dB else None) if dB is None else dB
+    fg = (z(Lt, 2, N) if want_fg else None) if fg is None else fg
+    tan = (z(Lt, 12, N) if want_tan else None) if tan is None else tan
+    for t, nm, rows in ((B, "B", 3), (dB, "dB", 9), (fg, "fg", 2), (tan, "tan", 12)):
+        if t is not None:
+            _need(t, nm, (Lt, rows, N) if t.dim() == 3 else (rows, N))
+    rc = _lib().dbie_eval_field(ctx.handle, _ptr(lam3), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
+                                _stream(stream))
+    _check(rc, ctx, "dbie_eval_field")
+    out = dict(B=B, dB=dB, fg=fg, tan=tan)
+    if squeeze:
+        out = {k: (v[0] if v is not None and v.dim() == 3 else v) for k, v in out.items()}
+    return out
+
+
+def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "nm", max_trials: int = 50,
+                      eps: float = 1e-4, init_step: float = 0.0, lambda_cap: float = 0.0,
+                      fp64_accept: bool = True, B=None, fg=None, status=None, trials=None,
+                      want_B: bool = True, want_fg: bool = True, stream=None):
+    N = ctx.n_points
+    _need(lambda_inout, "lambda_inout", (3, N))
+    dev = lambda_inout.device
+    B = (torch.empty(3, N, dtype=torch.float64, device=dev) if want_B else None) if B is None else B
+    fg = (torch.empty(2, N, dtype=torch.float64, device=dev) if want_fg else None) if fg is None else fg
+    status = torch.empty(N, dtype=torch.int32, device=dev) if status is None else status
+    trials = torch.empty(N, dtype=torch.int32, device=dev) if trials is None else trials
+    _need(status, "status", (N,), torch.int32)
+    _need(trials, "trials", (N,), torch.int32)
+    o = dbie_default_solve_opts()
+    o.method = {"nm": L.DBIE_NELDER_MEAD, "lm": L.DBIE_LEVENBERG_MARQUARDT}[method]
+    o.max_trials = int(max_trials)
+    o.eps = float(eps)
+    o.init_step = float(init_step)
+    o.lambda_cap = float(lambda_cap)
+    o.fp64_accept = int(bool(fp64_accept))
+    rc = _lib().dbie_solve_lambda(ctx.handle, _ptr(lambda_inout), ctypes.byref(o), _ptr(B), _ptr(fg),
+                                  _ptr(status), _ptr(trials), _stream(stream))
+    _check(rc, ctx, "dbie_solve_lambda")
+    return dict(lam=lambda_inout, B=B, fg=fg, status=status, trials=trials)
+
+
+def dbie_grad(ctx: Context, lam: torch.Tensor, gB=None, gdB=None, want_glambda: bool = True,
+              want_gB0: bool = True, want_resid_jac: bool = False, glambda=None, gB0=None,
+              resid_jac=None, stream=None):
+    N = ctx.n_points
+    _need(lam, "lambda", (3, N))
+    dev = lam.device
+    if gB is not None:
+        _need(gB, "gB", (3, N))
+    if gdB is not None:
+        _need(gdB, "gdB", (9, N))
+    glambda = (torch.empty(3, N, dtype=torch.float64, device=dev) if want_glambda else None) \
+        if glambda is None else glambda
+    gB0 = (torch.empty(3 * ctx.n_pixels, dtype=torch.float64, device=dev) if want_gB0 else None) \
+        if gB0 is None else gB0
+    resid_jac = (torch.empty(4, 3, N, dtype=torch.float64, device=dev) if want_resid_jac else None) \
+        if resid_jac is None else resid_jac
+    rc = _lib().dbie_grad(ctx.handle, _ptr(lam), _ptr(gB), _ptr(gdB), _ptr(glambda), _ptr(gB0),
+                          _ptr(resid_jac), _stream(stream))
+    _check(rc, ctx, "dbie_grad")
+    return dict(glambda=glambda, gB0=gB0, resid_jac=resid_jac)
+
+
+def split_gB0(ctx: Context, gB0: torch.Tensor) -> List[torch.Tensor]:
+    """View the concatenated gB0 as one [3, ny, nx] tensor per boundary."""
+    out, off = [], 0
+    for nx, ny in ctx.shapes:
+        out.append(gB0[off: off + 3 * nx * ny].view(3, ny, nx))
+        off += 3 * nx * ny
+    return out
+
+
+def dbie_timing(ctx: Context, enable: bool = True):
+    _check(_lib().dbie_timing(ctx.handle, int(bool(enable))), ctx, "dbie_timing")
+
+
+def dbie_timing_read(ctx: Context):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib().dbie_timing_read(ctx.handle, ctypes.byref(ms), ctypes.byref(n)), ctx, "dbie_timing_read")
+    return ms.value, n.value
+
+
+def dbie_query(ctx: Context) -> Dict[str, int]:
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    p, w, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib().dbie_query(ctx.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(p), ctypes.byref(w),
+                             ctypes.byref(t)), ctx, "dbie_query")
+    return dict(n_points=a.value, n_pixels=b.value, ppl=p.value, waves=w.value, tile_pixels=t.value)
+
+
+def dbie_destroy(ctx: Context):
+    ctx.close()
+
+
+def dbie_last_error(ctx: Optional[Context] = None) -> str:
+    m = _lib().dbie_last_error(ctx.handle if ctx is not None else None)
+    return m.decode() if m else ""

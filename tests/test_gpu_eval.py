@@ -1,0 +1,202 @@
+"""GPU parity of dbie_eval_field (through the C ABI) against the FP64 CPU oracle.
+
+Bars: relative L2 <= 1e-10 for the FP64 path and <= 1e-5 for the FP32C path, separately for B,
+grad B, the mu-tangents and (f, g) where stated.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1306_1122_amd as D
+from workloads import config1, config2, z_stratified_subsample
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32c": 1e-5}
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev())
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def ctx_for(boundaries, xyz, precision, seg=None, **kw):
+    bl = [dict(B0=T(b.B0), x0=b.x0, y0=b.y0, h=b.h) for b in boundaries]
+    return D.dbie_init(bl, T(xyz), seg=seg, precision=precision, **kw)
+
+
+def check_against_oracle(ctx, bd, xyz, lam, tol, tangents=True, fg=True, label=""):
+    out = D.dbie_eval_field(ctx, T(lam), want_tan=tangents)
+    torch.cuda.synchronize()
+    B, dB, tan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, xyz, lam, tangents=True)
+    errs = dict(B=rel(out["B"].cpu(), B), dB=rel(out["dB"].cpu(), dB))
+    if tangents:
+        errs["tan"] = rel(out["tan"].cpu(), tan)
+    if fg:
+        res = oracle.residuals(B, dB, bd.h)
+        fgo = out["fg"].cpu().numpy()
+        errs["f"] = rel(fgo[0], res["f"])
+        errs["g"] = rel(fgo[1], res["g"])
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k in ("B", "dB", "tan"):
+        if k in errs:
+            assert errs[k] <= tol, (label, k, errs[k])
+    return errs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_lowlou_full_workload(precision):
+    w = config1()
+    bd = w.boundaries[0]
+    ctx = ctx_for(w.boundaries, w.xyz, precision)
+    errs = check_against_oracle(ctx, bd, w.xyz, w.lam, TOL[precision], label=f"lowlou {precision}")
+    # f and g are derived in FP64 from B and grad B; they inherit the field error
+    assert errs["f"] <= 10 * TOL[precision] and errs["g"] <= 10 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_bipoles_full_size_sampled(precision):
+    """The 128x128 magnetogram with all 128x128x64 points on the GPU, as the benchmark launches it;
+    the oracle checks a z-stratified sample of the outputs."""
+    w = config2()
+    bd = w.boundaries[0]
+    ctx = ctx_for(w.boundaries, w.xyz, precision)
+    out = D.dbie_eval_field(ctx, T(w.lam), want_tan=True)
+    torch.cuda.synchronize()
+    idx = z_stratified_subsample(w.xyz, 512, seed=5)
+    B, dB, tan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], w.lam[:, idx], tangents=True)
+    e = dict(B=rel(out["B"][:, idx].cpu(), B), dB=rel(out["dB"][:, idx].cpu(), dB),
+             tan=rel(out["tan"][:, idx].cpu(), tan))
+    print("bipoles", precision, e, flush=True)
+    for k, v in e.items():
+        assert v <= TOL[precision], (k, v)
+    assert torch.isfinite(out["B"]).all() and torch.isfinite(out["dB"]).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+@pytest.mark.parametrize("n", [1, 7, 255, 256, 257, 1030])
+def test_ragged_point_counts_and_off_grid_points(precision, n):
+    rng = np.random.default_rng(100 + n)
+    nx, ny, h, x0, y0 = 37, 29, 0.25, -2.0, 3.0
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    # points inside, beside and far outside the magnetogram; z from 0.3 h to 40 h
+    xyz = np.stack([rng.uniform(x0 - 3, x0 + nx * h + 3, n), rng.uniform(y0 - 3, y0 + ny * h + 3, n),
+                    h * np.exp(rng.uniform(np.log(0.3), np.log(40.0), n))])
+    lam = rng.uniform(-2.0, 2.0, size=(3, n))
+
+    class Bd:
+        pass
+
+    bd = Bd()
+    bd.B0, bd.x0, bd.y0, bd.h = B0, x0, y0, h
+    ctx = ctx_for([bd], xyz, precision)
+    check_against_oracle(ctx, bd, xyz, lam, TOL[precision], fg=False, label=f"ragged n={n} {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_points_on_pixel_centres_in_the_lowest_layers(precision):
+    """z = 0.5h .. 2h directly above and between pixel centres: the near-field pairs (r < 2h) are
+    summed in FP64 on the FP32C path."""
+    rng = np.random.default_rng(3)
+    nx, ny = 24, 20
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    gx, gy = np.meshgrid(np.arange(2, 22, 0.5), np.arange(2, 18, 0.5))
+    pts = []
+    for z in (0.5, 1.0, 1.5, 1.999, 2.0):
+        pts.append(np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, z)]))
+    xyz = np.concatenate(pts, axis=1)
+    lam = rng.uniform(-0.5, 0.5, size=xyz.shape)
+
+    class Bd:
+        pass
+
+    bd = Bd()
+    bd.B0, bd.x0, bd.y0, bd.h = B0, 0.0, 0.0, 1.0
+    ctx = ctx_for([bd], xyz, precision)
+    check_against_oracle(ctx, bd, xyz, lam, TOL[precision], fg=False, label=f"near-field {precision}")
+
+
+def test_nearfield_radius_zero_is_plain_fp32():
+    """With the near-field pass switched off every pair is FP32; the error then stays small only
+    away from the boundary."""
+    rng = np.random.default_rng(4)
+    B0 = rng.normal(size=(3, 16, 16)).astype(np.float32).astype(np.float64)
+    xyz = np.stack([rng.uniform(0, 15, 200), rng.uniform(0, 15, 200), rng.uniform(3.0, 10.0, 200)])
+    lam = rng.uniform(-0.3, 0.3, size=(3, 200))
+
+    class Bd:
+        pass
+
+    bd = Bd()
+    bd.B0, bd.x0, bd.y0, bd.h = B0, 0.0, 0.0, 1.0
+    ctx = ctx_for([bd], xyz, "fp32c", nearfield_radius_h=0.0)
+    check_against_oracle(ctx, bd, xyz, lam, 1e-5, fg=False, label="radius 0")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_several_boundaries_of_uneven_size(precision):
+    rng = np.random.default_rng(5)
+    shapes = [(17, 23, 1.0, 0.0, 0.0), (64, 40, 0.5, -3.0, 2.0), (5, 9, 2.0, 1.0, -1.0)]
+    npts = [300, 1, 700]
+
+    class Bd:
+        pass
+
+    bds, xyzs, lams = [], [], []
+    for (nx, ny, h, x0, y0), n in zip(shapes, npts):
+        bd = Bd()
+        bd.B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+        bd.x0, bd.y0, bd.h = x0, y0, h
+        bds.append(bd)
+        xyzs.append(np.stack([rng.uniform(x0, x0 + nx * h, n), rng.uniform(y0, y0 + ny * h, n),
+                              rng.uniform(0.5 * h, 20 * h, n)]))
+        lams.append(rng.uniform(-1, 1, size=(3, n)))
+    xyz = np.concatenate(xyzs, axis=1)
+    lam = np.concatenate(lams, axis=1)
+    seg = np.concatenate([[0], np.cumsum(npts)])
+    ctx = ctx_for(bds, xyz, precision, seg=seg)
+    out = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+    torch.cuda.synchronize()
+    for b, bd in enumerate(bds):
+        s, e = seg[b], seg[b + 1]
+        B, dB, tan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, xyz[:, s:e], lam[:, s:e], tangents=True)
+        for name, ref in (("B", B), ("dB", dB), ("tan", tan)):
+            err = rel(out[name][:, s:e].cpu(), ref)
+            assert err <= TOL[precision], (b, name, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_multi_trial_equals_single_calls_and_is_deterministic(precision):
+    w = config1()
+    ctx = ctx_for(w.boundaries, w.xyz, precision)
+    rng = np.random.default_rng(6)
+    lams = rng.uniform(-2, 2, size=(3, 3, w.n_points))
+    multi = D.dbie_eval_field(ctx, T(lams), want_tan=True)
+    for k in range(3):
+        single = D.dbie_eval_field(ctx, T(lams[k]), want_tan=True)
+        again = D.dbie_eval_field(ctx, T(lams[k]), want_tan=True)
+        for name in ("B", "dB", "tan", "fg"):
+            assert torch.equal(multi[name][k], single[name]), name
+            assert torch.equal(again[name], single[name]), name
+
+
+def test_zero_points_and_invalid_points():
+    B0 = T(np.ones((3, 4, 4)))
+    ctx = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], torch.zeros(3, 0, dtype=torch.float64,
+                                                                         device=dev()))
+    out = D.dbie_eval_field(ctx, torch.zeros(3, 0, dtype=torch.float64, device=dev()))
+    assert out["B"].shape == (3, 0)
+    bad = T(np.array([[0.0, 1.0], [0.0, 1.0], [1.0, 0.0]]))
+    with pytest.raises(D.DbieError, match="z <= 0"):
+        D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], bad)
+    nanp = T(np.array([[np.nan], [0.0], [1.0]]))
+    with pytest.raises(D.DbieError, match="non-finite"):
+        D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], nanp)
