@@ -1,0 +1,219 @@
+"""Benchmark of the DBIE hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 128x128 FP32 bipole magnetogram (6 Gaussian bipoles, sheared horizontal field,
+20 G noise) with all 128x128x64 = 1,048,576 evaluation points; synthetic, seeded.
+One step = one call of dbie_solve_lambda in its gradient form (Levenberg-Marquardt in mu = lambda^2)
+with a budget of TRIALS_PER_STEP trials over every point: per trial the FP32C bulk sum of B, grad B
+and the mu-tangents, the FP64 near-field pairs and residuals, the LM update and the active-set
+compaction. The metric is kernel-pair evaluations per second (pixels x points x trials / time).
+
+Printed: one JSON line with the metric, a roofline object for the dominant kernel (the FP32C bulk
+sum; its launch time is measured with HIP events on the launch stream by the library), and the FP64
+CPU oracle timed on a bounded sample of the same workload on the host cores (cpu_baseline).
+"""
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# algorithmic FP32 flops per kernel pair (FMA = 2, add/mul = 1, sin/cos/rsqrt = 1), see the design doc
+FLOPS_FIELD_GRAD = 69
+FLOPS_FIELD_GRAD_TAN = 90
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+TRIALS_PER_STEP = 3
+
+
+def _oracle_chunk(args):
+    B0, x0, y0, h, xyz, lam = args
+    import oracle
+    B, dB, tan = oracle.field(B0, x0, y0, h, xyz, lam, tangents=True)
+    oracle.residuals(B, dB, h)
+    return xyz.shape[1]
+
+
+def cpu_baseline(w, n_sample, seed=7):
+    """The FP64 oracle (as it stands) on a z-stratified sample of the workload's points, one
+    process per host core; returns pairs/s of field + grad + tangents + residuals."""
+    from workloads import z_stratified_subsample
+    bd = w.boundaries[0]
+    idx = z_stratified_subsample(w.xyz, n_sample, seed)
+    cores = min(os.cpu_count() or 1, 16)
+    chunks = np.array_split(idx, cores * 4)
+    jobs = [(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, c], w.lam[:, c]) for c in chunks if c.size]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_chunk, jobs[:cores])          # warm the workers
+        t0 = time.perf_counter()
+        n = sum(pool.map(_oracle_chunk, jobs))
+        dt = time.perf_counter() - t0
+    pairs = n * bd.nx * bd.ny
+    return dict(value=pairs / dt, unit="pairs/s", cores=cores, kind="oracle",
+                sample=f"{n} z-stratified points of the {w.name} workload x all {bd.nx * bd.ny} pixels "
+                       f"(FP64 field + grad + mu-tangents + residuals), {dt:.2f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy 1 GiB once (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--shape", default="", help="FP32C tile shape ppl,waves,tile_pixels")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(points would be sharded across GPUs with the magnetogram replicated).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1306_1122_amd as D
+    from paper_1306_1122_amd import _lib
+    from workloads import config2
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    _lib.load()   # fails loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    w = config2()
+    bd = w.boundaries[0]
+    N = w.n_points
+    pairs = w.pairs_per_trial()
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    B0 = T(bd.B0)
+    xyz = T(w.xyz)
+    ctx = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision="fp32c")
+    if args.shape:
+        ppl, waves, tp = (int(v) for v in args.shape.split(","))
+        D.dbie_set_tile_shape(ctx, ppl, waves, tp)
+    q = D.dbie_query(ctx)
+    qt = D.dbie_query_tan(ctx)
+    lam = T(w.lam)
+    lam_io = torch.empty_like(lam)
+    status = torch.empty(N, dtype=torch.int32, device=dev)
+    trials = torch.empty(N, dtype=torch.int32, device=dev)
+
+    def step():
+        lam_io.copy_(lam)
+        D.dbie_solve_lambda(ctx, lam_io, method="lm", max_trials=TRIALS_PER_STEP, eps=1e-4,
+                            fp64_accept=False, status=status, trials=trials, want_B=False, want_fg=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.dbie_timing(ctx, True)
+    D.dbie_timing_read(ctx)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(args.steps):
+        step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    D.dbie_timing(ctx, False)
+    kern_ms, launches = D.dbie_timing_read(ctx)
+    step_ms = e0.elapsed_time(e1) / args.steps
+    kern_avg_ms = kern_ms / max(launches, 1)
+    # every point is active in every trial unless it converged earlier: count the evaluations made
+    evals_per_step = int(trials.sum().item())
+    pairs_per_step = evals_per_step * bd.nx * bd.ny
+    value = pairs_per_step / (step_ms * 1e-3)
+    # a launch covers the points still active in its round: use the mean pairs per launch
+    pairs_per_launch = pairs_per_step * args.steps / max(launches, 1)
+    achieved = FLOPS_FIELD_GRAD_TAN * pairs_per_launch / (kern_avg_ms * 1e-3) / 1e12
+
+    extras = {}
+    if not args.no_extras:
+        # the same pass without tangents (one Nelder-Mead trial) and the plain FP64 form
+        out = {}
+        for name, prec, tan in (("fp32c_field_grad", "fp32c", False), ("fp64_field_grad", "fp64", False)):
+            c2 = ctx if prec == "fp32c" else D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz,
+                                                        precision=prec)
+            reps = 5 if prec == "fp32c" else 2
+            D.dbie_eval_field(c2, lam, want_tan=tan)
+            torch.cuda.synchronize()
+            D.dbie_timing(c2, True)
+            D.dbie_timing_read(c2)
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(s)
+            for _ in range(reps):
+                D.dbie_eval_field(c2, lam, want_tan=tan)
+            a1.record(s)
+            torch.cuda.synchronize()
+            km, kl = D.dbie_timing_read(c2)
+            D.dbie_timing(c2, False)
+            ms = a0.elapsed_time(a1) / reps
+            out[name] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_trial=ms,
+                             bulk_kernel_ms=km / max(kl, 1),
+                             algorithmic_tflops=FLOPS_FIELD_GRAD * pairs / (km / max(kl, 1) * 1e-3) / 1e12)
+            if c2 is not ctx:
+                c2.close()
+        extras = out
+
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_sample)
+
+    line = {
+        "metric": "boundary x volume kernel-pair evals/s per lambda trial",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "magnetogram": [bd.nx, bd.ny], "points": N,
+                   "pairs_per_trial": pairs, "trials_per_step": TRIALS_PER_STEP,
+                   "evals_per_step": evals_per_step,
+                   "step": "dbie_solve_lambda, Levenberg-Marquardt, 3-trial budget: per trial FP32C B, "
+                           "grad B, mu-tangents + FP64 near field + FP64 residuals + LM update",
+                   "tile_shape": [q["ppl"], q["waves"], q["tile_pixels"]],
+                   "tile_shape_tangents": [qt["ppl"], qt["waves"], qt["tile_pixels"]]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "k_field32c (FP32C bulk sum with mu-tangents)",
+                     "flops_per_pair": FLOPS_FIELD_GRAD_TAN, "pairs_per_launch": pairs_per_launch,
+                     "avg_launch_ms": kern_avg_ms, "launches": launches},
+        "cpu_baseline": cpu,
+        "wall_s": wall,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

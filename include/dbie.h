@@ -158,11 +158,26 @@ DBIE_API int dbie_grad(dbie_ctx* ctx, const double* lambda, const double* gB, co
 DBIE_API int dbie_timing(dbie_ctx* ctx, int32_t enable);
 DBIE_API int dbie_timing_read(dbie_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Choose the FP32C tile shape (points per lane, waves per workgroup, pixels per LDS tile) for both
+ * the plain pass and the pass with tangents. Only the shapes the library was built with are
+ * accepted (DBIE_E_UNSUPPORTED otherwise; DBIE_E_UNSUPPORTED for an FP64 context). */
+DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int32_t tile_pixels);
+
+/* Solve tracing (time to solution): with enable != 0, dbie_solve_lambda records a HIP event on its
+ * stream at the start and after every round. dbie_solve_trace_read synchronises and returns, for
+ * the last solve, the elapsed milliseconds at the end of each round (t_ms) and the number of points
+ * that converged in each round (converged), for up to max_rounds rounds; *n_rounds = rounds run. */
+DBIE_API int dbie_solve_trace(dbie_ctx* ctx, int32_t enable);
+DBIE_API int dbie_solve_trace_read(dbie_ctx* ctx, double* t_ms, int32_t* converged, int32_t max_rounds,
+                                   int32_t* n_rounds);
+
 /* Sizes the context was built with: n_points, total pixels, FP32C tile shape (points per lane,
  * waves per workgroup, pixels per LDS tile) as chosen by defaults or the tuner. Any pointer may be
  * NULL. */
 DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixels, int32_t* ppl,
                         int32_t* waves, int32_t* tile_pixels);
+/* The tile shape of the FP32C pass with mu-tangents (the LM solver's pass). */
+DBIE_API int dbie_query_tan(const dbie_ctx* ctx, int32_t* ppl, int32_t* waves, int32_t* tile_pixels);
 
 DBIE_API void dbie_destroy(dbie_ctx* ctx);
 

@@ -47,6 +47,11 @@ SIGNATURES = {
     "dbie_timing_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "dbie_query": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
                              POINTER(c_int32), POINTER(c_int32)]),
+    "dbie_query_tan": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "dbie_set_tile_shape": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "dbie_solve_trace": (c_int32, [c_void_p, c_int32]),
+    "dbie_solve_trace_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32,
+                                        POINTER(c_int32)]),
     "dbie_destroy": (None, [c_void_p]),
     "dbie_last_error": (c_char_p, [c_void_p]),
 }

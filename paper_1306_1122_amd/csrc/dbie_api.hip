@@ -46,12 +46,19 @@ struct dbie_ctx {
     void* geo_block = nullptr;  // one allocation holding every geometry array
     Tile* tiles64 = nullptr;
     int64_t n_tiles64 = 0;
-    Tile* tiles32 = nullptr;
+    Tile* tiles32 = nullptr;     // static schedule of the plain FP32C pass
     int64_t n_tiles32 = 0;
+    Tile* tiles32t = nullptr;    // static schedule of the FP32C pass with mu-tangents
+    int64_t n_tiles32t = 0;
     F32Shape shape{2, 4, 256};
+    F32Shape shape_tan{1, 4, 256};
     double* acc = nullptr;      // [L][kAcc][N]
     int64_t acc_L = 0;
     SolverState solver{};
+    void* scratch[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t scratch_bytes[4] = {0, 0, 0, 0};
+    bool trace = false;
+    std::vector<hipEvent_t> trace_ev;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -112,8 +119,11 @@ void free_ctx(dbie_ctx* c) {
     (void)hipFree(c->geo_block);
     (void)hipFree(c->tiles64);
     (void)hipFree(c->tiles32);
+    (void)hipFree(c->tiles32t);
     (void)hipFree(c->acc);
     solver_free(c->solver);
+    for (int k = 0; k < 4; ++k) (void)hipFree(c->scratch[k]);
+    for (auto e : c->trace_ev) (void)hipEventDestroy(e);
     for (auto& p : c->ev) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
@@ -122,16 +132,17 @@ void free_ctx(dbie_ctx* c) {
     delete c;
 }
 
-int set_tiles32(dbie_ctx* c, F32Shape s) {
+int set_tiles32(dbie_ctx* c, F32Shape s, bool tan) {
     const int32_t per = s.ppl * s.waves * 64;
     std::vector<Tile> t = build_schedule(c->seg, per);
     Tile* d = nullptr;
     DBIE_HIP(c, dalloc(&d, t.size()));
     DBIE_HIP(c, hipMemcpy(d, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    (void)hipFree(c->tiles32);
-    c->tiles32 = d;
-    c->n_tiles32 = (int64_t)t.size();
-    c->shape = s;
+    Tile*& dst = tan ? c->tiles32t : c->tiles32;
+    (void)hipFree(dst);
+    dst = d;
+    (tan ? c->n_tiles32t : c->n_tiles32) = (int64_t)t.size();
+    (tan ? c->shape_tan : c->shape) = s;
     return DBIE_OK;
 }
 
@@ -151,8 +162,8 @@ int ensure_acc(dbie_ctx* c, int64_t L) {
 }
 
 // Bulk sum + finalize for L trials on the given lambda; the building block of every call.
-int eval_internal(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const int32_t* idx,
-                  int64_t n_idx, double* B, double* dB, double* fg, double* tn, hipStream_t s) {
+static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const EvalSet* set,
+                     double* B, double* dB, double* fg, double* tn, hipStream_t s) {
     int rc = ensure_acc(c, L);
     if (rc) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -161,29 +172,50 @@ int eval_internal(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan
         e1 = pool_event(c);
         if (e0 && e1) DBIE_HIP(c, hipEventRecord(e0, s));
     }
+    const int32_t* idx = set ? set->idx : nullptr;
     if (fp64)
-        DBIE_HIP(c, launch_field64(c->tiles64, c->n_tiles64, c->bnd_d, c->B0d, c->geo, lam, c->N, L, tan,
-                                   c->acc, s));
+        DBIE_HIP(c, launch_field64(set ? set->tiles64 : c->tiles64, set ? set->n_tiles64 : c->n_tiles64,
+                                   c->bnd_d, c->B0d, c->geo, lam, c->N, L, idx, tan, c->acc, s));
     else
-        DBIE_HIP(c, launch_field32c(c->tiles32, c->n_tiles32, c->bnd_d, c->pixf, c->geo, lam, c->N, L,
-                                    tan, c->shape, c->acc, s));
+        DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
+                                    set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
+                                    c->pixf, c->geo, lam, c->N, L, idx, tan, tan ? c->shape_tan : c->shape,
+                                    c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
         c->ev.emplace_back(e0, e1);
     }
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
-    DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->geo, lam, idx, idx ? n_idx : c->N, c->N, L, c->acc,
-                                near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
+    DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->geo, lam, idx, c->N, set ? set->n_dev : nullptr, c->N,
+                                L, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
     return DBIE_OK;
+}
+
+int eval_set(dbie_ctx* c, const double* lam, bool fp64, bool tan, const EvalSet* set, double* B, double* dB,
+             double* fg, double* tn, hipStream_t s) {
+    if (fp64 == false && !c->pixf) return fail(c, DBIE_E_UNSUPPORTED, "FP32C evaluation in an FP64 context");
+    return eval_core(c, lam, 1, fp64, tan, set, B, dB, fg, tn, s);
 }
 
 const Geo& ctx_geo(const dbie_ctx* c) { return c->geo; }
 const BoundaryDev* ctx_bnd(const dbie_ctx* c) { return c->bnd_d; }
 const BoundaryDev& ctx_bnd_host(const dbie_ctx* c, int b) { return c->bnd_h[b]; }
 int64_t ctx_n(const dbie_ctx* c) { return c->N; }
+const int64_t* ctx_seg(const dbie_ctx* c) { return c->seg.data(); }
+void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes) {
+    if (slot < 0 || slot >= 4) return nullptr;
+    if (c->scratch[slot] && c->scratch_bytes[slot] >= bytes) return c->scratch[slot];
+    (void)hipFree(c->scratch[slot]);
+    c->scratch[slot] = nullptr;
+    c->scratch_bytes[slot] = 0;
+    if (hipMalloc(&c->scratch[slot], std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    c->scratch_bytes[slot] = bytes;
+    return c->scratch[slot];
+}
+bool solver_tracing(const dbie_ctx* c) { return c->trace; }
+std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
-const double* ctx_xyz(const dbie_ctx* c) { return c->xyz; }
 int ctx_precision(const dbie_ctx* c) { return c->opt.precision; }
 double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
 SolverState& ctx_solver(dbie_ctx* c) { return c->solver; }
@@ -332,7 +364,8 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         c->n_tiles64 = (int64_t)t.size();
     }
     if (o.precision == DBIE_FP32C) {
-        rc = set_tiles32(c, F32Shape{2, 4, 256});
+        rc = set_tiles32(c, c->shape, false);
+        if (!rc) rc = set_tiles32(c, c->shape_tan, true);
         if (rc) return bail(rc);
     }
     int32_t* bad = nullptr;
@@ -364,8 +397,8 @@ int dbie_eval_field(dbie_ctx* c, const double* lambda, int32_t L, double* B, dou
     if ((int64_t)L * c->N > ((int64_t)1 << 31) - 1)
         return fail(c, DBIE_E_INVAL, "L * n_points exceeds 2^31 - 1");
     if (c->N == 0) return DBIE_OK;
-    return eval_internal(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, 0, B, dB,
-                         fg, tan, (hipStream_t)stream);
+    return eval_core(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, B, dB, fg, tan,
+                     (hipStream_t)stream);
 }
 
 int dbie_timing(dbie_ctx* c, int32_t enable) {
@@ -393,12 +426,54 @@ int dbie_timing_read(dbie_ctx* c, double* total_ms, int64_t* launches) {
 
 int dbie_query(const dbie_ctx* c, int64_t* n_points, int64_t* n_pixels, int32_t* ppl, int32_t* waves,
                int32_t* tile_pixels) {
+    // (the shape of the plain pass; the pass with tangents is reported by dbie_query_tan)
     if (!c) return DBIE_E_INVAL;
     if (n_points) *n_points = c->N;
     if (n_pixels) *n_pixels = c->npix_total;
     if (ppl) *ppl = c->shape.ppl;
     if (waves) *waves = c->shape.waves;
     if (tile_pixels) *tile_pixels = c->shape.tp;
+    return DBIE_OK;
+}
+
+int dbie_set_tile_shape(dbie_ctx* c, int32_t ppl, int32_t waves, int32_t tile_pixels) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    if (c->opt.precision != DBIE_FP32C) return fail(c, DBIE_E_UNSUPPORTED, "tile shapes apply to FP32C contexts");
+    const F32Shape sh{ppl, waves, tile_pixels};
+    int rc = dbie::set_shape(c, sh, false);
+    if (!rc) rc = dbie::set_shape(c, sh, true);
+    return rc;
+}
+
+int dbie_query_tan(const dbie_ctx* c, int32_t* ppl, int32_t* waves, int32_t* tile_pixels) {
+    if (!c) return DBIE_E_INVAL;
+    if (ppl) *ppl = c->shape_tan.ppl;
+    if (waves) *waves = c->shape_tan.waves;
+    if (tile_pixels) *tile_pixels = c->shape_tan.tp;
+    return DBIE_OK;
+}
+
+int dbie_solve_trace(dbie_ctx* c, int32_t enable) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    c->trace = enable != 0;
+    return DBIE_OK;
+}
+
+int dbie_solve_trace_read(dbie_ctx* c, double* t_ms, int32_t* converged, int32_t max_rounds,
+                          int32_t* n_rounds) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    const int32_t n = (int32_t)c->trace_ev.size() - 1;   // the first event marks the start
+    if (n_rounds) *n_rounds = std::max(n, 0);
+    if (n <= 0) return DBIE_OK;
+    DBIE_HIP(c, hipEventSynchronize(c->trace_ev.back()));
+    const int32_t m = std::min(n, max_rounds);
+    for (int32_t r = 0; r < m; ++r) {
+        float ms = 0.0f;
+        DBIE_HIP(c, hipEventElapsedTime(&ms, c->trace_ev[0], c->trace_ev[r + 1]));
+        if (t_ms) t_ms[r] = ms;
+    }
+    if (converged && c->solver.last_conv)
+        DBIE_HIP(c, hipMemcpy(converged, c->solver.last_conv, m * sizeof(int32_t), hipMemcpyDeviceToHost));
     return DBIE_OK;
 }
 
@@ -412,9 +487,80 @@ const char* dbie_last_error(const dbie_ctx* c) {
 }  // extern "C"
 
 namespace dbie {
-int set_shape(dbie_ctx* c, F32Shape s) {
+int set_shape(dbie_ctx* c, F32Shape s, bool tan) {
     if (!field32c_shape_supported(s)) return fail(c, DBIE_E_UNSUPPORTED, "tile shape not instantiated");
-    return set_tiles32(c, s);
+    return set_tiles32(c, s, tan);
 }
-F32Shape get_shape(const dbie_ctx* c) { return c->shape; }
+F32Shape get_shape(const dbie_ctx* c, bool tan) { return tan ? c->shape_tan : c->shape; }
+
+// Time every instantiated shape on this problem (one full evaluation each, after a warm-up) and keep
+// the fastest, separately for the plain pass and the pass with tangents. The optional cache is a
+// text file of lines "<n_points> <n_pixels> <tan> <ppl> <waves> <tile_pixels>".
+int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s) {
+    if (c->N == 0) return DBIE_OK;
+    for (int tan = 0; tan < 2; ++tan) {
+        bool cached = false;
+        if (cache_path) {
+            FILE* f = fopen(cache_path, "r");
+            if (f) {
+                long long n, p;
+                int t, a, b, d;
+                while (fscanf(f, "%lld %lld %d %d %d %d", &n, &p, &t, &a, &b, &d) == 6) {
+                    if (n == c->N && p == c->npix_total && t == tan && field32c_shape_supported(F32Shape{a, b, d})) {
+                        int rc = set_tiles32(c, F32Shape{a, b, d}, tan != 0);
+                        if (rc) { fclose(f); return rc; }
+                        cached = true;
+                    }
+                }
+                fclose(f);
+            }
+        }
+        if (cached) continue;
+        double* lam = (double*)ctx_scratch(c, 3, (size_t)c->N * 3 * sizeof(double));
+        double* out = (double*)ctx_scratch(c, 2, (size_t)c->N * 24 * sizeof(double));
+        if (!lam || !out) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the tuning workspace");
+        DBIE_HIP(c, hipMemsetAsync(lam, 0, (size_t)c->N * 3 * sizeof(double), s));
+        F32Shape cand[16];
+        const int nc = std::min(field32c_shapes(cand, 16), 16);
+        float best = 1e30f;
+        F32Shape bs = tan ? c->shape_tan : c->shape;
+        hipEvent_t e0, e1;
+        DBIE_HIP(c, hipEventCreate(&e0));
+        DBIE_HIP(c, hipEventCreate(&e1));
+        for (int k = 0; k < nc; ++k) {
+            int rc = set_tiles32(c, cand[k], tan != 0);
+            if (rc) return rc;
+            rc = eval_core(c, lam, 1, false, tan != 0, nullptr, out, out + 3 * c->N, nullptr,
+                           tan ? out + 12 * c->N : nullptr, s);
+            if (rc) return rc;
+            DBIE_HIP(c, hipEventRecord(e0, s));
+            for (int r = 0; r < 2; ++r) {
+                rc = eval_core(c, lam, 1, false, tan != 0, nullptr, out, out + 3 * c->N, nullptr,
+                               tan ? out + 12 * c->N : nullptr, s);
+                if (rc) return rc;
+            }
+            DBIE_HIP(c, hipEventRecord(e1, s));
+            DBIE_HIP(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            DBIE_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bs = cand[k];
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        int rc = set_tiles32(c, bs, tan != 0);
+        if (rc) return rc;
+        if (cache_path) {
+            FILE* f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%lld %lld %d %d %d %d\n", (long long)c->N, (long long)c->npix_total, tan, bs.ppl,
+                        bs.waves, bs.tp);
+                fclose(f);
+            }
+        }
+    }
+    return DBIE_OK;
+}
 }  // namespace dbie

@@ -181,9 +181,11 @@ hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bn
                        int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,
                        hipStream_t s);
 
+// The bulk kernels run over a schedule of tiles. Without `idx` a tile is a run of point indices;
+// with `idx` it is a run of entries of the active-point list idx (device schedules of the solver).
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                           const double* B0d, Geo geo, const double* lam, int64_t N, int32_t L,
-                          bool tan, double* acc, hipStream_t s);
+                          const int32_t* idx, bool tan, double* acc, hipStream_t s);
 
 struct F32Shape {
     int32_t ppl;     // points per lane
@@ -193,11 +195,14 @@ struct F32Shape {
 
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           bool tan, F32Shape shape, double* acc, hipStream_t s);
+                           const int32_t* idx, bool tan, F32Shape shape, double* acc, hipStream_t s);
 bool field32c_shape_supported(F32Shape shape);
+int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number
 
+// Over idx[0 .. n) (n = *n_dev when n_dev is given, else n_idx), or over every point without idx.
 hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, const double* lam,
-                           const int32_t* idx, int64_t n_idx, int64_t N, int32_t L, const double* acc,
+                           const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
+                           const double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s);
 

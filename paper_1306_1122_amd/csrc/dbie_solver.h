@@ -2,37 +2,58 @@
 // accessors they use. Not part of the public ABI.
 #pragma once
 
+#include <vector>
+
 #include "../../include/dbie.h"
 #include "dbie_internal.h"
 
 namespace dbie {
 
-// Device buffers owned by a context for dbie_solve_lambda / dbie_grad (allocated on first use).
+// Device buffers owned by a context for dbie_solve_lambda (allocated on first use, grown on need).
 struct SolverState {
-    void* block = nullptr;   // one allocation for every per-point solver array
-    int64_t n = 0;           // points it was sized for
+    void* block = nullptr;       // one allocation for every per-point solver array
+    int64_t bytes = 0;
     int32_t* count_h = nullptr;  // pinned host word: active-point count
+    int32_t last_rounds = 0;     // rounds of the last solve
+    int32_t* last_conv = nullptr;  // device: points converged in each round of the last solve
 };
 
 void solver_free(SolverState& s);
 
+// Which points an evaluation covers: an active-point list with a device-resident count and the
+// device-built schedules over it (tiles of list entries). NULL set = every point, static schedules.
+struct EvalSet {
+    const int32_t* idx;
+    const int32_t* n_dev;
+    const Tile* tiles32;
+    int64_t n_tiles32;
+    const Tile* tiles64;
+    int64_t n_tiles64;
+};
+
+// One lambda trial (L = 1) through the bulk kernel and the finalize pass.
+int eval_set(dbie_ctx* c, const double* lam, bool fp64, bool tan, const EvalSet* set, double* B, double* dB,
+             double* fg, double* tn, hipStream_t s);
+
 // context accessors (defined in dbie_api.hip)
-int ensure_acc(dbie_ctx* c, int64_t L);
-int eval_internal(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const int32_t* idx,
-                  int64_t n_idx, double* B, double* dB, double* fg, double* tn, hipStream_t s);
 const Geo& ctx_geo(const dbie_ctx* c);
 const BoundaryDev* ctx_bnd(const dbie_ctx* c);
 const BoundaryDev& ctx_bnd_host(const dbie_ctx* c, int b);
 int64_t ctx_n(const dbie_ctx* c);
 int32_t ctx_nb(const dbie_ctx* c);
+const int64_t* ctx_seg(const dbie_ctx* c);
 const double* ctx_B0d(const dbie_ctx* c);
-const double* ctx_xyz(const dbie_ctx* c);
 int ctx_precision(const dbie_ctx* c);
 double ctx_dvds(const dbie_ctx* c);
 SolverState& ctx_solver(dbie_ctx* c);
 int ctx_fail(dbie_ctx* c, int code, const char* msg);
-int set_shape(dbie_ctx* c, F32Shape s);
-F32Shape get_shape(const dbie_ctx* c);
+// Library-owned scratch block `slot` of at least `bytes` (grown on need); NULL on failure.
+void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes);
+bool solver_tracing(const dbie_ctx* c);
+std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c);
+// FP32C tile shapes: one for the plain field pass and one for the pass with mu-tangents.
+int set_shape(dbie_ctx* c, F32Shape s, bool tan);
+F32Shape get_shape(const dbie_ctx* c, bool tan);
 
 // Time the instantiated FP32C shapes on this problem and keep the fastest (optionally cached).
 int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s);

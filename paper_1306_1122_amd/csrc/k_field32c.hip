@@ -85,6 +85,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
                                                          const BoundaryDev* __restrict__ bnd,
                                                          const float* __restrict__ pixf, Geo geo,
                                                          const double* __restrict__ lam, int64_t N,
+                                                         const int32_t* __restrict__ idx, int xcd_remap,
                                                          double* __restrict__ acc) {
     constexpr int NT = 64 * WAVES;
     constexpr int NA = TAN ? kAcc : kAccField;
@@ -92,12 +93,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     __shared__ float4 s4[5][TQ];
     __shared__ int box[4];
 
-    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-    // run of the schedule so that its L2 sees few magnetograms. The host pads the schedule to a
-    // multiple of 8 tiles (empty tiles have count 0), which makes this remap a permutation.
+    // XCD-aware order (static schedules): workgroups are dealt round-robin to the 8 XCDs; give each
+    // XCD a contiguous run of the schedule so that its L2 sees few magnetograms. Schedules are padded
+    // to a multiple of 8 tiles (empty tiles have count 0), which makes this remap a permutation.
+    // Schedules built on the device over an active-point list keep the identity order.
     const int64_t per = (int64_t)gridDim.x / 8;
     const int64_t bx = blockIdx.x;
-    const Tile t = tiles[(bx & 7) * per + (bx >> 3)];
+    const Tile t = tiles[xcd_remap ? (bx & 7) * per + (bx >> 3) : bx];
     if (t.count == 0) return;
     const int64_t trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
@@ -118,7 +120,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     for (int j = 0; j < PPL; ++j) {
         const int q = tid + j * NT;
         live[j] = q < t.count;
-        const int64_t i = t.start + (live[j] ? q : 0);
+        const int64_t e = t.start + (live[j] ? q : 0);
+        const int64_t i = idx ? (int64_t)idx[e] : e;
         pid[j] = i;
         S.xn[j] = -geo.xi_int[i];
         S.xf[j] = geo.xi_frac[i];
@@ -215,6 +218,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     X(2, 8, 256)           \
     X(1, 8, 256)
 
+int field32c_shapes(F32Shape* out, int max) {
+    int n = 0;
+#define DBIE_LIST(P, W, T) \
+    if (n < max) out[n] = F32Shape{P, W, T}; \
+    ++n;
+    DBIE_F32_SHAPES(DBIE_LIST)
+#undef DBIE_LIST
+    return n;
+}
+
 bool field32c_shape_supported(F32Shape s) {
 #define DBIE_CHK(P, W, T) \
     if (s.ppl == P && s.waves == W && s.tp == T) return true;
@@ -225,17 +238,18 @@ bool field32c_shape_supported(F32Shape s) {
 
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           bool tan, F32Shape s, double* acc, hipStream_t st) {
+                           const int32_t* idx, bool tan, F32Shape s, double* acc, hipStream_t st) {
+    const int remap = idx ? 0 : 1;
     if (n_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)n_tiles, (unsigned)L);
 #define DBIE_LAUNCH(P, W, T)                                                                           \
     if (s.ppl == P && s.waves == W && s.tp == T) {                                                     \
         if (tan)                                                                                       \
             hipLaunchKernelGGL((k_field32c<P, W, T, true>), grid, dim3(64 * W), 0, st, tiles, n_tiles, \
-                               bnd, pixf, geo, lam, N, acc);                                           \
+                               bnd, pixf, geo, lam, N, idx, remap, acc);                                           \
         else                                                                                           \
             hipLaunchKernelGGL((k_field32c<P, W, T, false>), grid, dim3(64 * W), 0, st, tiles,         \
-                               n_tiles, bnd, pixf, geo, lam, N, acc);                                  \
+                               n_tiles, bnd, pixf, geo, lam, N, idx, remap, acc);                                  \
         return hipGetLastError();                                                                      \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)

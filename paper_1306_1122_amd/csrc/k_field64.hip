@@ -16,6 +16,7 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
                                                  const BoundaryDev* __restrict__ bnd,
                                                  const double* __restrict__ B0d, Geo geo,
                                                  const double* __restrict__ lam, int64_t N,
+                                                 const int32_t* __restrict__ idx,
                                                  double* __restrict__ acc) {
     constexpr int NA = TAN ? kAcc : kAccField;
     __shared__ double sa[kTP64], sb[kTP64], sx[kTP64], sy[kTP64], sz[kTP64];
@@ -27,7 +28,8 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
     for (int c0 = 0; c0 < t.count; c0 += blockDim.x) {
         const int j = c0 + (int)threadIdx.x;
         const bool live = j < t.count;
-        const int64_t i = t.start + (live ? j : 0);
+        const int64_t e = t.start + (live ? j : 0);
+        const int64_t i = idx ? (int64_t)idx[e] : e;
         const double u = geo.u[i], v = geo.v[i], w = geo.w[i];
         const double w2 = w * w;
         double lm[3];
@@ -65,13 +67,13 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
 
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                           const double* B0d, Geo geo, const double* lam, int64_t N, int32_t L,
-                          bool tan, double* acc, hipStream_t s) {
+                          const int32_t* idx, bool tan, double* acc, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)n_tiles, (unsigned)L);
     if (tan)
-        hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, acc);
+        hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, idx, acc);
     else
-        hipLaunchKernelGGL(k_field64<false>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, acc);
+        hipLaunchKernelGGL(k_field64<false>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, idx, acc);
     return hipGetLastError();
 }
 

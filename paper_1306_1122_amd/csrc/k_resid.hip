@@ -51,11 +51,11 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
                                                   const double* __restrict__ B0d, Geo geo,
                                                   const double* __restrict__ lam,
                                                   const int32_t* __restrict__ idx, int64_t n_idx,
-                                                  int64_t N, const double* __restrict__ acc, double dvds,
+                                                  const int32_t* __restrict__ n_dev, int64_t N, const double* __restrict__ acc, double dvds,
                                                   double* __restrict__ Bo, double* __restrict__ dBo,
                                                   double* __restrict__ fgo, double* __restrict__ tno) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_idx) return;
+    if (j >= (n_dev ? (int64_t)*n_dev : n_idx)) return;
     const int64_t i = idx ? (int64_t)idx[j] : j;
     const int64_t trial = blockIdx.y;
     const BoundaryDev bd = bnd[geo.bidx[i]];
@@ -99,13 +99,14 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
 }
 
 hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, const double* lam,
-                           const int32_t* idx, int64_t n_idx, int64_t N, int32_t L, const double* acc,
+                           const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
+                           const double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s) {
     if (n_idx == 0) return hipSuccess;
     const dim3 grid((unsigned)((n_idx + 255) / 256), (unsigned)L);
 #define DBIE_FIN(T, NR)                                                                            \
-    hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, geo, lam, idx, n_idx, N, \
+    hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, geo, lam, idx, n_idx, n_dev, N, \
                        acc, dvds, B, dB, fg, tanout)
     if (tan) {
         if (add_near) DBIE_FIN(true, true);

@@ -1,0 +1,814 @@
+// Device-resident per-point lambda search (Section 2.1, Eqs. 8-12) behind dbie_solve_lambda.
+//
+// A solve runs in rounds. In every round each active point evaluates one lambda triple (one trial):
+//   bulk sum over the active-point list -> finalize (B, grad B [, tangents]) -> update kernel
+//   (residuals, convergence test max(f, g) <= eps, and the next proposal) -> stable compaction of the
+//   active list and a device-built tile schedule for the next round.
+// Nothing crosses to the host inside a round; the host reads one pinned active count every few
+// rounds to stop early. The number of rounds never exceeds the trial budget, because every round
+// consumes at least one trial of every active point.
+//
+// Two update rules:
+//  * downhill simplex (Nelder-Mead) on Phi = f^2 + g^2 over (lambda_x, lambda_y, lambda_z), the
+//    derivative-free form the paper uses (Lagarias et al. formulation: reflection 1, expansion 2,
+//    contraction 1/2, shrink 1/2; vertices in fixed slots ordered by (Phi, slot)). Its vertex
+//    arithmetic is written in the same operation order as the CPU oracle with FP contraction off.
+//  * Levenberg-Marquardt in mu = lambda^2 >= 0 (the gradient form): the 4x3 Jacobian of the residual
+//    vector u = (J x B / (|J||B|), sign(div B) g) from the mu-tangents, Marquardt scaling, nu /= 10 on
+//    acceptance (Phi falls) and nu *= 10 on rejection, projection into [0, cap^2].
+#include <cmath>
+#include <vector>
+
+#include "dbie_solver.h"
+
+namespace dbie {
+
+constexpr int kCompactThreads = 256;
+constexpr int kCompactItems = 4;
+constexpr int kCompactBlock = kCompactThreads * kCompactItems;
+constexpr int32_t kNoEval = -1;
+
+// ------------------------------------------------------------------------------------------------
+// stable compaction of the active flags into a sorted index list + device tile schedules
+// ------------------------------------------------------------------------------------------------
+__global__ void k_compact_count(const int32_t* __restrict__ active, int64_t N, int32_t* __restrict__ bsum) {
+    __shared__ int32_t wsum[kCompactThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kCompactBlock;
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+        const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
+        c += (i < N && active[i]) ? 1 : 0;
+    }
+    // wave reduction (DPP / swizzle under the hood)
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kCompactThreads / 64; ++w) t += wsum[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the block counts in one workgroup; also clears the per-boundary counters.
+__global__ void k_compact_scan(int32_t* __restrict__ bsum, int32_t nblk, int32_t* __restrict__ total,
+                               int32_t* __restrict__ cnt_b, int32_t nb) {
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nblk + 1023) / 1024;
+    const int s0 = tid * per, s1 = min(nblk, s0 + per);
+    int32_t loc = 0;
+    for (int k = s0; k < s1; ++k) loc += bsum[k];
+    part[tid] = loc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - loc;
+    for (int k = s0; k < s1; ++k) {
+        const int32_t v = bsum[k];
+        bsum[k] = run;
+        run += v;
+    }
+    if (tid == 1023) *total = part[1023];
+    for (int b = tid; b < nb; b += 1024) cnt_b[b] = 0;
+}
+
+__global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
+                                  const int32_t* __restrict__ boff, const int32_t* __restrict__ bidx,
+                                  int32_t* __restrict__ list, int32_t* __restrict__ cnt_b) {
+    __shared__ int32_t wcnt[kCompactItems][kCompactThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kCompactBlock;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    bool fl[kCompactItems];
+    int32_t rk[kCompactItems];
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+        const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
+        fl[k] = i < N && active[i];
+        const uint64_t m = __ballot(fl[k]);
+        rk[k] = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        if (lane == 0) wcnt[k][wv] = __popcll(m);
+    }
+    __syncthreads();
+    int32_t run = boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+        int32_t before = run;
+        for (int w = 0; w < wv; ++w) before += wcnt[k][w];
+        if (fl[k]) {
+            const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
+            list[before + rk[k]] = (int32_t)i;
+            atomicAdd(&cnt_b[bidx[i]], 1);
+        }
+        for (int w = 0; w < kCompactThreads / 64; ++w) run += wcnt[k][w];
+    }
+}
+
+// Tiles of `per` consecutive list entries of one boundary; the remaining slots up to max_tiles get
+// count 0. The list is sorted by point index and points are grouped by boundary, so boundary b's
+// entries start at the sum of the counts of the boundaries before it.
+__global__ void k_build_tiles(const int32_t* __restrict__ cnt_b, int32_t nb, int32_t per,
+                              Tile* __restrict__ tiles, int64_t max_tiles, int32_t* __restrict__ scratch) {
+    // scratch: [nb] tile offsets, [nb] list offsets, [1] total tiles
+    if (threadIdx.x == 0) {
+        int32_t to = 0, lo = 0;
+        for (int b = 0; b < nb; ++b) {
+            scratch[b] = to;
+            scratch[nb + b] = lo;
+            to += (cnt_b[b] + per - 1) / per;
+            lo += cnt_b[b];
+        }
+        scratch[2 * nb] = to;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int32_t c = cnt_b[b];
+        const int32_t nt = (c + per - 1) / per;
+        for (int k = 0; k < nt; ++k) {
+            Tile t;
+            t.start = scratch[nb + b] + (int64_t)k * per;
+            t.count = min(per, c - k * per);
+            t.b = b;
+            tiles[scratch[b] + k] = t;
+        }
+    }
+    const int32_t used = scratch[2 * nb];
+    for (int64_t k = used + threadIdx.x; k < max_tiles; k += blockDim.x) tiles[k] = Tile{0, 0, 0};
+}
+
+// ------------------------------------------------------------------------------------------------
+// per-point state
+// ------------------------------------------------------------------------------------------------
+struct Common {
+    double* lam_cur;   // [3][N] the trial to evaluate next
+    double* best;      // [3][N] best (or converged) lambda
+    double* best_phi;  // [N]
+    int32_t* best_st;  // [N] residual status at best (kNoEval: not evaluated)
+    int32_t* trials;   // [N]
+    int32_t* status;   // [N]
+    int32_t* active;   // [N]
+    double* Bw;        // [3][N] evaluation outputs of the round
+    double* dBw;       // [9][N]
+    double* tanw;      // [12][N]
+    double* fgw;       // [2][N]
+    int32_t* conv;     // [max_rounds] points converging in each round
+};
+
+struct NMDev {
+    double* V;        // [4][3][N] vertices
+    double* F;        // [4][N]
+    double* xr;       // [3][N] reflected point of the current iteration
+    double* fr;       // [N]
+    int32_t* phase;   // [N]
+    int32_t* aux;     // [N] order (4 x 2 bits) | k << 8
+};
+
+struct LMDev {
+    double* mu;       // [3][N] accepted mu
+    double* mu_try;   // [3][N] mu being evaluated
+    double* Phi;      // [N]
+    double* rho;      // [N]
+    double* u;        // [4][N]
+    double* jac;      // [12][N]
+    double* nu;       // [N]
+    int32_t* phase;   // [N]
+};
+
+struct SolveCfg {
+    int32_t method, max_trials;
+    double eps, step, cap, dvds, nu0;
+};
+
+__device__ __forceinline__ double cap_of(const SolveCfg& c, const BoundaryDev& bd) {
+    return c.cap > 0.0 ? c.cap : 3.14159265358979323846 / bd.h;
+}
+__device__ __forceinline__ double step_of(const SolveCfg& c, const BoundaryDev& bd) {
+    return c.step > 0.0 ? c.step : 1.0 / ((double)max(bd.nx, bd.ny) * bd.h);
+}
+
+enum : int32_t { kPInit0 = 0, kPReflect = 4, kPExpand = 5, kPContractOut = 6, kPContractIn = 7, kPShrink = 8 };
+
+struct NMLocal {
+    double V[4][3];
+    double F[4];
+    double xr[3];
+    double fr;
+    int32_t phase;
+    int32_t ord[4];
+    int32_t k;
+    double P[3];   // the proposal
+};
+
+__device__ __forceinline__ void nm_new_iteration(NMLocal& s) {
+#pragma clang fp contract(off)
+    int o[4] = {0, 1, 2, 3};
+    for (int a = 1; a < 4; ++a) {
+        const int x = o[a];
+        int b = a - 1;
+        while (b >= 0 && (s.F[x] < s.F[o[b]] || (s.F[x] == s.F[o[b]] && x < o[b]))) {
+            o[b + 1] = o[b];
+            --b;
+        }
+        o[b + 1] = x;
+    }
+    for (int a = 0; a < 4; ++a) s.ord[a] = o[a];
+    for (int p = 0; p < 3; ++p) {
+        const double xb = ((s.V[o[0]][p] + s.V[o[1]][p]) + s.V[o[2]][p]) / 3.0;
+        s.xr[p] = (1.0 + 1.0) * xb - 1.0 * s.V[o[3]][p];
+        s.P[p] = s.xr[p];
+    }
+    s.phase = kPReflect;
+}
+
+__device__ __forceinline__ void nm_start_shrink(NMLocal& s) {
+#pragma clang fp contract(off)
+    const int lo = s.ord[0];
+    for (int a = 1; a < 4; ++a)
+        for (int p = 0; p < 3; ++p) s.V[s.ord[a]][p] = s.V[lo][p] + 0.5 * (s.V[s.ord[a]][p] - s.V[lo][p]);
+    s.phase = kPShrink;
+    s.k = 1;
+    for (int p = 0; p < 3; ++p) s.P[p] = s.V[s.ord[1]][p];
+}
+
+// Consume the value of the trial just made (T = the previous proposal) and set the next proposal.
+__device__ __forceinline__ void nm_advance(NMLocal& s, const double T[3], double phi) {
+#pragma clang fp contract(off)
+    const int lo = s.ord[0], sh = s.ord[2], hi = s.ord[3];
+    if (s.phase < kPReflect) {
+        const int k = s.phase;
+        s.F[k] = phi;
+        if (k < 3) {
+            s.phase = k + 1;
+            for (int p = 0; p < 3; ++p) s.P[p] = s.V[k + 1][p];
+        } else {
+            nm_new_iteration(s);
+        }
+        return;
+    }
+    if (s.phase == kPReflect) {
+        s.fr = phi;
+        double xb[3];
+        for (int p = 0; p < 3; ++p) xb[p] = ((s.V[lo][p] + s.V[s.ord[1]][p]) + s.V[sh][p]) / 3.0;
+        if (phi < s.F[lo]) {
+            for (int p = 0; p < 3; ++p) s.P[p] = (1.0 + 1.0 * 2.0) * xb[p] - 1.0 * 2.0 * s.V[hi][p];
+            s.phase = kPExpand;
+        } else if (phi < s.F[sh]) {
+            for (int p = 0; p < 3; ++p) s.V[hi][p] = s.xr[p];
+            s.F[hi] = phi;
+            nm_new_iteration(s);
+        } else if (phi < s.F[hi]) {
+            for (int p = 0; p < 3; ++p) s.P[p] = (1.0 + 0.5 * 1.0) * xb[p] - 0.5 * 1.0 * s.V[hi][p];
+            s.phase = kPContractOut;
+        } else {
+            for (int p = 0; p < 3; ++p) s.P[p] = (1.0 - 0.5) * xb[p] + 0.5 * s.V[hi][p];
+            s.phase = kPContractIn;
+        }
+        return;
+    }
+    if (s.phase == kPExpand) {
+        if (phi < s.fr) {
+            for (int p = 0; p < 3; ++p) s.V[hi][p] = T[p];
+            s.F[hi] = phi;
+        } else {
+            for (int p = 0; p < 3; ++p) s.V[hi][p] = s.xr[p];
+            s.F[hi] = s.fr;
+        }
+        nm_new_iteration(s);
+        return;
+    }
+    if (s.phase == kPContractOut || s.phase == kPContractIn) {
+        const bool acc = (s.phase == kPContractOut) ? (phi <= s.fr) : (phi < s.F[hi]);
+        if (acc) {
+            for (int p = 0; p < 3; ++p) s.V[hi][p] = T[p];
+            s.F[hi] = phi;
+            nm_new_iteration(s);
+        } else {
+            nm_start_shrink(s);
+        }
+        return;
+    }
+    // shrink: the k-th non-best vertex (in the iteration's order) was just evaluated
+    s.F[s.ord[s.k]] = phi;
+    if (s.k < 3) {
+        s.k += 1;
+        for (int p = 0; p < 3; ++p) s.P[p] = s.V[s.ord[s.k]][p];
+    } else {
+        nm_new_iteration(s);
+    }
+}
+
+__device__ __forceinline__ void nm_load(NMLocal& s, const NMDev& d, int64_t i, int64_t N) {
+    for (int v = 0; v < 4; ++v) {
+        for (int p = 0; p < 3; ++p) s.V[v][p] = d.V[(v * 3 + p) * N + i];
+        s.F[v] = d.F[v * N + i];
+    }
+    for (int p = 0; p < 3; ++p) s.xr[p] = d.xr[p * N + i];
+    s.fr = d.fr[i];
+    s.phase = d.phase[i];
+    const int32_t a = d.aux[i];
+    for (int v = 0; v < 4; ++v) s.ord[v] = (a >> (2 * v)) & 3;
+    s.k = (a >> 8) & 3;
+}
+
+__device__ __forceinline__ void nm_store(const NMLocal& s, const NMDev& d, int64_t i, int64_t N) {
+    for (int v = 0; v < 4; ++v) {
+        for (int p = 0; p < 3; ++p) d.V[(v * 3 + p) * N + i] = s.V[v][p];
+        d.F[v * N + i] = s.F[v];
+    }
+    for (int p = 0; p < 3; ++p) d.xr[p * N + i] = s.xr[p];
+    d.fr[i] = s.fr;
+    d.phase[i] = s.phase;
+    int32_t a = 0;
+    for (int v = 0; v < 4; ++v) a |= s.ord[v] << (2 * v);
+    d.aux[i] = a | (s.k << 8);
+}
+
+__device__ __forceinline__ bool feasible(const double P[3], double cap) {
+    return fabs(P[0]) <= cap && fabs(P[1]) <= cap && fabs(P[2]) <= cap;
+}
+
+__device__ __forceinline__ void record_best(const Common& C, int64_t i, int64_t N, const double T[3],
+                                            double phi, int32_t st) {
+    if (C.best_st[i] == kNoEval || phi < C.best_phi[i]) {
+        for (int p = 0; p < 3; ++p) C.best[p * N + i] = T[p];
+        C.best_phi[i] = phi;
+        C.best_st[i] = st;
+    }
+}
+
+__device__ __forceinline__ void finish_budget(const Common& C, int64_t i) {
+    C.active[i] = 0;
+    const int32_t bs = C.best_st[i];
+    if (isfinite(C.best_phi[i])) C.status[i] = kStBudget;
+    else C.status[i] = (bs == kStDegenerate || bs == kStNonfinite) ? bs : kStNonfinite;
+}
+
+// Advance the simplex until a feasible proposal exists or the budget is spent; infeasible proposals
+// (|lambda_p| > cap) cost a trial with Phi = +inf, like the oracle.
+__device__ void nm_propose(NMLocal& s, const Common& C, int64_t i, int64_t N, int32_t max_trials,
+                           double cap) {
+    while (!feasible(s.P, cap)) {
+        const int32_t tr = ++C.trials[i];
+        if (C.best_st[i] == kNoEval) {
+            for (int p = 0; p < 3; ++p) C.best[p * N + i] = s.P[p];
+            C.best_phi[i] = __builtin_inf();
+            C.best_st[i] = kStNonfinite;
+        }
+        if (tr >= max_trials) {
+            finish_budget(C, i);
+            return;
+        }
+        double T[3] = {s.P[0], s.P[1], s.P[2]};
+        nm_advance(s, T, __builtin_inf());
+    }
+    for (int p = 0; p < 3; ++p) C.lam_cur[p * N + i] = s.P[p];
+}
+
+__global__ void k_solve_init(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
+                             const int32_t* __restrict__ bidx, int64_t N, const double* __restrict__ lam0,
+                             Common C, NMDev nm, LMDev lm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const BoundaryDev bd = bnd[bidx[i]];
+    double l0[3];
+    bool fin = true;
+    for (int p = 0; p < 3; ++p) {
+        l0[p] = lam0[p * N + i];
+        fin = fin && isfinite(l0[p]);
+        C.best[p * N + i] = l0[p];
+    }
+    C.trials[i] = 0;
+    C.best_phi[i] = __builtin_inf();
+    C.best_st[i] = kNoEval;
+    C.status[i] = kStBudget;
+    C.active[i] = fin ? 1 : 0;
+    if (!fin) {
+        C.status[i] = kStNonfinite;
+        return;
+    }
+    if (cfg.method == DBIE_NELDER_MEAD) {
+        NMLocal s;
+        const double d = step_of(cfg, bd);
+        for (int v = 0; v < 4; ++v)
+            for (int p = 0; p < 3; ++p) s.V[v][p] = l0[p] + ((v >= 1 && v - 1 == p) ? d : 0.0);
+        for (int v = 0; v < 4; ++v) s.F[v] = __builtin_inf();
+        for (int p = 0; p < 3; ++p) s.xr[p] = 0.0;
+        s.fr = 0.0;
+        s.phase = kPInit0;
+        for (int v = 0; v < 4; ++v) s.ord[v] = v;
+        s.k = 0;
+        for (int p = 0; p < 3; ++p) s.P[p] = s.V[0][p];
+        nm_propose(s, C, i, N, cfg.max_trials, cap_of(cfg, bd));
+        nm_store(s, nm, i, N);
+    } else {
+        for (int p = 0; p < 3; ++p) {
+            const double m = l0[p] * l0[p];
+            lm.mu_try[p * N + i] = m;
+            lm.mu[p * N + i] = m;
+            C.lam_cur[p * N + i] = sqrt(m);
+        }
+        lm.phase[i] = 0;
+        lm.nu[i] = cfg.nu0;
+    }
+}
+
+__global__ void k_nm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
+                            const int32_t* __restrict__ bidx, int64_t N, const int32_t* __restrict__ list,
+                            const int32_t* __restrict__ n_active, int32_t round, Common C, NMDev nm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= *n_active) return;
+    const int64_t i = list[j];
+    const BoundaryDev bd = bnd[bidx[i]];
+    double B[3], dB[9], T[3];
+    for (int p = 0; p < 3; ++p) {
+        B[p] = C.Bw[p * N + i];
+        T[p] = C.lam_cur[p * N + i];
+    }
+    for (int r = 0; r < 9; ++r) dB[r] = C.dBw[r * N + i];
+    const Resid R = residual_fp64(B, dB, cfg.dvds * bd.h);
+    const int32_t tr = ++C.trials[i];
+    if (R.rho <= cfg.eps) {
+        for (int p = 0; p < 3; ++p) C.best[p * N + i] = T[p];
+        C.best_phi[i] = R.Phi;
+        C.best_st[i] = R.status;
+        C.status[i] = kStConverged;
+        C.active[i] = 0;
+        atomicAdd(&C.conv[round], 1);
+        return;
+    }
+    record_best(C, i, N, T, R.Phi, R.status);
+    if (tr >= cfg.max_trials) {
+        finish_budget(C, i);
+        return;
+    }
+    NMLocal s;
+    nm_load(s, nm, i, N);
+    nm_advance(s, T, R.Phi);
+    nm_propose(s, C, i, N, cfg.max_trials, cap_of(cfg, bd));
+    nm_store(s, nm, i, N);
+}
+
+// Solve (A + nu diag(A)) d = -J^T u with diag(A) floored at 1e-12 max diag(A); LU with partial
+// pivoting. d = 0 when A has no positive diagonal.
+__device__ __forceinline__ void lm_direction(const double jac[12], const double u[4], double nu, double d[3]) {
+    double A[3][3], g[3];
+    for (int a = 0; a < 3; ++a) {
+        g[a] = 0.0;
+        for (int q = 0; q < 4; ++q) g[a] += jac[q * 3 + a] * u[q];
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int q = 0; q < 4; ++q) s += jac[q * 3 + a] * jac[q * 3 + b];
+            A[a][b] = s;
+        }
+    }
+    const double m = fmax(A[0][0], fmax(A[1][1], A[2][2]));
+    d[0] = d[1] = d[2] = 0.0;
+    if (!(m > 0.0) || !isfinite(m)) return;
+    double M[3][4];
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) M[a][b] = A[a][b];
+        M[a][a] += nu * fmax(A[a][a], 1e-12 * m);
+        M[a][3] = -g[a];
+    }
+    for (int c = 0; c < 3; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(M[r][c]) > fabs(M[pr][c])) pr = r;
+        if (pr != c)
+            for (int k = 0; k < 4; ++k) {
+                const double t = M[c][k];
+                M[c][k] = M[pr][k];
+                M[pr][k] = t;
+            }
+        if (M[c][c] == 0.0) return;
+        for (int r = c + 1; r < 3; ++r) {
+            const double f = M[r][c] / M[c][c];
+            for (int k = c; k < 4; ++k) M[r][k] -= f * M[c][k];
+        }
+    }
+    double x[3];
+    for (int r = 2; r >= 0; --r) {
+        double s = M[r][3];
+        for (int k = r + 1; k < 3; ++k) s -= M[r][k] * x[k];
+        x[r] = s / M[r][r];
+    }
+    if (isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2])) {
+        d[0] = x[0];
+        d[1] = x[1];
+        d[2] = x[2];
+    }
+}
+
+__global__ void k_lm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
+                            const int32_t* __restrict__ bidx, int64_t N, const int32_t* __restrict__ list,
+                            const int32_t* __restrict__ n_active, int32_t round, Common C, LMDev lm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= *n_active) return;
+    const int64_t i = list[j];
+    const BoundaryDev bd = bnd[bidx[i]];
+    const double c = cfg.dvds * bd.h;
+    double B[3], dB[9], tn[12], mt[3];
+    for (int p = 0; p < 3; ++p) {
+        B[p] = C.Bw[p * N + i];
+        mt[p] = lm.mu_try[p * N + i];
+    }
+    for (int r = 0; r < 9; ++r) dB[r] = C.dBw[r * N + i];
+    for (int r = 0; r < 12; ++r) tn[r] = C.tanw[r * N + i];
+    const Resid R = residual_fp64(B, dB, c);
+    const int32_t tr = ++C.trials[i];
+    const int32_t phase = lm.phase[i];
+    if (phase == 0 && !isfinite(R.Phi)) {
+        for (int p = 0; p < 3; ++p) C.best[p * N + i] = sqrt(mt[p]);
+        C.status[i] = R.status;
+        C.active[i] = 0;
+        return;
+    }
+    if (R.rho <= cfg.eps) {
+        for (int p = 0; p < 3; ++p) C.best[p * N + i] = sqrt(mt[p]);
+        C.status[i] = kStConverged;
+        C.active[i] = 0;
+        atomicAdd(&C.conv[round], 1);
+        return;
+    }
+    double nu = lm.nu[i];
+    const bool accept = (phase == 0) || (R.Phi < lm.Phi[i]);
+    if (accept) {
+        double jac[12];
+        residual_jacobian_fp64(B, dB, tn, c, jac);
+        for (int p = 0; p < 3; ++p) lm.mu[p * N + i] = mt[p];
+        lm.Phi[i] = R.Phi;
+        lm.rho[i] = R.rho;
+        for (int q = 0; q < 4; ++q) lm.u[q * N + i] = R.u[q];
+        for (int r = 0; r < 12; ++r) lm.jac[r * N + i] = jac[r];
+        if (phase != 0) nu = nu / 10.0;
+    } else {
+        nu = nu * 10.0;
+    }
+    lm.nu[i] = nu;
+    lm.phase[i] = 1;
+    double mu[3];
+    for (int p = 0; p < 3; ++p) {
+        mu[p] = lm.mu[p * N + i];
+        C.best[p * N + i] = sqrt(mu[p]);
+    }
+    if (tr >= cfg.max_trials) {
+        C.status[i] = kStBudget;
+        C.active[i] = 0;
+        return;
+    }
+    double jac[12], u[4], d[3];
+    for (int r = 0; r < 12; ++r) jac[r] = lm.jac[r * N + i];
+    for (int q = 0; q < 4; ++q) u[q] = lm.u[q * N + i];
+    lm_direction(jac, u, nu, d);
+    const double cap = cap_of(cfg, bd);
+    const double cap2 = cap * cap;
+    for (int p = 0; p < 3; ++p) {
+        const double m = fmin(fmax(mu[p] + d[p], 0.0), cap2);
+        lm.mu_try[p * N + i] = m;
+        C.lam_cur[p * N + i] = sqrt(m);
+    }
+}
+
+// |lambda*| to the caller's array, plus status and trials.
+__global__ void k_solve_finish(int64_t N, Common C, double* __restrict__ lam_out, int32_t* __restrict__ st,
+                               int32_t* __restrict__ trials) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int p = 0; p < 3; ++p) lam_out[p * N + i] = fabs(C.best[p * N + i]);
+    st[i] = C.status[i];
+    trials[i] = C.trials[i];
+}
+
+// FP64 acceptance: CONVERGED iff max(f, g) <= eps in FP64 at the returned lambda.
+__global__ void k_solve_accept(int64_t N, const double* __restrict__ fg, double eps, int32_t* __restrict__ st) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t s = st[i];
+    if (s != kStConverged && s != kStBudget) return;
+    const double rho = fmax(fg[i], fg[N + i]);
+    st[i] = (rho <= eps) ? kStConverged : kStBudget;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+struct Layout {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t n) {
+        const size_t o = off;
+        off += (n * sizeof(T) + 255) / 256 * 256;
+        return o;
+    }
+};
+
+struct SolverBufs {
+    Common C;
+    NMDev nm;
+    LMDev lm;
+    int32_t* list;
+    int32_t* bsum;
+    int32_t* n_active;
+    int32_t* cnt_b;
+    int32_t* scratch;
+    Tile* tiles32;
+    Tile* tiles64;
+    int64_t max32, max64;
+    int32_t nblk;
+    int32_t max_rounds;
+};
+
+int64_t pad8(int64_t x) { return (x + 7) / 8 * 8; }
+
+}  // namespace
+
+void solver_free(SolverState& s) {
+    (void)hipFree(s.block);
+    if (s.count_h) (void)hipHostFree(s.count_h);
+    s = SolverState{};
+}
+
+static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs& b) {
+    SolverState& S = ctx_solver(c);
+    const int64_t N = ctx_n(c);
+    const int32_t nb = ctx_nb(c);
+    const F32Shape sh = get_shape(c, lm_mode);
+    const int32_t per32 = sh.ppl * sh.waves * 64;
+    b.max32 = pad8((N + per32 - 1) / per32 + nb);
+    b.max64 = pad8((N + 255) / 256 + nb);
+    b.nblk = (int32_t)((N + kCompactBlock - 1) / kCompactBlock);
+    b.max_rounds = max_rounds;
+    Layout L;
+    const size_t n = (size_t)N;
+    const size_t oLam = L.take<double>(3 * n), oBest = L.take<double>(3 * n), oBphi = L.take<double>(n);
+    const size_t oBst = L.take<int32_t>(n), oTr = L.take<int32_t>(n), oSt = L.take<int32_t>(n),
+                 oAct = L.take<int32_t>(n);
+    const size_t oB = L.take<double>(3 * n), odB = L.take<double>(9 * n), oTan = L.take<double>(12 * n),
+                 oFg = L.take<double>(2 * n);
+    const size_t oConv = L.take<int32_t>((size_t)max_rounds + 1);
+    const size_t oV = L.take<double>(12 * n), oF = L.take<double>(4 * n), oXr = L.take<double>(3 * n),
+                 oFr = L.take<double>(n), oPh = L.take<int32_t>(n), oAux = L.take<int32_t>(n);
+    const size_t oMu = L.take<double>(3 * n), oMut = L.take<double>(3 * n), oPhi = L.take<double>(n),
+                 oRho = L.take<double>(n), oU = L.take<double>(4 * n), oJac = L.take<double>(12 * n),
+                 oNu = L.take<double>(n), oLph = L.take<int32_t>(n);
+    const size_t oList = L.take<int32_t>(n), oBsum = L.take<int32_t>((size_t)b.nblk + 1),
+                 oNact = L.take<int32_t>(1), oCnt = L.take<int32_t>((size_t)nb),
+                 oScr = L.take<int32_t>(2 * (size_t)nb + 1);
+    const size_t oT32 = L.take<Tile>((size_t)b.max32), oT64 = L.take<Tile>((size_t)b.max64);
+    const size_t need = L.off;
+    if (!S.block || S.bytes < (int64_t)need) {
+        (void)hipFree(S.block);
+        S.block = nullptr;
+        S.bytes = 0;
+        if (hipMalloc(&S.block, need) != hipSuccess)
+            return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the solver workspace");
+        S.bytes = (int64_t)need;
+    }
+    if (!S.count_h) {
+        if (hipHostMalloc((void**)&S.count_h, sizeof(int32_t)) != hipSuccess)
+            return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate pinned host memory");
+    }
+    char* base = (char*)S.block;
+    auto D = [&](size_t o) { return (void*)(base + o); };
+    b.C = Common{(double*)D(oLam), (double*)D(oBest), (double*)D(oBphi), (int32_t*)D(oBst), (int32_t*)D(oTr),
+                 (int32_t*)D(oSt), (int32_t*)D(oAct), (double*)D(oB), (double*)D(odB), (double*)D(oTan),
+                 (double*)D(oFg), (int32_t*)D(oConv)};
+    b.nm = NMDev{(double*)D(oV), (double*)D(oF), (double*)D(oXr), (double*)D(oFr), (int32_t*)D(oPh),
+                 (int32_t*)D(oAux)};
+    b.lm = LMDev{(double*)D(oMu), (double*)D(oMut), (double*)D(oPhi), (double*)D(oRho), (double*)D(oU),
+                 (double*)D(oJac), (double*)D(oNu), (int32_t*)D(oLph)};
+    b.list = (int32_t*)D(oList);
+    b.bsum = (int32_t*)D(oBsum);
+    b.n_active = (int32_t*)D(oNact);
+    b.cnt_b = (int32_t*)D(oCnt);
+    b.scratch = (int32_t*)D(oScr);
+    b.tiles32 = (Tile*)D(oT32);
+    b.tiles64 = (Tile*)D(oT64);
+    return DBIE_OK;
+}
+
+static hipError_t compact(const SolverBufs& b, const int32_t* bidx, int64_t N, int32_t nb, int32_t per32,
+                          hipStream_t s) {
+    const unsigned nblk = (unsigned)std::max<int32_t>(b.nblk, 1);
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, N, b.bsum);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, b.bsum, (int32_t)nblk, b.n_active,
+                       b.cnt_b, nb);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, N, b.bsum,
+                       bidx, b.list, b.cnt_b);
+    hipLaunchKernelGGL(k_build_tiles, dim3(1), dim3(256), 0, s, b.cnt_b, nb, per32, b.tiles32, b.max32,
+                       b.scratch);
+    hipLaunchKernelGGL(k_build_tiles, dim3(1), dim3(256), 0, s, b.cnt_b, nb, (int32_t)256, b.tiles64,
+                       b.max64, b.scratch);
+    return hipGetLastError();
+}
+
+}  // namespace dbie
+
+using namespace dbie;
+
+extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts* opt, double* Bout,
+                                 double* fgout, int32_t* status, int32_t* trials, void* stream) {
+    if (!c) return DBIE_E_INVAL;
+    if (!opt) return ctx_fail(c, DBIE_E_INVAL, "solve options are NULL");
+    if (opt->method != DBIE_NELDER_MEAD && opt->method != DBIE_LEVENBERG_MARQUARDT)
+        return ctx_fail(c, DBIE_E_INVAL, "method must be DBIE_NELDER_MEAD or DBIE_LEVENBERG_MARQUARDT");
+    if (opt->max_trials < 1 || opt->max_trials > 1000000)
+        return ctx_fail(c, DBIE_E_INVAL, "max_trials must lie in [1, 1e6]");
+    if (!(opt->eps >= 0.0) || !std::isfinite(opt->eps)) return ctx_fail(c, DBIE_E_INVAL, "eps must be >= 0");
+    if (!std::isfinite(opt->init_step) || !std::isfinite(opt->lambda_cap))
+        return ctx_fail(c, DBIE_E_INVAL, "init_step and lambda_cap must be finite");
+    const int64_t N = ctx_n(c);
+    if (N > 0 && (!lam || !status || !trials))
+        return ctx_fail(c, DBIE_E_INVAL, "lambda_inout, status and trials are required");
+    if (N == 0) return DBIE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SolverBufs b;
+    const bool lmm = opt->method == DBIE_LEVENBERG_MARQUARDT;
+    int rc = solver_bufs(c, opt->max_trials, lmm, b);
+    if (rc) return rc;
+    const int32_t nb = ctx_nb(c);
+    const Geo& geo = ctx_geo(c);
+    const BoundaryDev* bnd = ctx_bnd(c);
+    const bool fp64 = ctx_precision(c) == DBIE_FP64;
+    const F32Shape sh = get_shape(c, lmm);
+    const int32_t per32 = sh.ppl * sh.waves * 64;
+    SolveCfg cfg{opt->method, opt->max_trials, opt->eps, opt->init_step, opt->lambda_cap, ctx_dvds(c), 1e-3};
+    const unsigned gN = (unsigned)((N + 255) / 256);
+#define SOLVE_HIP(call)                                                           \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) return ctx_fail(c, DBIE_E_DEVICE, hipGetErrorString(e_)); \
+    } while (0)
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((opt->max_trials + 256) / 256)), dim3(256), 0, s, b.C.conv,
+                       (int64_t)opt->max_trials + 1, 0);
+    hipLaunchKernelGGL(k_solve_init, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, lam, b.C, b.nm, b.lm);
+    SOLVE_HIP(hipGetLastError());
+    SOLVE_HIP(compact(b, geo.bidx, N, nb, per32, s));
+    EvalSet set{b.list, b.n_active, b.tiles32, b.max32, b.tiles64, b.max64};
+    int32_t rounds = 0;
+    const int32_t check_every = 4;
+    std::vector<hipEvent_t>& trace = solver_trace_events(c);
+    for (auto e : trace) (void)hipEventDestroy(e);
+    trace.clear();
+    if (solver_tracing(c)) {
+        hipEvent_t e = nullptr;
+        SOLVE_HIP(hipEventCreate(&e));
+        SOLVE_HIP(hipEventRecord(e, s));
+        trace.push_back(e);
+    }
+    for (; rounds < opt->max_trials; ++rounds) {
+        rc = eval_set(c, b.C.lam_cur, fp64, lmm, &set, b.C.Bw, b.C.dBw, nullptr, lmm ? b.C.tanw : nullptr, s);
+        if (rc) return rc;
+        if (lmm)
+            hipLaunchKernelGGL(k_lm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list,
+                               b.n_active, rounds, b.C, b.lm);
+        else
+            hipLaunchKernelGGL(k_nm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list,
+                               b.n_active, rounds, b.C, b.nm);
+        SOLVE_HIP(hipGetLastError());
+        SOLVE_HIP(compact(b, geo.bidx, N, nb, per32, s));
+        if (solver_tracing(c)) {
+            hipEvent_t e = nullptr;
+            SOLVE_HIP(hipEventCreate(&e));
+            SOLVE_HIP(hipEventRecord(e, s));
+            trace.push_back(e);
+        }
+        if ((rounds + 1) % check_every == 0) {
+            SOLVE_HIP(hipMemcpyAsync(ctx_solver(c).count_h, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            SOLVE_HIP(hipStreamSynchronize(s));
+            if (*ctx_solver(c).count_h == 0) {
+                ++rounds;
+                break;
+            }
+        }
+    }
+    ctx_solver(c).last_rounds = rounds;
+    ctx_solver(c).last_conv = b.C.conv;
+    hipLaunchKernelGGL(k_solve_finish, dim3(gN), dim3(256), 0, s, N, b.C, lam, status, trials);
+    SOLVE_HIP(hipGetLastError());
+    const bool accept64 = !fp64 && opt->fp64_accept;
+    if (Bout || fgout || accept64) {
+        double* Bdst = Bout ? Bout : b.C.Bw;
+        double* fgdst = fgout ? fgout : b.C.fgw;
+        rc = eval_set(c, lam, fp64 || accept64, false, nullptr, Bdst, b.C.dBw, fgdst, nullptr, s);
+        if (rc) return rc;
+        if (accept64) {
+            hipLaunchKernelGGL(k_solve_accept, dim3(gN), dim3(256), 0, s, N, fgdst, opt->eps, status);
+            SOLVE_HIP(hipGetLastError());
+        }
+    }
+    return DBIE_OK;
+#undef SOLVE_HIP
+}

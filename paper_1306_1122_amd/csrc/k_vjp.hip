@@ -1,0 +1,192 @@
+// Adjoint of the evaluation (dbie_grad): the transpose of the Eq. (16) nodal sum together with its
+// frozen-lambda gradient rows (the gradient with respect to B0), the lambda gradient from the
+// mu-tangents, and the residual Jacobian d u / d mu.
+//
+// Transpose in pixel units (see dbie_internal.h for the forward relations): with per-point weights
+//   alpha_p = w gB_p / 2pi + gZ_p / (2pi h),   beta_p = w^2 gZ_p / (2pi h),
+//   gx_p = -w gX_p / (2pi h),                  gy_p = -w gY_p / (2pi h)
+// (gX, gY, gZ = dLoss/d(dB_p/dx, dy, dz)),
+//   gB0_p(k) = sum_i [ N rho^-3 alpha_p + H rho^-5 (beta_p + gx_p (a_k - u_i) + gy_p (b_k - v_i)) ].
+// Pixels are the outputs (one lane per pixel); the points of the pixel's magnetogram stream through
+// LDS in tiles. Every output is written by exactly one lane: deterministic, no atomics. FP64.
+#include <algorithm>
+#include <vector>
+
+#include "dbie_solver.h"
+
+namespace dbie {
+
+constexpr int kVjpPts = 64;      // points per LDS tile
+constexpr int kVjpCoef = 15;     // Lambda[3], alpha[3], beta[3], gx[3], gy[3]
+constexpr double kInv2Pi_v = 0.15915494309189533577;
+
+struct PixTile {
+    int32_t b;
+    int32_t start;   // first pixel
+};
+
+__global__ void k_vjp_coef(int64_t N, const BoundaryDev* __restrict__ bnd, Geo geo,
+                           const double* __restrict__ lam, const double* __restrict__ gB,
+                           const double* __restrict__ gdB, double* __restrict__ coef) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const BoundaryDev bd = bnd[geo.bidx[i]];
+    const double w = geo.w[i], h = bd.h;
+    for (int p = 0; p < 3; ++p) {
+        const double b = gB ? gB[p * N + i] : 0.0;
+        const double gx = gdB ? gdB[(3 * p + 0) * N + i] : 0.0;
+        const double gy = gdB ? gdB[(3 * p + 1) * N + i] : 0.0;
+        const double gz = gdB ? gdB[(3 * p + 2) * N + i] : 0.0;
+        coef[(0 + p) * N + i] = lam[p * N + i] * h;
+        coef[(3 + p) * N + i] = w * kInv2Pi_v * b + gz * kInv2Pi_v / h;
+        coef[(6 + p) * N + i] = w * w * gz * kInv2Pi_v / h;
+        coef[(9 + p) * N + i] = -w * gx * kInv2Pi_v / h;
+        coef[(12 + p) * N + i] = -w * gy * kInv2Pi_v / h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptiles,
+                                               const BoundaryDev* __restrict__ bnd,
+                                               const int64_t* __restrict__ seg, Geo geo, int64_t N,
+                                               const double* __restrict__ coef, double* __restrict__ gB0) {
+    __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef][kVjpPts];
+    const PixTile pt = ptiles[blockIdx.x];
+    const BoundaryDev bd = bnd[pt.b];
+    const int32_t k = pt.start + (int32_t)threadIdx.x;
+    const bool live = k < bd.npix;
+    const double a = live ? (double)(k % bd.nx) : 0.0;
+    const double bb = live ? (double)(k / bd.nx) : 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t p0 = seg[pt.b], p1 = seg[pt.b + 1];
+    for (int64_t i0 = p0; i0 < p1; i0 += kVjpPts) {
+        const int n = (int)min<int64_t>(kVjpPts, p1 - i0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            const int64_t i = i0 + q;
+            su[q] = geo.u[i];
+            sv[q] = geo.v[i];
+            const double w = geo.w[i];
+            sw2[q] = w * w;
+        }
+        for (int q = threadIdx.x; q < kVjpCoef * n; q += blockDim.x) {
+            const int r = q / n, e = q - r * n;
+            sc[r][e] = coef[r * N + i0 + e];
+        }
+        __syncthreads();
+        double part[3] = {0.0, 0.0, 0.0};
+        for (int e = 0; e < n; ++e) {
+            const double dx = a - su[e], dy = bb - sv[e];
+            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, sw2[e]));
+            const double ri = rsqrt(r2);
+            const double r = r2 * ri;
+            const double ri2 = ri * ri;
+            const double ri3 = ri2 * ri;
+            const double ri5 = ri3 * ri2;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const double t = sc[p][e] * r;
+                double s, c;
+                sincos(t, &s, &c);
+                const double nn = __builtin_fma(t, s, c);
+                const double hh = __builtin_fma(t, t * c, -3.0 * nn);
+                const double lin = __builtin_fma(sc[9 + p][e], dx, __builtin_fma(sc[12 + p][e], dy, sc[6 + p][e]));
+                part[p] = __builtin_fma(nn * ri3, sc[3 + p][e], __builtin_fma(hh * ri5, lin, part[p]));
+            }
+        }
+        for (int p = 0; p < 3; ++p) acc[p] += part[p];
+    }
+    if (live) {
+        const int64_t o = bd.pix_off + k;
+        for (int p = 0; p < 3; ++p) gB0[o + (int64_t)p * bd.npix] = acc[p];
+    }
+}
+
+// g_mu_p = gB_p tan[p] + sum_q gdB[3p+q] tan[3+3p+q]; g_lambda = 2 lambda g_mu.
+__global__ void k_grad_lambda(int64_t N, const double* __restrict__ lam, const double* __restrict__ gB,
+                              const double* __restrict__ gdB, const double* __restrict__ tan,
+                              double* __restrict__ glam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int p = 0; p < 3; ++p) {
+        double g = gB ? gB[p * N + i] * tan[p * N + i] : 0.0;
+        if (gdB)
+            for (int q = 0; q < 3; ++q) g += gdB[(3 * p + q) * N + i] * tan[(3 + 3 * p + q) * N + i];
+        glam[p * N + i] = 2.0 * lam[p * N + i] * g;
+    }
+}
+
+__global__ void k_resid_jac(int64_t N, const BoundaryDev* __restrict__ bnd, const int32_t* __restrict__ bidx,
+                            double dvds, const double* __restrict__ B, const double* __restrict__ dB,
+                            const double* __restrict__ tan, double* __restrict__ jac_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double h = bnd[bidx[i]].h;
+    double b[3], d[9], t[12], jac[12];
+    for (int p = 0; p < 3; ++p) b[p] = B[p * N + i];
+    for (int r = 0; r < 9; ++r) d[r] = dB[r * N + i];
+    for (int r = 0; r < 12; ++r) t[r] = tan[r * N + i];
+    residual_jacobian_fp64(b, d, t, dvds * h, jac);
+    for (int r = 0; r < 12; ++r) jac_out[r * N + i] = jac[r];
+}
+
+}  // namespace dbie
+
+using namespace dbie;
+
+extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const double* gdB, double* glam,
+                         double* gB0, double* resid_jac, void* stream) {
+    if (!c) return DBIE_E_INVAL;
+    const int64_t N = ctx_n(c);
+    if (N > 0 && !lam) return ctx_fail(c, DBIE_E_INVAL, "lambda is required");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t nb = ctx_nb(c);
+    const Geo& geo = ctx_geo(c);
+    const BoundaryDev* bnd = ctx_bnd(c);
+    const unsigned gN = (unsigned)((std::max<int64_t>(N, 1) + 255) / 256);
+#define GRAD_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) return ctx_fail(c, DBIE_E_DEVICE, hipGetErrorString(e_)); \
+    } while (0)
+    if (N > 0 && (glam || resid_jac)) {
+        double* w = (double*)ctx_scratch(c, 0, (size_t)N * 24 * sizeof(double));
+        if (!w) return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the gradient workspace");
+        double* Bw = w;
+        double* dBw = w + 3 * N;
+        double* tw = w + 12 * N;
+        int rc = eval_set(c, lam, ctx_precision(c) == DBIE_FP64, true, nullptr, Bw, dBw, nullptr, tw, s);
+        if (rc) return rc;
+        if (glam) hipLaunchKernelGGL(k_grad_lambda, dim3(gN), dim3(256), 0, s, N, lam, gB, gdB, tw, glam);
+        if (resid_jac)
+            hipLaunchKernelGGL(k_resid_jac, dim3(gN), dim3(256), 0, s, N, bnd, geo.bidx, ctx_dvds(c), Bw, dBw,
+                               tw, resid_jac);
+        GRAD_HIP(hipGetLastError());
+    }
+    if (gB0) {
+        // pixel tiles of every boundary, and the point segments on the device
+        std::vector<PixTile> pt;
+        for (int32_t b = 0; b < nb; ++b) {
+            const BoundaryDev& bd = ctx_bnd_host(c, b);
+            for (int32_t k = 0; k < bd.npix; k += 256) pt.push_back(PixTile{b, k});
+        }
+        const size_t szc = (size_t)std::max<int64_t>(N, 1) * kVjpCoef * sizeof(double);
+        const size_t szt = (pt.size() * sizeof(PixTile) + 255) / 256 * 256;
+        const size_t szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
+        char* w = (char*)ctx_scratch(c, 1, szc + szt + szs);
+        if (!w) return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the adjoint workspace");
+        double* coef = (double*)w;
+        PixTile* ptd = (PixTile*)(w + szc);
+        int64_t* segd = (int64_t*)(w + szc + szt);
+        GRAD_HIP(hipMemcpyAsync(ptd, pt.data(), pt.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
+        GRAD_HIP(hipMemcpyAsync(segd, ctx_seg(c), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        if (N > 0)
+            hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
+        hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N, coef,
+                           gB0);
+        GRAD_HIP(hipGetLastError());
+        // the host arrays above must stay alive until the copies have been consumed
+        GRAD_HIP(hipStreamSynchronize(s));
+    }
+    return DBIE_OK;
+#undef GRAD_HIP
+}

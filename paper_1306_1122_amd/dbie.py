@@ -237,6 +237,35 @@ def dbie_query(ctx: Context) -> Dict[str, int]:
     return dict(n_points=a.value, n_pixels=b.value, ppl=p.value, waves=w.value, tile_pixels=t.value)
 
 
+def dbie_query_tan(ctx: Context) -> Dict[str, int]:
+    p, w, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib().dbie_query_tan(ctx.handle, ctypes.byref(p), ctypes.byref(w), ctypes.byref(t)), ctx,
+           "dbie_query_tan")
+    return dict(ppl=p.value, waves=w.value, tile_pixels=t.value)
+
+
+def dbie_set_tile_shape(ctx: Context, ppl: int, waves: int, tile_pixels: int):
+    _check(_lib().dbie_set_tile_shape(ctx.handle, int(ppl), int(waves), int(tile_pixels)), ctx,
+           "dbie_set_tile_shape")
+
+
+def dbie_solve_trace(ctx: Context, enable: bool = True):
+    _check(_lib().dbie_solve_trace(ctx.handle, int(bool(enable))), ctx, "dbie_solve_trace")
+
+
+def dbie_solve_trace_read(ctx: Context, max_rounds: int = 100000):
+    """Returns (t_ms [rounds], converged [rounds]) of the last traced solve."""
+    import numpy as np
+    n = ctypes.c_int32()
+    _check(_lib().dbie_solve_trace_read(ctx.handle, None, None, 0, ctypes.byref(n)), ctx,
+           "dbie_solve_trace_read")
+    m = min(n.value, max_rounds)
+    t = (ctypes.c_double * max(m, 1))()
+    cv = (ctypes.c_int32 * max(m, 1))()
+    _check(_lib().dbie_solve_trace_read(ctx.handle, t, cv, m, ctypes.byref(n)), ctx, "dbie_solve_trace_read")
+    return np.array(t[:m]), np.array(cv[:m], dtype=np.int64)
+
+
 def dbie_destroy(ctx: Context):
     ctx.close()
 

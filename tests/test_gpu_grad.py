@@ -1,0 +1,101 @@
+"""GPU adjoint (dbie_grad) and the torch.autograd.Function against the oracle, finite differences
+and the dot-product test."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1306_1122_amd as D
+from workloads import config3
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def case(seed=31, nx=23, ny=19, n=400, h=0.5):
+    rng = np.random.default_rng(seed)
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    x0, y0 = -1.0, 2.0
+    xyz = np.stack([rng.uniform(x0, x0 + nx * h, n), rng.uniform(y0, y0 + ny * h, n), rng.uniform(0.4 * h, 8 * h, n)])
+    lam = rng.uniform(0.1, 1.2, size=(3, n))
+    gB = rng.normal(size=(3, n))
+    gdB = rng.normal(size=(9, n))
+    return B0, x0, y0, h, xyz, lam, gB, gdB
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5)])
+def test_grad_matches_oracle(precision, tol):
+    B0, x0, y0, h, xyz, lam, gB, gdB = case()
+    ctx = D.dbie_init([dict(B0=T(B0), x0=x0, y0=y0, h=h)], T(xyz), precision=precision)
+    r = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB), want_resid_jac=True)
+    torch.cuda.synchronize()
+    gB0_ref, glam_ref, _ = oracle.vjp(B0, x0, y0, h, xyz, lam, gB, gdB)
+    # the B0 adjoint is FP64 in both contexts
+    assert rel(r["gB0"].cpu().numpy().reshape(3, *B0.shape[1:]), gB0_ref) <= 1e-10
+    assert rel(r["glambda"].cpu(), glam_ref) <= tol
+    B, dB, tan = oracle.field(B0, x0, y0, h, xyz, lam, tangents=True)
+    jac = oracle.residual_jacobian(B, dB, tan, h)
+    assert rel(r["resid_jac"].cpu(), jac) <= 10 * tol
+
+
+def test_dot_product_on_the_gpu():
+    B0, x0, y0, h, xyz, lam, gB, gdB = case(seed=32)
+    x = np.random.default_rng(5).normal(size=B0.shape)
+    cx = D.dbie_init([dict(B0=T(x), x0=x0, y0=y0, h=h)], T(xyz), precision="fp64")
+    out = D.dbie_eval_field(cx, T(lam))
+    lhs = float((out["B"] * T(gB)).sum() + (out["dB"] * T(gdB)).sum())
+    r = D.dbie_grad(cx, T(lam), gB=T(gB), gdB=T(gdB))
+    rhs = float((r["gB0"].view(3, *B0.shape[1:]) * T(x)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_lambda_gradient_against_differences_on_the_large_grid():
+    """The 256x256 magnetogram of the gradient workload, 1e3 seeded random interior points: the
+    lambda gradient from the tangents against central differences of the GPU field in mu."""
+    w = config3(nz=4)
+    bd = w.boundaries[0]
+    rng = np.random.default_rng(33)
+    idx = rng.choice(w.n_points, 1000, replace=False)
+    xyz = w.xyz[:, idx].copy()
+    xyz[2] = rng.uniform(1.0, 128.0, 1000)
+    lam = rng.uniform(0.01, 4 * np.pi / 256, size=(3, 1000))
+    gB = rng.normal(size=(3, 1000))
+    gdB = rng.normal(size=(9, 1000))
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(xyz), precision="fp64")
+    g = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB), want_gB0=False)["glambda"].cpu().numpy()
+    mu = lam * lam
+    fd = np.zeros_like(lam)
+    for p in range(3):
+        d = 1e-6 * mu[p]
+        mp, mm = mu.copy(), mu.copy()
+        mp[p] += d
+        mm[p] -= d
+        op = D.dbie_eval_field(ctx, T(np.sqrt(mp)))
+        om = D.dbie_eval_field(ctx, T(np.sqrt(mm)))
+        Lp = (op["B"] * T(gB)).sum(0) + (op["dB"] * T(gdB)).sum(0)
+        Lm = (om["B"] * T(gB)).sum(0) + (om["dB"] * T(gdB)).sum(0)
+        fd[p] = ((Lp - Lm) / (2 * T(d))).cpu().numpy() * 2 * lam[p]
+    assert rel(g, fd) <= 1e-6
+    # and the oracle's gradient on a subset
+    sub = slice(0, 40)
+    _, glam_ref, _ = oracle.vjp(bd.B0, bd.x0, bd.y0, bd.h, xyz[:, sub], lam[:, sub], gB[:, sub], gdB[:, sub])
+    assert rel(g[:, sub], glam_ref) <= 1e-10
+
+
+def test_autograd_function():
+    B0, x0, y0, h, xyz, lam, gB, gdB = case(seed=34, n=200)
+    B0t = T(B0).requires_grad_(True)
+    lamt = T(lam).requires_grad_(True)
+    B, dB = D.dbie_field(B0t, lamt, T(xyz), x0, y0, h, precision="fp64")
+    loss = (B * T(gB)).sum() + (dB * T(gdB)).sum()
+    loss.backward()
+    gB0_ref, glam_ref, _ = oracle.vjp(B0, x0, y0, h, xyz, lam, gB, gdB)
+    assert rel(B0t.grad.cpu(), gB0_ref) <= 1e-10
+    assert rel(lamt.grad.cpu(), glam_ref) <= 1e-10

@@ -1,0 +1,154 @@
+"""GPU lambda search (dbie_solve_lambda) against the oracle's solvers and re-evaluation.
+
+lambda* is not unique (the paper notes several lambda satisfy the conditions at a point), so the
+parity is on what is fixed: every point the GPU marks CONVERGED must satisfy max(f, g) <= eps when the
+FP64 oracle re-evaluates it at the returned lambda; the GPU's (B, f, g) at lambda* match the oracle
+there; and with FP64 evaluations the simplex trajectories coincide with the oracle's except where
+rounding flips a near-tie decision.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1306_1122_amd as D
+from workloads import config1
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def lowlou_ctx(precision):
+    w = config1()
+    bd = w.boundaries[0]
+    return w, bd, D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision=precision)
+
+
+def oracle_solve(bd, xyz, method, budget, eps, idx):
+    cap = math.pi / bd.h
+    delta = oracle.default_nm_step(bd.nx, bd.ny, bd.h)
+    out = {}
+    for i in idx:
+        prob = oracle.PointProblem(bd.B0, bd.x0, bd.y0, bd.h, xyz[:, i])
+        if method == "nm":
+            out[i] = oracle.solve_point_nm(prob, np.zeros(3), budget, eps, delta, cap)
+        else:
+            out[i] = oracle.solve_point_lm(prob, np.zeros(3), budget, eps, cap)
+    return out
+
+
+@pytest.mark.parametrize("method,budget", [("nm", 50), ("lm", 20)])
+def test_fp64_solve_matches_oracle_trajectories(method, budget):
+    w, bd, ctx = lowlou_ctx("fp64")
+    N = w.n_points
+    lam = torch.zeros(3, N, dtype=torch.float64, device="cuda:0")
+    r = D.dbie_solve_lambda(ctx, lam, method=method, max_trials=budget, eps=1e-4)
+    torch.cuda.synchronize()
+    lg = r["lam"].cpu().numpy()
+    st = r["status"].cpu().numpy()
+    tr = r["trials"].cpu().numpy()
+    assert np.all(tr >= 1) and np.all(tr <= budget)
+    idx = list(range(0, N, 4))
+    ref = oracle_solve(bd, w.xyz, method, budget, 1e-4, idx)
+    same = 0
+    for i in idx:
+        lo, so, to, _ = ref[i]
+        if np.allclose(lg[:, i], np.abs(lo), rtol=1e-9, atol=1e-12) and tr[i] == to and st[i] == so:
+            same += 1
+    frac = same / len(idx)
+    print(f"{method}: identical trajectories {same}/{len(idx)}", flush=True)
+    assert frac >= 0.9, frac
+    # field and residuals at lambda*: the GPU's outputs equal the oracle's re-evaluation
+    Bo, dBo = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz, lg)
+    res = oracle.residuals(Bo, dBo, bd.h)
+    assert rel(r["B"].cpu(), Bo) <= 1e-10
+    fg = r["fg"].cpu().numpy()
+    ok = np.isfinite(res["f"])
+    assert rel(fg[0][ok], res["f"][ok]) <= 1e-9 and rel(fg[1][ok], res["g"][ok]) <= 1e-9
+    conv = st == oracle.ST_CONVERGED
+    assert np.all(res["rho"][conv] <= 1e-4 * (1 + 1e-6))
+    # the search never ends worse than its start (lambda = 0)
+    B0_, dB0_ = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz, np.zeros((3, N)))
+    phi0 = oracle.residuals(B0_, dB0_, bd.h)["Phi"]
+    assert np.all(res["Phi"] <= phi0 * (1 + 1e-12))
+
+
+def test_fp32c_lm_with_fp64_acceptance():
+    w, bd, ctx = lowlou_ctx("fp32c")
+    N = w.n_points
+    lam = torch.zeros(3, N, dtype=torch.float64, device="cuda:0")
+    r = D.dbie_solve_lambda(ctx, lam, method="lm", max_trials=20, eps=1e-4, fp64_accept=True)
+    torch.cuda.synchronize()
+    lg = r["lam"].cpu().numpy()
+    st = r["status"].cpu().numpy()
+    Bo, dBo = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz, lg)
+    res = oracle.residuals(Bo, dBo, bd.h)
+    # the acceptance pass is FP64: its field, residuals and statuses are the oracle's
+    assert rel(r["B"].cpu(), Bo) <= 1e-10
+    conv = st == oracle.ST_CONVERGED
+    assert np.array_equal(conv, res["rho"] <= 1e-4)
+    B0_, dB0_ = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz, np.zeros((3, N)))
+    phi0 = oracle.residuals(B0_, dB0_, bd.h)["Phi"]
+    # LM accepts only decreases of Phi (in FP32C): allow the FP32C-vs-FP64 difference
+    assert np.mean(res["Phi"] <= phi0 * (1 + 1e-4)) >= 0.99
+
+
+@pytest.mark.parametrize("method", ["nm", "lm"])
+def test_solve_is_deterministic_and_batched_equals_single(method):
+    rng = np.random.default_rng(21)
+    bds, xyzs, seg = [], [], [0]
+    for nx, ny, n in ((20, 16, 300), (12, 30, 257)):
+        B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+        bds.append(dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0))
+        xyzs.append(np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0.5, 8, n)]))
+        seg.append(seg[-1] + n)
+    xyz = np.concatenate(xyzs, axis=1)
+    lam0 = rng.uniform(0, 0.2, size=xyz.shape)
+    outs = []
+    for prec in ("fp64", "fp32c"):
+        ctx = D.dbie_init(bds, T(xyz), seg=seg, precision=prec)
+        a = D.dbie_solve_lambda(ctx, T(lam0), method=method, max_trials=12, fp64_accept=False)
+        b = D.dbie_solve_lambda(ctx, T(lam0), method=method, max_trials=12, fp64_accept=False)
+        for k in ("lam", "status", "trials", "B", "fg"):
+            assert torch.equal(a[k], b[k]), (prec, k)
+        for bi in range(2):
+            c1 = D.dbie_init([bds[bi]], T(xyz[:, seg[bi]:seg[bi + 1]]), precision=prec)
+            s1 = D.dbie_solve_lambda(c1, T(lam0[:, seg[bi]:seg[bi + 1]]), method=method, max_trials=12,
+                                     fp64_accept=False)
+            for k in ("lam", "status", "trials"):
+                assert torch.equal(s1[k], a[k][..., seg[bi]:seg[bi + 1]]), (prec, bi, k)
+        outs.append(a)
+
+
+def test_solver_edge_cases():
+    rng = np.random.default_rng(22)
+    B0 = rng.normal(size=(3, 10, 10))
+    xyz = np.stack([rng.uniform(0, 9, 6), rng.uniform(0, 9, 6), rng.uniform(1, 5, 6)])
+    ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision="fp64")
+    lam0 = np.zeros((3, 6))
+    lam0[0, 1] = np.nan           # non-finite start
+    lam0[1, 2] = 10.0             # beyond the cap pi/h: every vertex of the simplex is infeasible
+    r = D.dbie_solve_lambda(ctx, T(lam0), method="nm", max_trials=5)
+    st = r["status"].cpu().numpy()
+    tr = r["trials"].cpu().numpy()
+    assert st[1] == D._lib.DBIE_ST_NONFINITE and tr[1] == 0
+    assert st[2] == D._lib.DBIE_ST_NONFINITE and tr[2] == 5
+    # budget of one trial: exactly one evaluation
+    r1 = D.dbie_solve_lambda(ctx, T(np.zeros((3, 6))), method="lm", max_trials=1)
+    assert torch.all(r1["trials"] == 1)
+    # zero boundary field: |B| = 0 everywhere
+    ctx0 = D.dbie_init([dict(B0=T(np.zeros((3, 10, 10))), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision="fp64")
+    for m in ("nm", "lm"):
+        r0 = D.dbie_solve_lambda(ctx0, T(np.zeros((3, 6))), method=m, max_trials=6)
+        assert torch.all(r0["status"] == D._lib.DBIE_ST_DEGENERATE), m
+    with pytest.raises(D.DbieError, match="max_trials"):
+        D.dbie_solve_lambda(ctx, T(np.zeros((3, 6))), method="nm", max_trials=0)
