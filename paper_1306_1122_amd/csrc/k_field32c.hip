@@ -9,7 +9,8 @@
 // Arithmetic per pair, all FP32:
 //   dx = (a_k - floor(u)) - frac(u)    (the integer difference is exact: one rounding in total)
 //   rho^-1 = rsq(dx^2 + dy^2 + w^2), and per component t = Lambda rho, sin/cos in revolutions
-//   (range-reduced by fract), N = t sin t + cos t, H = t (t cos t) - 3 N, and the sums
+//   (range-reduced by fract only when a workgroup's |Lambda| rho / 2pi can exceed the hardware's
+//   accurate range of 256 revolutions), N = t sin t + cos t, H = t (t cos t) - 3 N, and the sums
 //   A0 += N rho^-3 B0,  A1 += H rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += H rho^-3 B0 rho^-2.
 // Compensation: each pixel tile is summed in FP32 (error ~ TP u), and the tile partials are added
 // into FP64 totals, so the error does not grow with the magnetogram size.
@@ -31,7 +32,7 @@ struct PointState {
     uint32_t msk[PPL];
 };
 
-template <int PPL, bool TAN, bool SLOW>
+template <int PPL, bool TAN, bool SLOW, bool FRACT>
 __device__ __forceinline__ void pixel_step(const PointState<PPL, TAN>& S, float a, float b, float bx,
                                            float by, float bz, float (&acc)[PPL][TAN ? kAcc : kAccField]) {
 #pragma unroll
@@ -55,7 +56,8 @@ __device__ __forceinline__ void pixel_step(const PointState<PPL, TAN>& S, float 
         const float dyr = dy * ri2;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            const float tr = __builtin_amdgcn_fractf(S.lr[j][p] * r);
+            // v_sin / v_cos take revolutions and are accurate on [-256, 256]; FRACT reduces first
+            const float tr = FRACT ? __builtin_amdgcn_fractf(S.lr[j][p] * r) : S.lr[j][p] * r;
             const float sn = __builtin_amdgcn_sinf(tr);
             const float cs = __builtin_amdgcn_cosf(tr);
             const float t = S.lt[j][p] * r;
@@ -79,6 +81,18 @@ __device__ __forceinline__ void pixel_step(const PointState<PPL, TAN>& S, float 
     }
 }
 
+template <int PPL, int TP, bool TAN, bool SLOW, bool FRACT>
+__device__ __forceinline__ void tile_loop(const PointState<PPL, TAN>& S, const float4 (*s4)[TP / 4],
+                                          float (&part)[PPL][TAN ? kAcc : kAccField]) {
+    for (int q = 0; q < TP / 4; ++q) {
+        const float4 A = s4[0][q], Bq = s4[1][q], X = s4[2][q], Y = s4[3][q], Z = s4[4][q];
+        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.x, Bq.x, X.x, Y.x, Z.x, part);
+        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.y, Bq.y, X.y, Y.y, Z.y, part);
+        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.z, Bq.z, X.z, Y.z, Z.z, part);
+        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.w, Bq.w, X.w, Y.w, Z.w, part);
+    }
+}
+
 template <int PPL, int WAVES, int TP, bool TAN>
 __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
@@ -92,6 +106,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     constexpr int TQ = TP / 4;
     __shared__ float4 s4[5][TQ];
     __shared__ int box[4];
+    __shared__ float rev_max;   // bound of |Lambda| r / 2pi over the workgroup's pairs
 
     // XCD-aware order (static schedules): workgroups are dealt round-robin to the 8 XCDs; give each
     // XCD a contiguous run of the schedule so that its L2 sees few magnetograms. Schedules are padded
@@ -110,6 +125,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
         box[1] = INT_MIN;
         box[2] = INT_MAX;
         box[3] = INT_MIN;
+        rev_max = 0.0f;
     }
     __syncthreads();
 
@@ -139,6 +155,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
         S.fa[j] = (float)wa;
         S.fb[j] = (float)wb;
         S.msk[j] = live[j] ? geo.near_mask[i] : 0u;
+        {
+            // farthest pixel centre of the magnetogram from this point
+            const float uf = -S.xn[j] + S.xf[j], vf = -S.yn[j] + S.yf[j];
+            const float dxm = fmaxf(fabsf(uf), fabsf((float)(bd.nx - 1) - uf)) + 1.0f;
+            const float dym = fmaxf(fabsf(vf), fabsf((float)(bd.ny - 1) - vf)) + 1.0f;
+            const float rmax = sqrtf(dxm * dxm + dym * dym + S.w2[j]);
+            const float lmax = fmaxf(fabsf(S.lr[j][0]), fmaxf(fabsf(S.lr[j][1]), fabsf(S.lr[j][2])));
+            const float rv = live[j] ? lmax * rmax : 0.0f;
+            // non-negative floats order like their bit patterns; NaN (bits above +inf) forces FRACT
+            atomicMax(reinterpret_cast<int*>(&rev_max), __float_as_int(rv));
+        }
         if (S.msk[j]) {
             atomicMin(&box[0], wa - kNearWin);
             atomicMax(&box[1], wa + kNearWin);
@@ -149,6 +176,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     __syncthreads();
     const int amin = box[0], amax = box[1], bmin = box[2], bmax = box[3];
     const bool any_near = amin <= amax;
+    const bool need_fract = !(rev_max < 255.0f);
 
     double tot[PPL][NA];
     float part[PPL][NA];
@@ -180,21 +208,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
 #pragma unroll
             for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
         if (!slow) {
-            for (int q = 0; q < TQ; ++q) {
-                const float4 A = s4[0][q], Bq = s4[1][q], X = s4[2][q], Y = s4[3][q], Z = s4[4][q];
-                pixel_step<PPL, TAN, false>(S, A.x, Bq.x, X.x, Y.x, Z.x, part);
-                pixel_step<PPL, TAN, false>(S, A.y, Bq.y, X.y, Y.y, Z.y, part);
-                pixel_step<PPL, TAN, false>(S, A.z, Bq.z, X.z, Y.z, Z.z, part);
-                pixel_step<PPL, TAN, false>(S, A.w, Bq.w, X.w, Y.w, Z.w, part);
-            }
+            if (need_fract) tile_loop<PPL, TP, TAN, false, true>(S, s4, part);
+            else tile_loop<PPL, TP, TAN, false, false>(S, s4, part);
         } else {
-            for (int q = 0; q < TQ; ++q) {
-                const float4 A = s4[0][q], Bq = s4[1][q], X = s4[2][q], Y = s4[3][q], Z = s4[4][q];
-                pixel_step<PPL, TAN, true>(S, A.x, Bq.x, X.x, Y.x, Z.x, part);
-                pixel_step<PPL, TAN, true>(S, A.y, Bq.y, X.y, Y.y, Z.y, part);
-                pixel_step<PPL, TAN, true>(S, A.z, Bq.z, X.z, Y.z, Z.z, part);
-                pixel_step<PPL, TAN, true>(S, A.w, Bq.w, X.w, Y.w, Z.w, part);
-            }
+            if (need_fract) tile_loop<PPL, TP, TAN, true, true>(S, s4, part);
+            else tile_loop<PPL, TP, TAN, true, false>(S, s4, part);
         }
 #pragma unroll
         for (int j = 0; j < PPL; ++j)

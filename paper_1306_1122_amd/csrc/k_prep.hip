@@ -54,7 +54,8 @@ __global__ void k_prep_points(const Tile* __restrict__ tiles, const BoundaryDev*
 }
 
 // FP32 pixel planes of one boundary: a, b (pixel indices as exact floats), Bx, By, Bz, each padded
-// to npix_pad with zero field at a far-away position (zero terms, finite distance).
+// to npix_pad with zero field placed on pixel (0, 0): zero terms at a distance inside the range the
+// bulk kernel's bound on the sin/cos argument covers.
 __global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, float* __restrict__ pixf) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= bd.npix_pad) return;
@@ -68,8 +69,8 @@ __global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, floa
         base[3 * P + k] = (float)B0d[bd.pix_off + bd.npix + k];
         base[4 * P + k] = (float)B0d[bd.pix_off + 2 * (int64_t)bd.npix + k];
     } else {
-        base[k] = -65536.0f;
-        base[P + k] = -65536.0f;
+        base[k] = 0.0f;
+        base[P + k] = 0.0f;
         base[2 * P + k] = 0.0f;
         base[3 * P + k] = 0.0f;
         base[4 * P + k] = 0.0f;

@@ -51,9 +51,8 @@ __global__ void k_compact_count(const int32_t* __restrict__ active, int64_t N, i
     }
 }
 
-// Exclusive scan of the block counts in one workgroup; also clears the per-boundary counters.
-__global__ void k_compact_scan(int32_t* __restrict__ bsum, int32_t nblk, int32_t* __restrict__ total,
-                               int32_t* __restrict__ cnt_b, int32_t nb) {
+// Exclusive scan of the block counts in one workgroup.
+__global__ void k_compact_scan(int32_t* __restrict__ bsum, int32_t nblk, int32_t* __restrict__ total) {
     __shared__ int32_t part[1024];
     const int tid = threadIdx.x;
     const int per = (nblk + 1023) / 1024;
@@ -75,12 +74,10 @@ __global__ void k_compact_scan(int32_t* __restrict__ bsum, int32_t nblk, int32_t
         run += v;
     }
     if (tid == 1023) *total = part[1023];
-    for (int b = tid; b < nb; b += 1024) cnt_b[b] = 0;
 }
 
 __global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
-                                  const int32_t* __restrict__ boff, const int32_t* __restrict__ bidx,
-                                  int32_t* __restrict__ list, int32_t* __restrict__ cnt_b) {
+                                  const int32_t* __restrict__ boff, int32_t* __restrict__ list) {
     __shared__ int32_t wcnt[kCompactItems][kCompactThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kCompactBlock;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -103,42 +100,70 @@ __global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
         if (fl[k]) {
             const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
             list[before + rk[k]] = (int32_t)i;
-            atomicAdd(&cnt_b[bidx[i]], 1);
         }
         for (int w = 0; w < kCompactThreads / 64; ++w) run += wcnt[k][w];
     }
 }
 
-// Tiles of `per` consecutive list entries of one boundary; the remaining slots up to max_tiles get
-// count 0. The list is sorted by point index and points are grouped by boundary, so boundary b's
-// entries start at the sum of the counts of the boundaries before it.
-__global__ void k_build_tiles(const int32_t* __restrict__ cnt_b, int32_t nb, int32_t per,
-                              Tile* __restrict__ tiles, int64_t max_tiles, int32_t* __restrict__ scratch) {
-    // scratch: [nb] tile offsets, [nb] list offsets, [1] total tiles
-    if (threadIdx.x == 0) {
-        int32_t to = 0, lo = 0;
-        for (int b = 0; b < nb; ++b) {
-            scratch[b] = to;
-            scratch[nb + b] = lo;
-            to += (cnt_b[b] + per - 1) / per;
-            lo += cnt_b[b];
+// Active points of each boundary from the ranks at its segment ends (rank(s) = active points with
+// index < s = block prefix + the active flags of the block before s), then the tile offsets of both
+// schedules. One workgroup; thread b handles segment start b.
+__global__ void k_seg_counts(const int32_t* __restrict__ active, int64_t N, const int32_t* __restrict__ boff,
+                             const int32_t* __restrict__ total, const int64_t* __restrict__ seg, int32_t nb,
+                             int32_t* __restrict__ cnt_b, int32_t* __restrict__ rank, int32_t per32,
+                             int32_t per64, int32_t* __restrict__ off32, int32_t* __restrict__ off64) {
+    for (int b = threadIdx.x; b <= nb; b += blockDim.x) {
+        const int64_t sp = seg[b];
+        int32_t r;
+        if (sp >= N) {
+            r = *total;
+        } else {
+            const int64_t blk = sp / kCompactBlock;
+            r = boff[blk];
+            for (int64_t i = blk * kCompactBlock; i < sp; ++i) r += active[i] ? 1 : 0;
         }
-        scratch[2 * nb] = to;
+        rank[b] = r;
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int32_t c = cnt_b[b];
-        const int32_t nt = (c + per - 1) / per;
-        for (int k = 0; k < nt; ++k) {
-            Tile t;
-            t.start = scratch[nb + b] + (int64_t)k * per;
-            t.count = min(per, c - k * per);
-            t.b = b;
-            tiles[scratch[b] + k] = t;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt_b[b] = rank[b + 1] - rank[b];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t32 = 0, t64 = 0;
+        for (int b = 0; b < nb; ++b) {
+            off32[b] = t32;
+            off64[b] = t64;
+            const int32_t c = rank[b + 1] - rank[b];
+            t32 += (c + per32 - 1) / per32;
+            t64 += (c + per64 - 1) / per64;
         }
+        off32[nb] = t32;
+        off64[nb] = t64;
     }
-    const int32_t used = scratch[2 * nb];
-    for (int64_t k = used + threadIdx.x; k < max_tiles; k += blockDim.x) tiles[k] = Tile{0, 0, 0};
+}
+
+// Tile k of a schedule: the boundary whose tile range holds k (binary search over off), and the
+// run of `per` list entries it covers; slots past the last tile get count 0.
+__global__ void k_fill_tiles(const int32_t* __restrict__ cnt_b, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ rank_start, int32_t nb, int32_t per,
+                             Tile* __restrict__ tiles, int64_t max_tiles) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= max_tiles) return;
+    if (k >= off[nb]) {
+        tiles[k] = Tile{0, 0, 0};
+        return;
+    }
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (off[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const int32_t j = (int32_t)(k - off[lo]);
+    Tile t;
+    t.start = (int64_t)rank_start[lo] + (int64_t)j * per;
+    t.count = min(per, cnt_b[lo] - j * per);
+    t.b = lo;
+    tiles[k] = t;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -621,8 +646,11 @@ struct SolverBufs {
     int32_t* list;
     int32_t* bsum;
     int32_t* n_active;
-    int32_t* cnt_b;
-    int32_t* scratch;
+    int32_t* cnt_b;     // [nb] active points per boundary
+    int32_t* rank;      // [nb + 1] list offset of each boundary
+    int32_t* off32;     // [nb + 1] tile offsets of the FP32C schedule
+    int32_t* off64;     // [nb + 1] tile offsets of the FP64 schedule
+    int64_t* segd;      // [nb + 1] point segments
     Tile* tiles32;
     Tile* tiles64;
     int64_t max32, max64;
@@ -665,7 +693,8 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
                  oNu = L.take<double>(n), oLph = L.take<int32_t>(n);
     const size_t oList = L.take<int32_t>(n), oBsum = L.take<int32_t>((size_t)b.nblk + 1),
                  oNact = L.take<int32_t>(1), oCnt = L.take<int32_t>((size_t)nb),
-                 oScr = L.take<int32_t>(2 * (size_t)nb + 1);
+                 oRank = L.take<int32_t>((size_t)nb + 1), oO32 = L.take<int32_t>((size_t)nb + 1),
+                 oO64 = L.take<int32_t>((size_t)nb + 1), oSeg = L.take<int64_t>((size_t)nb + 1);
     const size_t oT32 = L.take<Tile>((size_t)b.max32), oT64 = L.take<Tile>((size_t)b.max64);
     const size_t need = L.off;
     if (!S.block || S.bytes < (int64_t)need) {
@@ -693,24 +722,27 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
     b.bsum = (int32_t*)D(oBsum);
     b.n_active = (int32_t*)D(oNact);
     b.cnt_b = (int32_t*)D(oCnt);
-    b.scratch = (int32_t*)D(oScr);
+    b.rank = (int32_t*)D(oRank);
+    b.off32 = (int32_t*)D(oO32);
+    b.off64 = (int32_t*)D(oO64);
+    b.segd = (int64_t*)D(oSeg);
     b.tiles32 = (Tile*)D(oT32);
     b.tiles64 = (Tile*)D(oT64);
     return DBIE_OK;
 }
 
-static hipError_t compact(const SolverBufs& b, const int32_t* bidx, int64_t N, int32_t nb, int32_t per32,
-                          hipStream_t s) {
+static hipError_t compact(const SolverBufs& b, int64_t N, int32_t nb, int32_t per32, hipStream_t s) {
     const unsigned nblk = (unsigned)std::max<int32_t>(b.nblk, 1);
     hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, N, b.bsum);
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, b.bsum, (int32_t)nblk, b.n_active,
-                       b.cnt_b, nb);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, b.bsum, (int32_t)nblk, b.n_active);
     hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, N, b.bsum,
-                       bidx, b.list, b.cnt_b);
-    hipLaunchKernelGGL(k_build_tiles, dim3(1), dim3(256), 0, s, b.cnt_b, nb, per32, b.tiles32, b.max32,
-                       b.scratch);
-    hipLaunchKernelGGL(k_build_tiles, dim3(1), dim3(256), 0, s, b.cnt_b, nb, (int32_t)256, b.tiles64,
-                       b.max64, b.scratch);
+                       b.list);
+    hipLaunchKernelGGL(k_seg_counts, dim3(1), dim3(256), 0, s, b.C.active, N, b.bsum, b.n_active, b.segd, nb,
+                       b.cnt_b, b.rank, per32, (int32_t)256, b.off32, b.off64);
+    hipLaunchKernelGGL(k_fill_tiles, dim3((unsigned)((b.max32 + 255) / 256)), dim3(256), 0, s, b.cnt_b, b.off32,
+                       b.rank, nb, per32, b.tiles32, b.max32);
+    hipLaunchKernelGGL(k_fill_tiles, dim3((unsigned)((b.max64 + 255) / 256)), dim3(256), 0, s, b.cnt_b, b.off64,
+                       b.rank, nb, (int32_t)256, b.tiles64, b.max64);
     return hipGetLastError();
 }
 
@@ -755,7 +787,8 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
                        (int64_t)opt->max_trials + 1, 0);
     hipLaunchKernelGGL(k_solve_init, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, lam, b.C, b.nm, b.lm);
     SOLVE_HIP(hipGetLastError());
-    SOLVE_HIP(compact(b, geo.bidx, N, nb, per32, s));
+    SOLVE_HIP(hipMemcpyAsync(b.segd, ctx_seg(c), (size_t)(nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SOLVE_HIP(compact(b, N, nb, per32, s));
     EvalSet set{b.list, b.n_active, b.tiles32, b.max32, b.tiles64, b.max64};
     int32_t rounds = 0;
     const int32_t check_every = 4;
@@ -778,7 +811,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
             hipLaunchKernelGGL(k_nm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list,
                                b.n_active, rounds, b.C, b.nm);
         SOLVE_HIP(hipGetLastError());
-        SOLVE_HIP(compact(b, geo.bidx, N, nb, per32, s));
+        SOLVE_HIP(compact(b, N, nb, per32, s));
         if (solver_tracing(c)) {
             hipEvent_t e = nullptr;
             SOLVE_HIP(hipEventCreate(&e));
