@@ -63,6 +63,20 @@ def cpu_baseline(w, n_sample, seed=7):
                        f"(FP64 field + grad + mu-tangents + residuals), {dt:.2f} s wall")
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_k_field32c.json")) as fh:
+            t = json.load(fh)
+        with open(os.path.join(ROOT, "paper_1306_1122_amd", "csrc", "k_field32c.hip"), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return float(t["hbm_bytes_per_launch"]) if t.get("source_sha256") == sha else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,7 +217,8 @@ def main():
                    "tile_shape": [q["ppl"], q["waves"], q["tile_pixels"]],
                    "tile_shape_tangents": [qt["ppl"], qt["waves"], qt["tile_pixels"]]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": "k_field32c (FP32C bulk sum with mu-tangents)",
                      "flops_per_pair": FLOPS_FIELD_GRAD_TAN, "pairs_per_launch": pairs_per_launch,
                      "avg_launch_ms": kern_avg_ms, "launches": launches},
