@@ -77,12 +77,139 @@ def measured_traffic():
     return float(t["hbm_bytes_per_launch"]) if t.get("source_sha256") == sha else None
 
 
+def _timed(f, reps):
+    import torch
+    f()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s):
+    """One evaluation of B and grad B (no tangents: one Nelder-Mead trial) in FP32C and in FP64."""
+    out = {}
+    for name, prec, reps in (("fp32c_field_grad", "fp32c", 5), ("fp64_field_grad", "fp64", 2)):
+        c2 = ctx if prec == "fp32c" else D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz,
+                                                    precision=prec)
+        D.dbie_timing(c2, True)
+        ms = _timed(lambda: D.dbie_eval_field(c2, lam), reps)
+        km, kl = D.dbie_timing_read(c2)
+        D.dbie_timing(c2, False)
+        k = km / max(kl, 1)
+        out[name] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_trial=ms, bulk_kernel_ms=k,
+                         algorithmic_tflops=FLOPS_FIELD_GRAD * pairs / (k * 1e-3) / 1e12)
+        if c2 is not ctx:
+            c2.close()
+    return out
+
+
+def time_to_solution(D, dev, n_sample=65536):
+    """Plain form (FP64 Nelder-Mead, 200 trials) vs fast form (FP32C Levenberg-Marquardt, 20 trials,
+    FP64 acceptance) on a z-stratified sample of the 256x256x128 bipole grid, from lambda = 0.
+    q* = the solved fraction (max(f, g) <= 1e-4 in FP64) the plain form reaches within its budget;
+    TTS(form) = solve time until that form's solved fraction reaches q* (round-end HIP events)."""
+    import torch
+    from workloads import config3, z_stratified_subsample
+    w = config3()
+    bd = w.boundaries[0]
+    idx = z_stratified_subsample(w.xyz, n_sample, 3)
+    xyz = torch.tensor(np.ascontiguousarray(w.xyz[:, idx]), dtype=torch.float64, device=dev)
+    B0 = torch.tensor(bd.B0, dtype=torch.float64, device=dev)
+    n = xyz.shape[1]
+    res = {"workload": f"{n} z-stratified points of {w.name}", "eps": 1e-4}
+    for form, prec, meth, budget in (("plain_fp64_nelder_mead", "fp64", "nm", 200),
+                                     ("fast_fp32c_levenberg_marquardt", "fp32c", "lm", 20)):
+        ctx = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision=prec)
+        lam = torch.zeros(3, n, dtype=torch.float64, device=dev)
+        D.dbie_solve_trace(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = D.dbie_solve_lambda(ctx, lam, method=meth, max_trials=budget, eps=1e-4, fp64_accept=True,
+                                want_B=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t, cv = D.dbie_solve_trace_read(ctx)
+        st = r["status"].cpu().numpy()
+        fg = r["fg"].cpu().numpy()
+        ctx.close()
+        frac = np.cumsum(cv) / n
+        res[form] = dict(budget=budget, wall_s=wall, rounds=int(len(t)),
+                         solved_fraction=float(np.mean(st == 0)),
+                         mean_f=float(np.nanmean(fg[0])), mean_g=float(np.nanmean(fg[1])),
+                         median_rho=float(np.nanmedian(np.maximum(fg[0], fg[1]))),
+                         curve_ms=[float(v) for v in t], curve_fraction=[float(v) for v in frac])
+    q = res["plain_fp64_nelder_mead"]["solved_fraction"]
+    res["q_star"] = q
+    for form in ("plain_fp64_nelder_mead", "fast_fp32c_levenberg_marquardt"):
+        f = np.array(res[form]["curve_fraction"])
+        tms = np.array(res[form]["curve_ms"])
+        hit = np.nonzero(f >= q)[0] if q > 0 else np.array([], dtype=int)
+        res[form]["tts_ms"] = float(tms[hit[0]]) if hit.size else None
+        # keep the JSON line short: curves at 8 sample rounds
+        k = np.unique(np.linspace(0, len(tms) - 1, 8).astype(int)) if len(tms) else []
+        res[form]["curve_ms"] = [res[form]["curve_ms"][i] for i in k]
+        res[form]["curve_fraction"] = [res[form]["curve_fraction"][i] for i in k]
+    a = res["plain_fp64_nelder_mead"]["tts_ms"]
+    b = res["fast_fp32c_levenberg_marquardt"]["tts_ms"]
+    res["tts_speedup"] = (a / b) if (a and b) else None
+    return res
+
+
+def batched(D, dev):
+    """64 magnetograms of uneven size in one launch vs one launch per magnetogram (FP32C, B + grad B)."""
+    import torch
+    from workloads import config4
+    w = config4()
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    bds = [dict(B0=T(b.B0), x0=b.x0, y0=b.y0, h=b.h) for b in w.boundaries]
+    ctx = D.dbie_init(bds, T(w.xyz), seg=w.seg, precision="fp32c")
+    lam = T(w.lam)
+    pairs = w.pairs_per_trial()
+    one = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
+    ctx.close()
+    parts = []
+    for b in range(len(bds)):
+        s0, s1 = int(w.seg[b]), int(w.seg[b + 1])
+        parts.append((D.dbie_init([bds[b]], T(w.xyz[:, s0:s1]), precision="fp32c"), T(w.lam[:, s0:s1])))
+
+    def each():
+        for c, l in parts:
+            D.dbie_eval_field(c, l)
+
+    sep = _timed(each, 1)
+    return dict(points=w.n_points, pairs=pairs, one_launch_ms=one, one_launch_pairs_per_s=pairs / (one * 1e-3),
+                separate_launches_ms=sep, separate_pairs_per_s=pairs / (sep * 1e-3))
+
+
+def active_region(D, dev):
+    """512x256 active-region-like magnetogram with 2^20 points on 4096 arcs (FP32C + FP64 near field)."""
+    import torch
+    from workloads import config5
+    w = config5()
+    bd = w.boundaries[0]
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=0.0, y0=0.0, h=1.0)], T(w.xyz), precision="fp32c")
+    lam = T(w.lam)
+    pairs = w.pairs_per_trial()
+    ms = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
+    mst = _timed(lambda: D.dbie_eval_field(ctx, lam, want_tan=True), 2)
+    ctx.close()
+    return dict(points=w.n_points, pairs=pairs, field_grad_ms=ms, field_grad_pairs_per_s=pairs / (ms * 1e-3),
+                with_tangents_ms=mst, with_tangents_pairs_per_s=pairs / (mst * 1e-3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -112,7 +239,7 @@ def main():
     T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
     B0 = T(bd.B0)
     xyz = T(w.xyz)
-    ctx = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision="fp32c")
+    ctx = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision="fp32c", tune=not args.shape)
     if args.shape:
         ppl, waves, tp = (int(v) for v in args.shape.split(","))
         D.dbie_set_tile_shape(ctx, ppl, waves, tp)
@@ -158,32 +285,14 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        # the same pass without tangents (one Nelder-Mead trial) and the plain FP64 form
-        out = {}
-        for name, prec, tan in (("fp32c_field_grad", "fp32c", False), ("fp64_field_grad", "fp64", False)):
-            c2 = ctx if prec == "fp32c" else D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz,
-                                                        precision=prec)
-            reps = 5 if prec == "fp32c" else 2
-            D.dbie_eval_field(c2, lam, want_tan=tan)
-            torch.cuda.synchronize()
-            D.dbie_timing(c2, True)
-            D.dbie_timing_read(c2)
-            a0 = torch.cuda.Event(enable_timing=True)
-            a1 = torch.cuda.Event(enable_timing=True)
-            a0.record(s)
-            for _ in range(reps):
-                D.dbie_eval_field(c2, lam, want_tan=tan)
-            a1.record(s)
-            torch.cuda.synchronize()
-            km, kl = D.dbie_timing_read(c2)
-            D.dbie_timing(c2, False)
-            ms = a0.elapsed_time(a1) / reps
-            out[name] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_trial=ms,
-                             bulk_kernel_ms=km / max(kl, 1),
-                             algorithmic_tflops=FLOPS_FIELD_GRAD * pairs / (km / max(kl, 1) * 1e-3) / 1e12)
-            if c2 is not ctx:
-                c2.close()
-        extras = out
+        for name, fn in (("per_trial_rates", lambda: per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s)),
+                         ("time_to_solution", lambda: time_to_solution(D, dev)),
+                         ("batched_64_magnetograms", lambda: batched(D, dev)),
+                         ("active_region_512x256_arcs", lambda: active_region(D, dev))):
+            try:
+                extras[name] = fn()
+            except Exception as exc:  # an extra must not hide the headline line
+                extras[name] = {"error": repr(exc)}
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)

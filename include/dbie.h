@@ -106,10 +106,11 @@ typedef struct {
     double init_step;     /* simplex edge (Nelder-Mead); <= 0 means 1 / (longer side of the magnetogram) */
     double lambda_cap;    /* |lambda| <= cap; <= 0 means pi / h */
     int32_t fp64_accept;  /* FP32C contexts: re-evaluate the result in FP64 and set status from it */
+    int32_t use_graph;    /* 1: replay the rounds from a captured HIP graph (bitwise the same results) */
 } dbie_solve_opts;
 
 /* Fill defaults: FP32C, radius 2, dV/dSigma = 1/6, no tuning / Nelder-Mead, 50 trials, eps 1e-4,
- * default step and cap, FP64 acceptance on. Return DBIE_OK, or DBIE_E_INVAL for NULL. */
+ * default step and cap, FP64 acceptance on, graph replay on. Return DBIE_OK, or DBIE_E_INVAL for NULL. */
 DBIE_API int dbie_default_options(dbie_options* opt);
 DBIE_API int dbie_default_solve_opts(dbie_solve_opts* opt);
 
@@ -138,7 +139,9 @@ DBIE_API int dbie_eval_field(dbie_ctx* ctx, const double* lambda, int32_t L, dou
  * One trial is one evaluation of (B, grad B) at one lambda triple for one point. Nelder-Mead uses the
  * simplex {lambda0, lambda0 + step e_p}, coefficients 1, 2, 1/2, 1/2; a proposal outside the cap
  * costs a trial and counts as Phi = +inf. LM starts at mu = lambda0^2. The host reads one active-point
- * count per few rounds (synchronising `stream`) and returns when every point is done. */
+ * count per few rounds (synchronising `stream`) and returns when every point is done. The rounds
+ * between two reads are captured once into a HIP graph per context and configuration and replayed
+ * (not while timing or tracing is enabled). */
 DBIE_API int dbie_solve_lambda(dbie_ctx* ctx, double* lambda_inout, const dbie_solve_opts* opt,
                                double* B, double* fg, int32_t* status, int32_t* trials, void* stream);
 

@@ -19,7 +19,6 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr int kTile64 = 256;         // points per workgroup of the FP64 kernels
-constexpr int kPixPad = 512;         // FP32 pixel planes are padded to a multiple of this
 
 template <class T>
 hipError_t dalloc(T** p, size_t n) {
@@ -40,18 +39,24 @@ struct dbie_ctx {
     std::vector<int64_t> seg;
     BoundaryDev* bnd_d = nullptr;
     double* B0d = nullptr;      // FP64 planes, concatenated per boundary
-    float* pixf = nullptr;      // FP32 planes (a, b, Bx, By, Bz), padded, FP32C only
+    float* pixf = nullptr;      // FP32 pixel blocks (Bx, By, Bz planes per block), FP32C only
     double* xyz = nullptr;
     Geo geo{};
     void* geo_block = nullptr;  // one allocation holding every geometry array
+    int32_t* near_ptr = nullptr;   // adjoint near lists (FP32C): CSR by global pixel index
+    int32_t* near_pts = nullptr;
+    int32_t* pix_bnd = nullptr;
+    int64_t near_pairs = 0;
+    int32_t* perm = nullptr;    // FP32C point order (NULL = identity): per magnetogram, the points
+                                // with near-field pairs first, sorted by their window, then the rest
     Tile* tiles64 = nullptr;
     int64_t n_tiles64 = 0;
     Tile* tiles32 = nullptr;     // static schedule of the plain FP32C pass
     int64_t n_tiles32 = 0;
     Tile* tiles32t = nullptr;    // static schedule of the FP32C pass with mu-tangents
     int64_t n_tiles32t = 0;
-    F32Shape shape{2, 4, 256};
-    F32Shape shape_tan{1, 4, 256};
+    F32Shape shape{1, 8, kRows * kCols};
+    F32Shape shape_tan{1, 4, kRows * kCols};
     double* acc = nullptr;      // [L][kAcc][N]
     int64_t acc_L = 0;
     SolverState solver{};
@@ -117,6 +122,10 @@ void free_ctx(dbie_ctx* c) {
     (void)hipFree(c->pixf);
     (void)hipFree(c->xyz);
     (void)hipFree(c->geo_block);
+    (void)hipFree(c->perm);
+    (void)hipFree(c->near_ptr);
+    (void)hipFree(c->near_pts);
+    (void)hipFree(c->pix_bnd);
     (void)hipFree(c->tiles64);
     (void)hipFree(c->tiles32);
     (void)hipFree(c->tiles32t);
@@ -179,8 +188,8 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
-                                    c->pixf, c->geo, lam, c->N, L, idx, tan, tan ? c->shape_tan : c->shape,
-                                    c->acc, s));
+                                    c->pixf, c->geo, lam, c->N, L, set ? idx : c->perm, set == nullptr, tan,
+                                    tan ? c->shape_tan : c->shape, c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
         c->ev.emplace_back(e0, e1);
@@ -201,6 +210,7 @@ const Geo& ctx_geo(const dbie_ctx* c) { return c->geo; }
 const BoundaryDev* ctx_bnd(const dbie_ctx* c) { return c->bnd_d; }
 const BoundaryDev& ctx_bnd_host(const dbie_ctx* c, int b) { return c->bnd_h[b]; }
 int64_t ctx_n(const dbie_ctx* c) { return c->N; }
+const int32_t* ctx_perm(const dbie_ctx* c) { return c->perm; }
 const int64_t* ctx_seg(const dbie_ctx* c) { return c->seg.data(); }
 void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes) {
     if (slot < 0 || slot >= 4) return nullptr;
@@ -213,6 +223,10 @@ void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes) {
     return c->scratch[slot];
 }
 bool solver_tracing(const dbie_ctx* c) { return c->trace; }
+NearLists ctx_near_lists(const dbie_ctx* c) {
+    return NearLists{c->npix_total, c->near_pairs, c->near_ptr, c->near_pts, c->pix_bnd};
+}
+bool ctx_timing(const dbie_ctx* c) { return c->timing; }
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
@@ -243,6 +257,7 @@ int dbie_default_solve_opts(dbie_solve_opts* o) {
     o->init_step = 0.0;
     o->lambda_cap = 0.0;
     o->fp64_accept = 1;
+    o->use_graph = 1;
     return DBIE_OK;
 }
 
@@ -302,14 +317,16 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         d.nx = bd.nx;
         d.ny = bd.ny;
         d.npix = bd.nx * bd.ny;
-        d.npix_pad = (d.npix + kPixPad - 1) / kPixPad * kPixPad;
+        d.ntx = (bd.nx + kCols - 1) / kCols;
+        d.nty = (bd.ny + kRows - 1) / kRows;
+        d.npix_pad = d.ntx * d.nty * kRows * kCols;
         d.pix_off = off;
         d.pixf_off = offf;
         d.x0 = bd.x0;
         d.y0 = bd.y0;
         d.h = bd.h;
         off += 3 * (int64_t)d.npix;
-        offf += 5 * (int64_t)d.npix_pad;
+        offf += 3 * (int64_t)d.npix_pad;
         c->bnd_h.push_back(d);
     }
     c->npix_total = off / 3;
@@ -380,6 +397,59 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     (void)hipFree(bad);
     if (bad_h) return bail(fail(c, DBIE_E_INVAL, "a point has z <= 0, a non-finite coordinate, or lies "
                                                  "more than 4e6 pixels away"));
+    if (o.precision == DBIE_FP32C && r > 0.0 && N > 0) {
+        // Points with near-field pairs take the masked loop of the FP32C kernel for the pixel tiles
+        // their window touches; grouping them (sorted by window) keeps that loop to few wavefronts.
+        std::vector<uint32_t> mask(N);
+        std::vector<int32_t> wa(N), wb(N);
+        DBIE_INIT_HIP(hipMemcpy(mask.data(), c->geo.near_mask, N * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        DBIE_INIT_HIP(hipMemcpy(wa.data(), c->geo.win_a, N * sizeof(int32_t), hipMemcpyDeviceToHost));
+        DBIE_INIT_HIP(hipMemcpy(wb.data(), c->geo.win_b, N * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<int32_t> perm;
+        perm.reserve(N);
+        bool identity = true;
+        for (int32_t b = 0; b < nb; ++b) {
+            std::vector<int32_t> low, high;
+            for (int64_t i = seg[b]; i < seg[b + 1]; ++i) (mask[i] ? low : high).push_back((int32_t)i);
+            std::stable_sort(low.begin(), low.end(), [&](int32_t x, int32_t y) {
+                return wb[x] != wb[y] ? wb[x] < wb[y] : wa[x] < wa[y];
+            });
+            for (int32_t i : low) perm.push_back(i);
+            for (int32_t i : high) perm.push_back(i);
+        }
+        for (int64_t k = 0; k < N && identity; ++k) identity = perm[k] == (int32_t)k;
+        if (!identity) {
+            DBIE_INIT_HIP(dalloc(&c->perm, (size_t)N));
+            DBIE_INIT_HIP(hipMemcpy(c->perm, perm.data(), N * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
+        // the near pairs by pixel for the adjoint (counting sort by pixel; points ascending)
+        const int64_t P = c->npix_total;
+        std::vector<int32_t> ptr(P + 1, 0), pixb(P);
+        for (int32_t b = 0; b < nb; ++b)
+            for (int64_t k = 0; k < c->bnd_h[b].npix; ++k) pixb[c->bnd_h[b].pix_off / 3 + k] = b;
+        auto pair_pixel = [&](int64_t i, int bit) -> int64_t {
+            int32_t b = 0;
+            while (!(i >= seg[b] && i < seg[b + 1])) ++b;
+            const BoundaryDev& bd = c->bnd_h[b];
+            const int32_t pa = wa[i] + bit % kNearSide - kNearWin, pb = wb[i] + bit / kNearSide - kNearWin;
+            return bd.pix_off / 3 + (int64_t)pb * bd.nx + pa;
+        };
+        for (int64_t i = 0; i < N; ++i)
+            for (uint32_t m = mask[i]; m; m &= m - 1u) ++ptr[pair_pixel(i, __builtin_ctz(m)) + 1];
+        for (int64_t g = 0; g < P; ++g) ptr[g + 1] += ptr[g];
+        c->near_pairs = ptr[P];
+        if (c->near_pairs > 0) {
+            std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1), pts(c->near_pairs);
+            for (int64_t i = 0; i < N; ++i)
+                for (uint32_t m = mask[i]; m; m &= m - 1u) pts[fill[pair_pixel(i, __builtin_ctz(m))]++] = (int32_t)i;
+            DBIE_INIT_HIP(dalloc(&c->near_ptr, (size_t)P + 1));
+            DBIE_INIT_HIP(dalloc(&c->near_pts, (size_t)c->near_pairs));
+            DBIE_INIT_HIP(dalloc(&c->pix_bnd, (size_t)P));
+            DBIE_INIT_HIP(hipMemcpy(c->near_ptr, ptr.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+            DBIE_INIT_HIP(hipMemcpy(c->near_pts, pts.data(), c->near_pairs * sizeof(int32_t), hipMemcpyHostToDevice));
+            DBIE_INIT_HIP(hipMemcpy(c->pix_bnd, pixb.data(), P * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
+    }
     if (o.precision == DBIE_FP32C && o.tune) {
         rc = tune_shapes(c, opt ? opt->tune_cache : nullptr, s);
         if (rc) return bail(rc);

@@ -25,13 +25,16 @@ constexpr int kAccTan = 9;      // rows 12 + 3p + j: T0, T1, T2 of component p
 constexpr int kAcc = kAccField + kAccTan;
 constexpr int kNearWin = 2;     // near-field window half-width in pixels (radius <= 2 h)
 constexpr int kNearSide = 2 * kNearWin + 1;
+constexpr int kRows = 32;       // FP32C pixel block: kRows x kCols pixels, tile-major in HBM
+constexpr int kCols = 8;
 
 struct BoundaryDev {
     int32_t nx, ny;
     int32_t npix;       // nx * ny
-    int32_t npix_pad;   // FP32 planes padded to a multiple of the largest pixel tile
+    int32_t ntx, nty;   // FP32C pixel blocks along x and y (ceil(nx / kCols), ceil(ny / kRows))
+    int32_t npix_pad;   // ntx * nty * kRows * kCols
     int64_t pix_off;    // offset of this boundary in the FP64 planes (3 planes of npix each)
-    int64_t pixf_off;   // offset of this boundary in the FP32 planes (5 planes of npix_pad each)
+    int64_t pixf_off;   // offset of this boundary in the FP32 blocks (3 * npix_pad floats)
     double x0, y0, h;
 };
 
@@ -193,9 +196,11 @@ struct F32Shape {
     int32_t tp;      // pixels per LDS tile
 };
 
+// remap_xcd: deal contiguous runs of the schedule to the 8 XCDs (static schedules).
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, bool tan, F32Shape shape, double* acc, hipStream_t s);
+                           const int32_t* idx, bool remap_xcd, bool tan, F32Shape shape, double* acc,
+                           hipStream_t s);
 bool field32c_shape_supported(F32Shape shape);
 int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number
 

@@ -9,8 +9,19 @@
 
 namespace dbie {
 
+// What a captured solver graph depends on (compared bytewise before a replay).
+struct GraphKey {
+    int32_t method, max_trials, fp64, per32;
+    double eps, step, cap;
+    void* block;
+    hipStream_t stream;
+    const int32_t* perm;
+};
+
 // Device buffers owned by a context for dbie_solve_lambda (allocated on first use, grown on need).
 struct SolverState {
+    hipGraphExec_t exec = nullptr;   // captured rounds, replayed while `key` matches
+    GraphKey key{};
     void* block = nullptr;       // one allocation for every per-point solver array
     int64_t bytes = 0;
     int32_t* count_h = nullptr;  // pinned host word: active-point count
@@ -31,6 +42,9 @@ struct EvalSet {
     int64_t n_tiles64;
 };
 
+// Make sure the accumulator workspace holds L trials (allocates; never called during capture).
+int ensure_acc(dbie_ctx* c, int64_t L);
+
 // One lambda trial (L = 1) through the bulk kernel and the finalize pass.
 int eval_set(dbie_ctx* c, const double* lam, bool fp64, bool tan, const EvalSet* set, double* B, double* dB,
              double* fg, double* tn, hipStream_t s);
@@ -40,6 +54,7 @@ const Geo& ctx_geo(const dbie_ctx* c);
 const BoundaryDev* ctx_bnd(const dbie_ctx* c);
 const BoundaryDev& ctx_bnd_host(const dbie_ctx* c, int b);
 int64_t ctx_n(const dbie_ctx* c);
+const int32_t* ctx_perm(const dbie_ctx* c);   // FP32C point order or NULL (identity)
 int32_t ctx_nb(const dbie_ctx* c);
 const int64_t* ctx_seg(const dbie_ctx* c);
 const double* ctx_B0d(const dbie_ctx* c);
@@ -49,7 +64,17 @@ SolverState& ctx_solver(dbie_ctx* c);
 int ctx_fail(dbie_ctx* c, int code, const char* msg);
 // Library-owned scratch block `slot` of at least `bytes` (grown on need); NULL on failure.
 void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes);
+// Near-field pairs grouped by pixel (global pixel index over all magnetograms), for the adjoint.
+struct NearLists {
+    int64_t npix_total;
+    int64_t n_pairs;
+    const int32_t* ptr;      // [npix_total + 1]
+    const int32_t* pts;      // [n_pairs] point indices, ascending per pixel
+    const int32_t* pix_bnd;  // [npix_total] magnetogram of each pixel
+};
+NearLists ctx_near_lists(const dbie_ctx* c);
 bool solver_tracing(const dbie_ctx* c);
+bool ctx_timing(const dbie_ctx* c);
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c);
 // FP32C tile shapes: one for the plain field pass and one for the pass with mu-tangents.
 int set_shape(dbie_ctx* c, F32Shape s, bool tan);

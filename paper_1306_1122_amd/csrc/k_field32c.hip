@@ -1,22 +1,24 @@
 // FP32 bulk kernel sum with compensated accumulation (the FP32C path).
 //
-// Work decomposition: one workgroup per schedule tile (<= PPL * 64 * WAVES consecutive points of one
-// magnetogram) and one grid row per lambda trial. Lane l of the workgroup owns points l, l + NT,
-// ..., so a wavefront holds 64 consecutive points (spatially coherent). The magnetogram streams
-// through LDS in tiles of TP pixels (five planes: a, b, Bx, By, Bz); every lane reads the same
-// address (broadcast), four pixels per ds_read_b128.
+// Work decomposition: one workgroup per schedule tile (<= PPL * 64 * WAVES points of one
+// magnetogram) and one grid row per lambda trial. Lane l of the workgroup owns points l, l + NT, ...
+// of the tile, so a wavefront holds 64 consecutive points (the library orders points so that these
+// are spatially coherent). The magnetogram streams through LDS in blocks of kRows x kCols pixels
+// (three planes Bx, By, Bz, tile-major in HBM); every lane reads the same LDS address (broadcast).
 //
-// Arithmetic per pair, all FP32:
-//   dx = (a_k - floor(u)) - frac(u)    (the integer difference is exact: one rounding in total)
-//   rho^-1 = rsq(dx^2 + dy^2 + w^2), and per component t = Lambda rho, sin/cos in revolutions
-//   (range-reduced by fract only when a workgroup's |Lambda| rho / 2pi can exceed the hardware's
-//   accurate range of 256 revolutions), N = t sin t + cos t, H = t (t cos t) - 3 N, and the sums
-//   A0 += N rho^-3 B0,  A1 += H rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += H rho^-3 B0 rho^-2.
-// Compensation: each pixel tile is summed in FP32 (error ~ TP u), and the tile partials are added
-// into FP64 totals, so the error does not grow with the magnetogram size.
+// Arithmetic per pair, all FP32. For each block and point the kCols column offsets
+//   dx_c = (a0 + c - floor(u)) - frac(u)           (exact integer difference, one rounding)
+// are kept in registers; for each row dy = (b0 + r - floor(v)) - frac(v) and q = dy^2 + w^2; then
+//   rho^2 = dx_c^2 + q, rho^-1 = rsq(rho^2), and per component t = Lambda rho, sin/cos in
+//   revolutions (range-reduced by fract only when a wavefront's |Lambda| rho / 2pi can exceed the
+//   hardware's accurate range of 256 revolutions), N = t sin t + cos t, H = t (t cos t) - 3 N,
+//   A0 += N rho^-3 B0,  A1 += H rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += H rho^-3 B0 rho^-2
+//   (and with tangents T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy).
+// Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
+// FP64 totals, so the error does not grow with the magnetogram size.
 // Near field: pairs whose (FP64-classified) distance is below the near radius are skipped here and
-// summed in FP64 by the finalize pass. Tiles that cannot contain such a pair for any point of the
-// workgroup take the unmasked loop; the test is uniform over the workgroup.
+// summed in FP64 by the finalize pass. Blocks that cannot contain such a pair for any point of the
+// wavefront take the unmasked loop; the test is uniform over the wavefront.
 #include <climits>
 
 #include "dbie_internal.h"
@@ -32,68 +34,86 @@ struct PointState {
     uint32_t msk[PPL];
 };
 
+// One pair given dx, dy (pixels), q = dy^2 + w^2 and the field of the pixel.
+template <bool TAN, bool FRACT>
+__device__ __forceinline__ void pair32(float dx, float dy, float q, const float lt[3], const float lr[3],
+                                       float bx, float by, float bz, float* acc) {
+    const float r2 = fmaf(dx, dx, q);
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float dxr = dx * ri2;
+    const float dyr = dy * ri2;
+    const float b0[3] = {bx, by, bz};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        // v_sin / v_cos take revolutions and are accurate on [-256, 256]; FRACT reduces first
+        const float tr = FRACT ? __builtin_amdgcn_fractf(lr[p] * r) : lr[p] * r;
+        const float sn = __builtin_amdgcn_sinf(tr);
+        const float cs = __builtin_amdgcn_cosf(tr);
+        const float t = lt[p] * r;
+        const float n = fmaf(t, sn, cs);
+        const float hh = fmaf(t, t * cs, -3.0f * n);
+        const float b3 = ri3 * b0[p];
+        const float hb = hh * b3;
+        if (TAN) {
+            const float nb = n * b3;
+            acc[4 * p + 0] += nb;
+            acc[12 + 3 * p + 0] = fmaf(cs, ri * b0[p], acc[12 + 3 * p + 0]);
+            acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
+            acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
+        } else {
+            acc[4 * p + 0] = fmaf(n, b3, acc[4 * p + 0]);
+        }
+        acc[4 * p + 1] = fmaf(hb, dxr, acc[4 * p + 1]);
+        acc[4 * p + 2] = fmaf(hb, dyr, acc[4 * p + 2]);
+        acc[4 * p + 3] = fmaf(hb, ri2, acc[4 * p + 3]);
+    }
+}
+
+// One block of kRows x kCols pixels with origin (a0, b0) and `rows` valid rows, for all PPL points.
 template <int PPL, bool TAN, bool SLOW, bool FRACT>
-__device__ __forceinline__ void pixel_step(const PointState<PPL, TAN>& S, float a, float b, float bx,
-                                           float by, float bz, float (&acc)[PPL][TAN ? kAcc : kAccField]) {
+__device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
+                                           const float4 (*sB)[kRows][kCols / 4], float a0, float b0,
+                                           int rows, float (&part)[PPL][TAN ? kAcc : kAccField]) {
+    static_assert(kCols == 8, "the row body reads two float4 per plane");
+    float dxc[PPL][kCols];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-        const float dx = (a + S.xn[j]) - S.xf[j];
-        const float dy = (b + S.yn[j]) - S.yf[j];
-        float b0[3] = {bx, by, bz};
-        if (SLOW) {
-            const float da = a - S.fa[j], db = b - S.fb[j];
-            const bool in = fabsf(da) <= (float)kNearWin && fabsf(db) <= (float)kNearWin;
-            const int bit = in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
-            const bool nr = in && ((S.msk[j] >> bit) & 1u);
-            if (nr) b0[0] = b0[1] = b0[2] = 0.0f;
-        }
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, S.w2[j]));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float r = r2 * ri;
-        const float ri2 = ri * ri;
-        const float ri3 = ri2 * ri;
-        const float dxr = dx * ri2;
-        const float dyr = dy * ri2;
+        const float base = a0 + S.xn[j];   // exact: integers
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            // v_sin / v_cos take revolutions and are accurate on [-256, 256]; FRACT reduces first
-            const float tr = FRACT ? __builtin_amdgcn_fractf(S.lr[j][p] * r) : S.lr[j][p] * r;
-            const float sn = __builtin_amdgcn_sinf(tr);
-            const float cs = __builtin_amdgcn_cosf(tr);
-            const float t = S.lt[j][p] * r;
-            const float n = fmaf(t, sn, cs);
-            const float hh = fmaf(t, t * cs, -3.0f * n);
-            const float b3 = ri3 * b0[p];
-            const float hb = hh * b3;
-            if (TAN) {
-                const float nb = n * b3;
-                acc[j][4 * p + 0] += nb;
-                acc[j][12 + 3 * p + 0] = fmaf(cs, ri * b0[p], acc[j][12 + 3 * p + 0]);
-                acc[j][12 + 3 * p + 1] = fmaf(nb, dx, acc[j][12 + 3 * p + 1]);
-                acc[j][12 + 3 * p + 2] = fmaf(nb, dy, acc[j][12 + 3 * p + 2]);
-            } else {
-                acc[j][4 * p + 0] = fmaf(n, b3, acc[j][4 * p + 0]);
+        for (int c = 0; c < kCols; ++c) dxc[j][c] = (base + (float)c) - S.xf[j];
+    }
+    for (int r = 0; r < rows; ++r) {
+        const float4 X0 = sB[0][r][0], X1 = sB[0][r][1];
+        const float4 Y0 = sB[1][r][0], Y1 = sB[1][r][1];
+        const float4 Z0 = sB[2][r][0], Z1 = sB[2][r][1];
+        const float bxs[kCols] = {X0.x, X0.y, X0.z, X0.w, X1.x, X1.y, X1.z, X1.w};
+        const float bys[kCols] = {Y0.x, Y0.y, Y0.z, Y0.w, Y1.x, Y1.y, Y1.z, Y1.w};
+        const float bzs[kCols] = {Z0.x, Z0.y, Z0.z, Z0.w, Z1.x, Z1.y, Z1.z, Z1.w};
+        const float brow = b0 + (float)r;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            const float dy = (brow + S.yn[j]) - S.yf[j];
+            const float q = fmaf(dy, dy, S.w2[j]);
+#pragma unroll
+            for (int c = 0; c < kCols; ++c) {
+                float bx = bxs[c], by = bys[c], bz = bzs[c];
+                if (SLOW) {
+                    const float da = (a0 + (float)c) - S.fa[j], db = brow - S.fb[j];
+                    const bool in = fabsf(da) <= (float)kNearWin && fabsf(db) <= (float)kNearWin;
+                    const int bit =
+                        in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
+                    if (in && ((S.msk[j] >> bit) & 1u)) bx = by = bz = 0.0f;
+                }
+                pair32<TAN, FRACT>(dxc[j][c], dy, q, S.lt[j], S.lr[j], bx, by, bz, part[j]);
             }
-            acc[j][4 * p + 1] = fmaf(hb, dxr, acc[j][4 * p + 1]);
-            acc[j][4 * p + 2] = fmaf(hb, dyr, acc[j][4 * p + 2]);
-            acc[j][4 * p + 3] = fmaf(hb, ri2, acc[j][4 * p + 3]);
         }
     }
 }
 
-template <int PPL, int TP, bool TAN, bool SLOW, bool FRACT>
-__device__ __forceinline__ void tile_loop(const PointState<PPL, TAN>& S, const float4 (*s4)[TP / 4],
-                                          float (&part)[PPL][TAN ? kAcc : kAccField]) {
-    for (int q = 0; q < TP / 4; ++q) {
-        const float4 A = s4[0][q], Bq = s4[1][q], X = s4[2][q], Y = s4[3][q], Z = s4[4][q];
-        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.x, Bq.x, X.x, Y.x, Z.x, part);
-        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.y, Bq.y, X.y, Y.y, Z.y, part);
-        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.z, Bq.z, X.z, Y.z, Z.z, part);
-        pixel_step<PPL, TAN, SLOW, FRACT>(S, A.w, Bq.w, X.w, Y.w, Z.w, part);
-    }
-}
-
-template <int PPL, int WAVES, int TP, bool TAN>
+template <int PPL, int WAVES, bool TAN>
 __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
                                                          const BoundaryDev* __restrict__ bnd,
@@ -103,10 +123,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
                                                          double* __restrict__ acc) {
     constexpr int NT = 64 * WAVES;
     constexpr int NA = TAN ? kAcc : kAccField;
-    constexpr int TQ = TP / 4;
-    __shared__ float4 s4[5][TQ];
-    __shared__ int box[4];
-    __shared__ float rev_max;   // bound of |Lambda| r / 2pi over the workgroup's pairs
+    constexpr int BQ = kRows * kCols / 4;   // float4 per plane of a block
+    __shared__ float4 sB[3][kRows][kCols / 4];
 
     // XCD-aware order (static schedules): workgroups are dealt round-robin to the 8 XCDs; give each
     // XCD a contiguous run of the schedule so that its L2 sees few magnetograms. Schedules are padded
@@ -120,15 +138,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     const BoundaryDev bd = bnd[t.b];
     const int tid = threadIdx.x;
 
-    if (tid == 0) {
-        box[0] = INT_MAX;
-        box[1] = INT_MIN;
-        box[2] = INT_MAX;
-        box[3] = INT_MIN;
-        rev_max = 0.0f;
-    }
-    __syncthreads();
-
+    // per-wavefront bounds: the box of the near-field windows of its points and the largest
+    // |Lambda| r / 2pi of its pairs
+    int amin = INT_MAX, amax = INT_MIN, bmin = INT_MAX, bmax = INT_MIN;
+    float rv_w = 0.0f;
     PointState<PPL, TAN> S;
     bool live[PPL];
     int64_t pid[PPL];
@@ -156,27 +169,31 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
         S.fb[j] = (float)wb;
         S.msk[j] = live[j] ? geo.near_mask[i] : 0u;
         {
-            // farthest pixel centre of the magnetogram from this point
+            // farthest pixel centre of the (column-padded) magnetogram from this point
             const float uf = -S.xn[j] + S.xf[j], vf = -S.yn[j] + S.yf[j];
-            const float dxm = fmaxf(fabsf(uf), fabsf((float)(bd.nx - 1) - uf)) + 1.0f;
+            const float dxm = fmaxf(fabsf(uf), fabsf((float)(bd.ntx * kCols - 1) - uf)) + 1.0f;
             const float dym = fmaxf(fabsf(vf), fabsf((float)(bd.ny - 1) - vf)) + 1.0f;
             const float rmax = sqrtf(dxm * dxm + dym * dym + S.w2[j]);
             const float lmax = fmaxf(fabsf(S.lr[j][0]), fmaxf(fabsf(S.lr[j][1]), fabsf(S.lr[j][2])));
             const float rv = live[j] ? lmax * rmax : 0.0f;
-            // non-negative floats order like their bit patterns; NaN (bits above +inf) forces FRACT
-            atomicMax(reinterpret_cast<int*>(&rev_max), __float_as_int(rv));
+            rv_w = (rv == rv) ? fmaxf(rv_w, rv) : __builtin_inff();   // NaN lambda forces FRACT
         }
         if (S.msk[j]) {
-            atomicMin(&box[0], wa - kNearWin);
-            atomicMax(&box[1], wa + kNearWin);
-            atomicMin(&box[2], wb - kNearWin);
-            atomicMax(&box[3], wb + kNearWin);
+            amin = min(amin, wa - kNearWin);
+            amax = max(amax, wa + kNearWin);
+            bmin = min(bmin, wb - kNearWin);
+            bmax = max(bmax, wb + kNearWin);
         }
     }
-    __syncthreads();
-    const int amin = box[0], amax = box[1], bmin = box[2], bmax = box[3];
+    for (int off = 32; off > 0; off >>= 1) {
+        amin = min(amin, __shfl_xor(amin, off, 64));
+        amax = max(amax, __shfl_xor(amax, off, 64));
+        bmin = min(bmin, __shfl_xor(bmin, off, 64));
+        bmax = max(bmax, __shfl_xor(bmax, off, 64));
+        rv_w = fmaxf(rv_w, __shfl_xor(rv_w, off, 64));
+    }
     const bool any_near = amin <= amax;
-    const bool need_fract = !(rev_max < 255.0f);
+    const bool need_fract = !(rv_w < 255.0f);
 
     double tot[PPL][NA];
     float part[PPL][NA];
@@ -185,34 +202,31 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
 #pragma unroll
         for (int r = 0; r < NA; ++r) tot[j][r] = 0.0;
 
-    const float* P = pixf + bd.pixf_off;
-    const int64_t PP = bd.npix_pad;
-    const int npix = bd.npix, nx = bd.nx;
-    for (int k0 = 0; k0 < npix; k0 += TP) {
+    const float4* P = reinterpret_cast<const float4*>(pixf + bd.pixf_off);
+    const int nblk = bd.ntx * bd.nty;
+    for (int k = 0; k < nblk; ++k) {
+        const int ty = k / bd.ntx, tx = k - ty * bd.ntx;
+        const int a0 = tx * kCols, b0 = ty * kRows;
+        const int rows = min(kRows, bd.ny - b0);
         __syncthreads();
-        for (int q = tid; q < 5 * TQ; q += NT) {
-            const int pl = q / TQ, o = q - pl * TQ;
-            s4[pl][o] = reinterpret_cast<const float4*>(P + pl * PP + k0)[o];
+        for (int q = tid; q < 3 * BQ; q += NT) {
+            const int pl = q / BQ, o = q - pl * BQ;
+            sB[pl][o / (kCols / 4)][o % (kCols / 4)] = P[(int64_t)k * 3 * BQ + q];
         }
         __syncthreads();
         bool slow = false;
-        if (any_near) {
-            const int klast = min(k0 + TP, npix) - 1;
-            const int r0 = k0 / nx, r1 = klast / nx;
-            const int c0 = (r0 == r1) ? k0 - r0 * nx : 0;
-            const int c1 = (r0 == r1) ? klast - r1 * nx : nx - 1;
-            slow = !(r1 < bmin || r0 > bmax || c1 < amin || c0 > amax);
-        }
+        if (any_near) slow = !(b0 + rows - 1 < bmin || b0 > bmax || a0 + kCols - 1 < amin || a0 > amax);
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
 #pragma unroll
             for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
+        const float fa0 = (float)a0, fb0 = (float)b0;
         if (!slow) {
-            if (need_fract) tile_loop<PPL, TP, TAN, false, true>(S, s4, part);
-            else tile_loop<PPL, TP, TAN, false, false>(S, s4, part);
+            if (need_fract) block_loop<PPL, TAN, false, true>(S, sB, fa0, fb0, rows, part);
+            else block_loop<PPL, TAN, false, false>(S, sB, fa0, fb0, rows, part);
         } else {
-            if (need_fract) tile_loop<PPL, TP, TAN, true, true>(S, s4, part);
-            else tile_loop<PPL, TP, TAN, true, false>(S, s4, part);
+            if (need_fract) block_loop<PPL, TAN, true, true>(S, sB, fa0, fb0, rows, part);
+            else block_loop<PPL, TAN, true, false>(S, sB, fa0, fb0, rows, part);
         }
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
@@ -227,19 +241,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     }
 }
 
-// The instantiated shapes (points per lane, waves per workgroup, pixels per LDS tile).
+// The instantiated shapes (points per lane, waves per workgroup); the pixel block is kRows x kCols.
+// (shapes whose tangent variant would spill registers to scratch are left out)
 #define DBIE_F32_SHAPES(X) \
-    X(1, 4, 256)           \
-    X(2, 4, 256)           \
-    X(4, 4, 256)           \
-    X(2, 4, 128)           \
-    X(2, 8, 256)           \
-    X(1, 8, 256)
+    X(1, 2)                \
+    X(1, 4)                \
+    X(1, 8)                \
+    X(2, 4)
 
 int field32c_shapes(F32Shape* out, int max) {
     int n = 0;
-#define DBIE_LIST(P, W, T) \
-    if (n < max) out[n] = F32Shape{P, W, T}; \
+#define DBIE_LIST(P, W)                                  \
+    if (n < max) out[n] = F32Shape{P, W, kRows * kCols}; \
     ++n;
     DBIE_F32_SHAPES(DBIE_LIST)
 #undef DBIE_LIST
@@ -247,8 +260,8 @@ int field32c_shapes(F32Shape* out, int max) {
 }
 
 bool field32c_shape_supported(F32Shape s) {
-#define DBIE_CHK(P, W, T) \
-    if (s.ppl == P && s.waves == W && s.tp == T) return true;
+#define DBIE_CHK(P, W) \
+    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) return true;
     DBIE_F32_SHAPES(DBIE_CHK)
 #undef DBIE_CHK
     return false;
@@ -256,19 +269,20 @@ bool field32c_shape_supported(F32Shape s) {
 
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, bool tan, F32Shape s, double* acc, hipStream_t st) {
-    const int remap = idx ? 0 : 1;
+                           const int32_t* idx, bool remap_xcd, bool tan, F32Shape s, double* acc,
+                           hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
+    const int remap = remap_xcd ? 1 : 0;
     const dim3 grid((unsigned)n_tiles, (unsigned)L);
-#define DBIE_LAUNCH(P, W, T)                                                                           \
-    if (s.ppl == P && s.waves == W && s.tp == T) {                                                     \
-        if (tan)                                                                                       \
-            hipLaunchKernelGGL((k_field32c<P, W, T, true>), grid, dim3(64 * W), 0, st, tiles, n_tiles, \
-                               bnd, pixf, geo, lam, N, idx, remap, acc);                                           \
-        else                                                                                           \
-            hipLaunchKernelGGL((k_field32c<P, W, T, false>), grid, dim3(64 * W), 0, st, tiles,         \
-                               n_tiles, bnd, pixf, geo, lam, N, idx, remap, acc);                                  \
-        return hipGetLastError();                                                                      \
+#define DBIE_LAUNCH(P, W)                                                                            \
+    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {                                       \
+        if (tan)                                                                                     \
+            hipLaunchKernelGGL((k_field32c<P, W, true>), grid, dim3(64 * W), 0, st, tiles, n_tiles,  \
+                               bnd, pixf, geo, lam, N, idx, remap, acc);                             \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_field32c<P, W, false>), grid, dim3(64 * W), 0, st, tiles, n_tiles, \
+                               bnd, pixf, geo, lam, N, idx, remap, acc);                             \
+        return hipGetLastError();                                                                    \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)
 #undef DBIE_LAUNCH

@@ -53,28 +53,21 @@ __global__ void k_prep_points(const Tile* __restrict__ tiles, const BoundaryDev*
     }
 }
 
-// FP32 pixel planes of one boundary: a, b (pixel indices as exact floats), Bx, By, Bz, each padded
-// to npix_pad with zero field placed on pixel (0, 0): zero terms at a distance inside the range the
-// bulk kernel's bound on the sin/cos argument covers.
+// FP32 pixel blocks of one boundary: block k = (ty, tx) holds three planes (Bx, By, Bz) of
+// kRows x kCols floats for pixels (tx kCols + c, ty kRows + r); pixels beyond the magnetogram hold zero.
 __global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, float* __restrict__ pixf) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= bd.npix_pad) return;
-    float* base = pixf + bd.pixf_off;
-    const int64_t P = bd.npix_pad;
-    if (k < bd.npix) {
-        const int32_t a = (int32_t)(k % bd.nx), b = (int32_t)(k / bd.nx);
-        base[k] = (float)a;
-        base[P + k] = (float)b;
-        base[2 * P + k] = (float)B0d[bd.pix_off + k];
-        base[3 * P + k] = (float)B0d[bd.pix_off + bd.npix + k];
-        base[4 * P + k] = (float)B0d[bd.pix_off + 2 * (int64_t)bd.npix + k];
-    } else {
-        base[k] = 0.0f;
-        base[P + k] = 0.0f;
-        base[2 * P + k] = 0.0f;
-        base[3 * P + k] = 0.0f;
-        base[4 * P + k] = 0.0f;
-    }
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int BP = kRows * kCols;
+    if (e >= 3 * (int64_t)bd.npix_pad) return;
+    const int64_t k = e / (3 * BP);
+    const int rem = (int)(e - k * 3 * BP);
+    const int pl = rem / BP, o = rem - pl * BP;
+    const int r = o / kCols, c = o - r * kCols;
+    const int ty = (int)(k / bd.ntx), tx = (int)(k - (int64_t)ty * bd.ntx);
+    const int a = tx * kCols + c, b = ty * kRows + r;
+    float v = 0.0f;
+    if (a < bd.nx && b < bd.ny) v = (float)B0d[bd.pix_off + (int64_t)pl * bd.npix + (int64_t)b * bd.nx + a];
+    pixf[bd.pixf_off + e] = v;
 }
 
 hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
@@ -89,7 +82,7 @@ hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bn
     }
     if (!fp64_only) {
         for (int32_t b = 0; b < nb; ++b) {
-            const int64_t P = bnd_host[b].npix_pad;
+            const int64_t P = 3 * (int64_t)bnd_host[b].npix_pad;
             hipLaunchKernelGGL(k_fill_pixf, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
                                bnd_host[b], B0d, pixf);
             hipError_t e = hipGetLastError();

@@ -17,6 +17,7 @@
 //    vector u = (J x B / (|J||B|), sign(div B) g) from the mu-tangents, Marquardt scaling, nu /= 10 on
 //    acceptance (Phi falls) and nu *= 10 on rejection, projection into [0, cap^2].
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "dbie_solver.h"
@@ -31,14 +32,19 @@ constexpr int32_t kNoEval = -1;
 // ------------------------------------------------------------------------------------------------
 // stable compaction of the active flags into a sorted index list + device tile schedules
 // ------------------------------------------------------------------------------------------------
-__global__ void k_compact_count(const int32_t* __restrict__ active, int64_t N, int32_t* __restrict__ bsum) {
+// The active flags are read in the order `perm` (NULL = identity): list entries keep that order, so
+// the device schedules inherit the grouping of the points with near-field pairs.
+__device__ __forceinline__ int64_t at_pos(const int32_t* perm, int64_t k) { return perm ? (int64_t)perm[k] : k; }
+
+__global__ void k_compact_count(const int32_t* __restrict__ active, const int32_t* __restrict__ perm, int64_t N,
+                                int32_t* __restrict__ bsum) {
     __shared__ int32_t wsum[kCompactThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kCompactBlock;
     int32_t c = 0;
 #pragma unroll
     for (int k = 0; k < kCompactItems; ++k) {
         const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
-        c += (i < N && active[i]) ? 1 : 0;
+        c += (i < N && active[at_pos(perm, i)]) ? 1 : 0;
     }
     // wave reduction (DPP / swizzle under the hood)
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
@@ -76,8 +82,8 @@ __global__ void k_compact_scan(int32_t* __restrict__ bsum, int32_t nblk, int32_t
     if (tid == 1023) *total = part[1023];
 }
 
-__global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
-                                  const int32_t* __restrict__ boff, int32_t* __restrict__ list) {
+__global__ void k_compact_scatter(const int32_t* __restrict__ active, const int32_t* __restrict__ perm,
+                                  int64_t N, const int32_t* __restrict__ boff, int32_t* __restrict__ list) {
     __shared__ int32_t wcnt[kCompactItems][kCompactThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kCompactBlock;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -86,7 +92,7 @@ __global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
 #pragma unroll
     for (int k = 0; k < kCompactItems; ++k) {
         const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
-        fl[k] = i < N && active[i];
+        fl[k] = i < N && active[at_pos(perm, i)];
         const uint64_t m = __ballot(fl[k]);
         rk[k] = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
         if (lane == 0) wcnt[k][wv] = __popcll(m);
@@ -99,7 +105,7 @@ __global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
         for (int w = 0; w < wv; ++w) before += wcnt[k][w];
         if (fl[k]) {
             const int64_t i = base + (int64_t)k * kCompactThreads + threadIdx.x;
-            list[before + rk[k]] = (int32_t)i;
+            list[before + rk[k]] = (int32_t)at_pos(perm, i);
         }
         for (int w = 0; w < kCompactThreads / 64; ++w) run += wcnt[k][w];
     }
@@ -108,7 +114,8 @@ __global__ void k_compact_scatter(const int32_t* __restrict__ active, int64_t N,
 // Active points of each boundary from the ranks at its segment ends (rank(s) = active points with
 // index < s = block prefix + the active flags of the block before s), then the tile offsets of both
 // schedules. One workgroup; thread b handles segment start b.
-__global__ void k_seg_counts(const int32_t* __restrict__ active, int64_t N, const int32_t* __restrict__ boff,
+__global__ void k_seg_counts(const int32_t* __restrict__ active, const int32_t* __restrict__ perm, int64_t N,
+                             const int32_t* __restrict__ boff,
                              const int32_t* __restrict__ total, const int64_t* __restrict__ seg, int32_t nb,
                              int32_t* __restrict__ cnt_b, int32_t* __restrict__ rank, int32_t per32,
                              int32_t per64, int32_t* __restrict__ off32, int32_t* __restrict__ off64) {
@@ -120,7 +127,7 @@ __global__ void k_seg_counts(const int32_t* __restrict__ active, int64_t N, cons
         } else {
             const int64_t blk = sp / kCompactBlock;
             r = boff[blk];
-            for (int64_t i = blk * kCompactBlock; i < sp; ++i) r += active[i] ? 1 : 0;
+            for (int64_t i = blk * kCompactBlock; i < sp; ++i) r += active[at_pos(perm, i)] ? 1 : 0;
         }
         rank[b] = r;
     }
@@ -444,7 +451,8 @@ __global__ void k_solve_init(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
 
 __global__ void k_nm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
                             const int32_t* __restrict__ bidx, int64_t N, const int32_t* __restrict__ list,
-                            const int32_t* __restrict__ n_active, int32_t round, Common C, NMDev nm) {
+                            const int32_t* __restrict__ n_active, const int32_t* __restrict__ round,
+                            Common C, NMDev nm) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= *n_active) return;
     const int64_t i = list[j];
@@ -463,7 +471,7 @@ __global__ void k_nm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
         C.best_st[i] = R.status;
         C.status[i] = kStConverged;
         C.active[i] = 0;
-        atomicAdd(&C.conv[round], 1);
+        atomicAdd(&C.conv[*round], 1);
         return;
     }
     record_best(C, i, N, T, R.Phi, R.status);
@@ -531,7 +539,8 @@ __device__ __forceinline__ void lm_direction(const double jac[12], const double 
 
 __global__ void k_lm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
                             const int32_t* __restrict__ bidx, int64_t N, const int32_t* __restrict__ list,
-                            const int32_t* __restrict__ n_active, int32_t round, Common C, LMDev lm) {
+                            const int32_t* __restrict__ n_active, const int32_t* __restrict__ round,
+                            Common C, LMDev lm) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= *n_active) return;
     const int64_t i = list[j];
@@ -557,7 +566,7 @@ __global__ void k_lm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
         for (int p = 0; p < 3; ++p) C.best[p * N + i] = sqrt(mt[p]);
         C.status[i] = kStConverged;
         C.active[i] = 0;
-        atomicAdd(&C.conv[round], 1);
+        atomicAdd(&C.conv[*round], 1);
         return;
     }
     double nu = lm.nu[i];
@@ -619,6 +628,9 @@ __global__ void k_solve_accept(int64_t N, const double* __restrict__ fg, double 
     st[i] = (rho <= eps) ? kStConverged : kStBudget;
 }
 
+// The round counter read by the update kernels (a device word, so that captured rounds replay).
+__global__ void k_round_next(int32_t* __restrict__ round) { *round += 1; }
+
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -646,6 +658,7 @@ struct SolverBufs {
     int32_t* list;
     int32_t* bsum;
     int32_t* n_active;
+    int32_t* round;     // [1] index of the current round
     int32_t* cnt_b;     // [nb] active points per boundary
     int32_t* rank;      // [nb + 1] list offset of each boundary
     int32_t* off32;     // [nb + 1] tile offsets of the FP32C schedule
@@ -663,6 +676,7 @@ int64_t pad8(int64_t x) { return (x + 7) / 8 * 8; }
 }  // namespace
 
 void solver_free(SolverState& s) {
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
     (void)hipFree(s.block);
     if (s.count_h) (void)hipHostFree(s.count_h);
     s = SolverState{};
@@ -692,7 +706,7 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
                  oRho = L.take<double>(n), oU = L.take<double>(4 * n), oJac = L.take<double>(12 * n),
                  oNu = L.take<double>(n), oLph = L.take<int32_t>(n);
     const size_t oList = L.take<int32_t>(n), oBsum = L.take<int32_t>((size_t)b.nblk + 1),
-                 oNact = L.take<int32_t>(1), oCnt = L.take<int32_t>((size_t)nb),
+                 oNact = L.take<int32_t>(1), oRnd = L.take<int32_t>(1), oCnt = L.take<int32_t>((size_t)nb),
                  oRank = L.take<int32_t>((size_t)nb + 1), oO32 = L.take<int32_t>((size_t)nb + 1),
                  oO64 = L.take<int32_t>((size_t)nb + 1), oSeg = L.take<int64_t>((size_t)nb + 1);
     const size_t oT32 = L.take<Tile>((size_t)b.max32), oT64 = L.take<Tile>((size_t)b.max64);
@@ -721,6 +735,7 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
     b.list = (int32_t*)D(oList);
     b.bsum = (int32_t*)D(oBsum);
     b.n_active = (int32_t*)D(oNact);
+    b.round = (int32_t*)D(oRnd);
     b.cnt_b = (int32_t*)D(oCnt);
     b.rank = (int32_t*)D(oRank);
     b.off32 = (int32_t*)D(oO32);
@@ -731,14 +746,15 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
     return DBIE_OK;
 }
 
-static hipError_t compact(const SolverBufs& b, int64_t N, int32_t nb, int32_t per32, hipStream_t s) {
+static hipError_t compact(const SolverBufs& b, const int32_t* perm, int64_t N, int32_t nb, int32_t per32,
+                          hipStream_t s) {
     const unsigned nblk = (unsigned)std::max<int32_t>(b.nblk, 1);
-    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, N, b.bsum);
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, perm, N, b.bsum);
     hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, b.bsum, (int32_t)nblk, b.n_active);
-    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, N, b.bsum,
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(kCompactThreads), 0, s, b.C.active, perm, N, b.bsum,
                        b.list);
-    hipLaunchKernelGGL(k_seg_counts, dim3(1), dim3(256), 0, s, b.C.active, N, b.bsum, b.n_active, b.segd, nb,
-                       b.cnt_b, b.rank, per32, (int32_t)256, b.off32, b.off64);
+    hipLaunchKernelGGL(k_seg_counts, dim3(1), dim3(256), 0, s, b.C.active, perm, N, b.bsum, b.n_active, b.segd,
+                       nb, b.cnt_b, b.rank, per32, (int32_t)256, b.off32, b.off64);
     hipLaunchKernelGGL(k_fill_tiles, dim3((unsigned)((b.max32 + 255) / 256)), dim3(256), 0, s, b.cnt_b, b.off32,
                        b.rank, nb, per32, b.tiles32, b.max32);
     hipLaunchKernelGGL(k_fill_tiles, dim3((unsigned)((b.max64 + 255) / 256)), dim3(256), 0, s, b.cnt_b, b.off64,
@@ -788,43 +804,105 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     hipLaunchKernelGGL(k_solve_init, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, lam, b.C, b.nm, b.lm);
     SOLVE_HIP(hipGetLastError());
     SOLVE_HIP(hipMemcpyAsync(b.segd, ctx_seg(c), (size_t)(nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    SOLVE_HIP(compact(b, N, nb, per32, s));
+    const int32_t* perm = fp64 ? nullptr : ctx_perm(c);
+    SOLVE_HIP(compact(b, perm, N, nb, per32, s));
     EvalSet set{b.list, b.n_active, b.tiles32, b.max32, b.tiles64, b.max64};
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, b.round, (int64_t)1, 0);
+    SOLVE_HIP(hipGetLastError());
+    // one round: bulk sum + finalize over the active list, update, compaction, round counter
+    auto enqueue_round = [&]() -> int {
+        int r = eval_set(c, b.C.lam_cur, fp64, lmm, &set, b.C.Bw, b.C.dBw, nullptr, lmm ? b.C.tanw : nullptr, s);
+        if (r) return r;
+        if (lmm)
+            hipLaunchKernelGGL(k_lm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list, b.n_active,
+                               b.round, b.C, b.lm);
+        else
+            hipLaunchKernelGGL(k_nm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list, b.n_active,
+                               b.round, b.C, b.nm);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = compact(b, perm, N, nb, per32, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, s, b.round);
+            e = hipGetLastError();
+        }
+        return e == hipSuccess ? DBIE_OK : ctx_fail(c, DBIE_E_DEVICE, hipGetErrorString(e));
+    };
     int32_t rounds = 0;
     const int32_t check_every = 4;
     std::vector<hipEvent_t>& trace = solver_trace_events(c);
     for (auto e : trace) (void)hipEventDestroy(e);
     trace.clear();
-    if (solver_tracing(c)) {
+    const bool tracing = solver_tracing(c);
+    if (tracing) {
         hipEvent_t e = nullptr;
         SOLVE_HIP(hipEventCreate(&e));
         SOLVE_HIP(hipEventRecord(e, s));
         trace.push_back(e);
     }
-    for (; rounds < opt->max_trials; ++rounds) {
-        rc = eval_set(c, b.C.lam_cur, fp64, lmm, &set, b.C.Bw, b.C.dBw, nullptr, lmm ? b.C.tanw : nullptr, s);
+    // Graph replay of check_every rounds: captured once per context and solve configuration (all
+    // kernel arguments are fixed; the round index lives on the device). Not used while recording
+    // events (timing or tracing).
+    const bool graphs = opt->use_graph && !tracing && !ctx_timing(c) && opt->max_trials >= check_every;
+    hipGraphExec_t exec = nullptr;
+    if (graphs) {
+        rc = ensure_acc(c, 1);   // no allocation may happen inside the capture
         if (rc) return rc;
-        if (lmm)
-            hipLaunchKernelGGL(k_lm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list,
-                               b.n_active, rounds, b.C, b.lm);
-        else
-            hipLaunchKernelGGL(k_nm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list,
-                               b.n_active, rounds, b.C, b.nm);
-        SOLVE_HIP(hipGetLastError());
-        SOLVE_HIP(compact(b, N, nb, per32, s));
-        if (solver_tracing(c)) {
-            hipEvent_t e = nullptr;
-            SOLVE_HIP(hipEventCreate(&e));
-            SOLVE_HIP(hipEventRecord(e, s));
-            trace.push_back(e);
+        GraphKey key;
+        std::memset(&key, 0, sizeof(key));   // compared bytewise, padding included
+        key.method = opt->method;
+        key.max_trials = opt->max_trials;
+        key.fp64 = fp64;
+        key.eps = opt->eps;
+        key.step = opt->init_step;
+        key.cap = opt->lambda_cap;
+        key.block = ctx_solver(c).block;
+        key.stream = s;
+        key.per32 = per32;
+        key.perm = perm;
+        SolverState& S = ctx_solver(c);
+        if (S.exec && std::memcmp(&S.key, &key, sizeof(GraphKey)) == 0) {
+            exec = S.exec;
+        } else {
+            if (S.exec) (void)hipGraphExecDestroy(S.exec);
+            S.exec = nullptr;
+            hipGraph_t g = nullptr;
+            SOLVE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int rc2 = DBIE_OK;
+            for (int k = 0; k < check_every && rc2 == DBIE_OK; ++k) rc2 = enqueue_round();
+            const hipError_t ee = hipStreamEndCapture(s, &g);
+            if (rc2) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc2;
+            }
+            SOLVE_HIP(ee);
+            const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SOLVE_HIP(ei);
+            S.exec = exec;
+            S.key = key;
         }
-        if ((rounds + 1) % check_every == 0) {
+    }
+    while (rounds < opt->max_trials) {
+        const int32_t k = std::min(check_every, opt->max_trials - rounds);
+        if (exec && k == check_every) {
+            SOLVE_HIP(hipGraphLaunch(exec, s));
+        } else {
+            for (int32_t j = 0; j < k; ++j) {
+                rc = enqueue_round();
+                if (rc) return rc;
+                if (tracing) {
+                    hipEvent_t e = nullptr;
+                    SOLVE_HIP(hipEventCreate(&e));
+                    SOLVE_HIP(hipEventRecord(e, s));
+                    trace.push_back(e);
+                }
+            }
+        }
+        rounds += k;
+        if (rounds < opt->max_trials) {
             SOLVE_HIP(hipMemcpyAsync(ctx_solver(c).count_h, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             SOLVE_HIP(hipStreamSynchronize(s));
-            if (*ctx_solver(c).count_h == 0) {
-                ++rounds;
-                break;
-            }
+            if (*ctx_solver(c).count_h == 0) break;
         }
     }
     ctx_solver(c).last_rounds = rounds;

@@ -7,8 +7,9 @@
 //   gx_p = -w gX_p / (2pi h),                  gy_p = -w gY_p / (2pi h)
 // (gX, gY, gZ = dLoss/d(dB_p/dx, dy, dz)),
 //   gB0_p(k) = sum_i [ N rho^-3 alpha_p + H rho^-5 (beta_p + gx_p (a_k - u_i) + gy_p (b_k - v_i)) ].
-// Pixels are the outputs (one lane per pixel); the points of the pixel's magnetogram stream through
-// LDS in tiles. Every output is written by exactly one lane: deterministic, no atomics. FP64.
+// Pixels are the outputs; the points of the pixel's magnetogram stream through LDS in tiles. Every
+// output is written by exactly one lane: deterministic, no atomics. FP64 in an FP64 context; in an
+// FP32C context the far pairs in FP32 (cascaded into FP64) and the near pairs in FP64.
 #include <algorithm>
 #include <vector>
 
@@ -19,6 +20,7 @@ namespace dbie {
 constexpr int kVjpPts = 64;      // points per LDS tile
 constexpr int kVjpCoef = 15;     // Lambda[3], alpha[3], beta[3], gx[3], gy[3]
 constexpr double kInv2Pi_v = 0.15915494309189533577;
+constexpr int kVjpPix = 4;       // pixels per lane of the FP32C adjoint
 
 struct PixTile {
     int32_t b;
@@ -101,6 +103,160 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
     }
 }
 
+// ---- FP32C adjoint --------------------------------------------------------------------------
+// Same transpose in FP32, PPX pixels per lane (the point data read from LDS is shared by them),
+// FP32 partials per point tile cascaded into FP64. Pairs classified near in dbie_init are skipped
+// here (point tiles holding such points take a masked loop) and added in FP64 by k_vjp_near.
+constexpr int kVjp32Pts = 64;
+constexpr int kVjp32F = 26;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^2, Lambda[3], Lambda/2pi[3],
+                              // alpha[3], beta[3], gx[3], gy[3], window a, window b, mask (as bits)
+
+template <int PPX, bool SLOW>
+__device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e, const float a[PPX],
+                                            const float b[PPX], float (&acc)[PPX][3]) {
+    const float X = sp[0][e], xf = sp[1][e], Y = sp[2][e], yf = sp[3][e], w2 = sp[4][e];
+#pragma unroll
+    for (int j = 0; j < PPX; ++j) {
+        const float dx = (a[j] - X) - xf;
+        const float dy = (b[j] - Y) - yf;
+        float keep = 1.0f;
+        if (SLOW) {
+            const float da = a[j] - sp[23][e], db = b[j] - sp[24][e];
+            const bool in = fabsf(da) <= (float)kNearWin && fabsf(db) <= (float)kNearWin;
+            const int bit = in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
+            if (in && ((__float_as_uint(sp[25][e]) >> bit) & 1u)) keep = 0.0f;
+        }
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, w2));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * ri;
+        const float ri2 = ri * ri;
+        const float ri3 = ri2 * ri * keep;
+        const float ri5 = ri3 * ri2;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const float tr = __builtin_amdgcn_fractf(sp[8 + p][e] * r);
+            const float sn = __builtin_amdgcn_sinf(tr);
+            const float cs = __builtin_amdgcn_cosf(tr);
+            const float t = sp[5 + p][e] * r;
+            const float n = fmaf(t, sn, cs);
+            const float hh = fmaf(t, t * cs, -3.0f * n);
+            const float lin = fmaf(sp[17 + p][e], dx, fmaf(sp[20 + p][e], dy, sp[14 + p][e]));
+            acc[j][p] = fmaf(n * ri3, sp[11 + p][e], fmaf(hh * ri5, lin, acc[j][p]));
+        }
+    }
+}
+
+template <int PPX>
+__global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptiles,
+                                                const BoundaryDev* __restrict__ bnd,
+                                                const int64_t* __restrict__ seg, const int32_t* __restrict__ perm,
+                                                Geo geo, int64_t N, const double* __restrict__ coef,
+                                                double* __restrict__ gB0) {
+    __shared__ float sp[kVjp32F][kVjp32Pts];
+    __shared__ int any_near;
+    const PixTile pt = ptiles[blockIdx.x];
+    const BoundaryDev bd = bnd[pt.b];
+    float a[PPX], b[PPX];
+    bool live[PPX];
+#pragma unroll
+    for (int j = 0; j < PPX; ++j) {
+        const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
+        live[j] = k < bd.npix;
+        a[j] = live[j] ? (float)(k % bd.nx) : 0.0f;
+        b[j] = live[j] ? (float)(k / bd.nx) : 0.0f;
+    }
+    double tot[PPX][3];
+    float part[PPX][3];
+#pragma unroll
+    for (int j = 0; j < PPX; ++j)
+        for (int p = 0; p < 3; ++p) tot[j][p] = 0.0;
+    const int64_t p0 = seg[pt.b], p1 = seg[pt.b + 1];
+    for (int64_t i0 = p0; i0 < p1; i0 += kVjp32Pts) {
+        const int n = (int)min<int64_t>(kVjp32Pts, p1 - i0);
+        __syncthreads();
+        if (threadIdx.x == 0) any_near = 0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int64_t i = perm ? (int64_t)perm[i0 + e] : i0 + e;
+            sp[0][e] = geo.xi_int[i];
+            sp[1][e] = geo.xi_frac[i];
+            sp[2][e] = geo.yi_int[i];
+            sp[3][e] = geo.yi_frac[i];
+            const float wf = geo.wf[i];
+            sp[4][e] = wf * wf;
+            for (int p = 0; p < 3; ++p) {
+                const double L = coef[(0 + p) * N + i];
+                sp[5 + p][e] = (float)L;
+                sp[8 + p][e] = (float)(L * 0.15915494309189533577);
+                sp[11 + p][e] = (float)coef[(3 + p) * N + i];
+                sp[14 + p][e] = (float)coef[(6 + p) * N + i];
+                sp[17 + p][e] = (float)coef[(9 + p) * N + i];
+                sp[20 + p][e] = (float)coef[(12 + p) * N + i];
+            }
+            sp[23][e] = (float)geo.win_a[i];
+            sp[24][e] = (float)geo.win_b[i];
+            const uint32_t m = geo.near_mask[i];
+            sp[25][e] = __uint_as_float(m);
+            if (m) any_near = 1;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PPX; ++j)
+            for (int p = 0; p < 3; ++p) part[j][p] = 0.0f;
+        if (any_near) {
+            for (int e = 0; e < n; ++e) vjp32_point<PPX, true>(sp, e, a, b, part);
+        } else {
+            for (int e = 0; e < n; ++e) vjp32_point<PPX, false>(sp, e, a, b, part);
+        }
+#pragma unroll
+        for (int j = 0; j < PPX; ++j)
+            for (int p = 0; p < 3; ++p) tot[j][p] += (double)part[j][p];
+    }
+#pragma unroll
+    for (int j = 0; j < PPX; ++j) {
+        if (!live[j]) continue;
+        const int64_t o = bd.pix_off + pt.start + (int64_t)threadIdx.x + j * 256;
+        for (int p = 0; p < 3; ++p) gB0[o + (int64_t)p * bd.npix] = tot[j][p];
+    }
+}
+
+// FP64 near pairs of the adjoint: pixel g (global index over all boundaries) gathers the points
+// listed in near_pts[near_ptr[g] .. near_ptr[g+1]) (sorted by point) and adds to its output.
+__global__ void k_vjp_near(int64_t npix_total, const int32_t* __restrict__ near_ptr,
+                           const int32_t* __restrict__ near_pts, const int32_t* __restrict__ pix_bnd,
+                           const BoundaryDev* __restrict__ bnd, Geo geo, int64_t N,
+                           const double* __restrict__ coef, double* __restrict__ gB0) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npix_total) return;
+    const int32_t s0 = near_ptr[g], s1 = near_ptr[g + 1];
+    if (s0 == s1) return;
+    const BoundaryDev bd = bnd[pix_bnd[g]];
+    const int64_t k = g - bd.pix_off / 3;
+    const double a = (double)(k % bd.nx), bb = (double)(k / bd.nx);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int32_t q = s0; q < s1; ++q) {
+        const int64_t i = near_pts[q];
+        const double dx = a - geo.u[i], dy = bb - geo.v[i], w = geo.w[i];
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w * w));
+        const double ri = rsqrt(r2);
+        const double r = r2 * ri;
+        const double ri2 = ri * ri;
+        const double ri3 = ri2 * ri;
+        const double ri5 = ri3 * ri2;
+        for (int p = 0; p < 3; ++p) {
+            const double t = coef[(0 + p) * N + i] * r;
+            double sn, cs;
+            sincos(t, &sn, &cs);
+            const double nn = __builtin_fma(t, sn, cs);
+            const double hh = __builtin_fma(t, t * cs, -3.0 * nn);
+            const double lin = __builtin_fma(coef[(9 + p) * N + i], dx,
+                                             __builtin_fma(coef[(12 + p) * N + i], dy, coef[(6 + p) * N + i]));
+            acc[p] = __builtin_fma(nn * ri3, coef[(3 + p) * N + i], __builtin_fma(hh * ri5, lin, acc[p]));
+        }
+    }
+    for (int p = 0; p < 3; ++p) gB0[bd.pix_off + (int64_t)p * bd.npix + k] += acc[p];
+}
+
 // g_mu_p = gB_p tan[p] + sum_q gdB[3p+q] tan[3+3p+q]; g_lambda = 2 lambda g_mu.
 __global__ void k_grad_lambda(int64_t N, const double* __restrict__ lam, const double* __restrict__ gB,
                               const double* __restrict__ gdB, const double* __restrict__ tan,
@@ -164,25 +320,37 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
     }
     if (gB0) {
         // pixel tiles of every boundary, and the point segments on the device
-        std::vector<PixTile> pt;
+        std::vector<PixTile> pt, pt32;
         for (int32_t b = 0; b < nb; ++b) {
             const BoundaryDev& bd = ctx_bnd_host(c, b);
             for (int32_t k = 0; k < bd.npix; k += 256) pt.push_back(PixTile{b, k});
+            for (int32_t k = 0; k < bd.npix; k += 256 * kVjpPix) pt32.push_back(PixTile{b, k});
         }
         const size_t szc = (size_t)std::max<int64_t>(N, 1) * kVjpCoef * sizeof(double);
-        const size_t szt = (pt.size() * sizeof(PixTile) + 255) / 256 * 256;
+        const size_t szt = ((pt.size() + pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
         const size_t szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
         char* w = (char*)ctx_scratch(c, 1, szc + szt + szs);
         if (!w) return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the adjoint workspace");
         double* coef = (double*)w;
         PixTile* ptd = (PixTile*)(w + szc);
         int64_t* segd = (int64_t*)(w + szc + szt);
+        PixTile* ptd32 = ptd + pt.size();
         GRAD_HIP(hipMemcpyAsync(ptd, pt.data(), pt.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
+        GRAD_HIP(hipMemcpyAsync(ptd32, pt32.data(), pt32.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
         GRAD_HIP(hipMemcpyAsync(segd, ctx_seg(c), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
         if (N > 0)
             hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
-        hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N, coef,
-                           gB0);
+        if (ctx_precision(c) == DBIE_FP64) {
+            hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N, coef,
+                               gB0);
+        } else {
+            hipLaunchKernelGGL(k_vjp32c<kVjpPix>, dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32, bnd, segd,
+                               ctx_perm(c), geo, N, coef, gB0);
+            const NearLists nl = ctx_near_lists(c);
+            if (nl.n_pairs > 0)
+                hipLaunchKernelGGL(k_vjp_near, dim3((unsigned)((nl.npix_total + 255) / 256)), dim3(256), 0, s,
+                                   nl.npix_total, nl.ptr, nl.pts, nl.pix_bnd, bnd, geo, N, coef, gB0);
+        }
         GRAD_HIP(hipGetLastError());
         // the host arrays above must stay alive until the copies have been consumed
         GRAD_HIP(hipStreamSynchronize(s));

@@ -164,7 +164,7 @@ def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, t
 def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "nm", max_trials: int = 50,
                       eps: float = 1e-4, init_step: float = 0.0, lambda_cap: float = 0.0,
                       fp64_accept: bool = True, B=None, fg=None, status=None, trials=None,
-                      want_B: bool = True, want_fg: bool = True, stream=None):
+                      want_B: bool = True, want_fg: bool = True, use_graph: bool = True, stream=None):
     N = ctx.n_points
     _need(lambda_inout, "lambda_inout", (3, N))
     dev = lambda_inout.device
@@ -181,6 +181,7 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
     o.init_step = float(init_step)
     o.lambda_cap = float(lambda_cap)
     o.fp64_accept = int(bool(fp64_accept))
+    o.use_graph = int(bool(use_graph))
     rc = _lib().dbie_solve_lambda(ctx.handle, _ptr(lambda_inout), ctypes.byref(o), _ptr(B), _ptr(fg),
                                   _ptr(status), _ptr(trials), _stream(stream))
     _check(rc, ctx, "dbie_solve_lambda")

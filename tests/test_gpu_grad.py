@@ -37,12 +37,37 @@ def test_grad_matches_oracle(precision, tol):
     r = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB), want_resid_jac=True)
     torch.cuda.synchronize()
     gB0_ref, glam_ref, _ = oracle.vjp(B0, x0, y0, h, xyz, lam, gB, gdB)
-    # the B0 adjoint is FP64 in both contexts
-    assert rel(r["gB0"].cpu().numpy().reshape(3, *B0.shape[1:]), gB0_ref) <= 1e-10
+    # points down to 0.4 h: the FP32C adjoint sums their near pairs in FP64
+    assert rel(r["gB0"].cpu().numpy().reshape(3, *B0.shape[1:]), gB0_ref) <= tol
     assert rel(r["glambda"].cpu(), glam_ref) <= tol
     B, dB, tan = oracle.field(B0, x0, y0, h, xyz, lam, tangents=True)
     jac = oracle.residual_jacobian(B, dB, tan, h)
     assert rel(r["resid_jac"].cpu(), jac) <= 10 * tol
+
+
+def test_fp32c_adjoint_on_batched_boundaries_and_determinism():
+    rng = np.random.default_rng(35)
+    bds, xyzs, seg, B0s = [], [], [0], []
+    for nx, ny, n in ((21, 17, 500), (40, 9, 300)):
+        B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+        B0s.append(B0)
+        bds.append(dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0))
+        xyzs.append(np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0.5, 6.0, n)]))
+        seg.append(seg[-1] + n)
+    xyz = np.concatenate(xyzs, axis=1)
+    n = xyz.shape[1]
+    lam = rng.uniform(0.0, 0.5, size=(3, n))
+    gB = rng.normal(size=(3, n))
+    gdB = rng.normal(size=(9, n))
+    ctx = D.dbie_init(bds, T(xyz), seg=seg, precision="fp32c")
+    r1 = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB))
+    r2 = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB))
+    assert torch.equal(r1["gB0"], r2["gB0"]) and torch.equal(r1["glambda"], r2["glambda"])
+    parts = D.split_gB0(ctx, r1["gB0"])
+    for b in range(2):
+        s0, s1 = seg[b], seg[b + 1]
+        ref, _, _ = oracle.vjp(B0s[b], 0.0, 0.0, 1.0, xyz[:, s0:s1], lam[:, s0:s1], gB[:, s0:s1], gdB[:, s0:s1])
+        assert rel(parts[b].cpu(), ref) <= 1e-5, b
 
 
 def test_dot_product_on_the_gpu():

@@ -152,3 +152,20 @@ def test_solver_edge_cases():
         assert torch.all(r0["status"] == D._lib.DBIE_ST_DEGENERATE), m
     with pytest.raises(D.DbieError, match="max_trials"):
         D.dbie_solve_lambda(ctx, T(np.zeros((3, 6))), method="nm", max_trials=0)
+
+
+@pytest.mark.parametrize("method,prec", [("nm", "fp64"), ("lm", "fp32c")])
+def test_graph_replay_equals_eager_rounds(method, prec):
+    """The rounds replayed from a captured HIP graph give bitwise the eager results, on every replay,
+    with eager solves and synchronisations in between."""
+    w, bd, ctx = lowlou_ctx(prec)
+    N = w.n_points
+    rng = np.random.default_rng(51)
+    for rep in range(3):
+        lam0 = T(rng.uniform(0.0, 0.5, size=(3, N)))
+        eager = D.dbie_solve_lambda(ctx, lam0.clone(), method=method, max_trials=18, use_graph=False)
+        torch.cuda.synchronize()
+        graph = D.dbie_solve_lambda(ctx, lam0.clone(), method=method, max_trials=18, use_graph=True)
+        torch.cuda.synchronize()
+        for k in ("lam", "status", "trials", "B", "fg"):
+            assert torch.equal(eager[k], graph[k]), (rep, k)
