@@ -131,6 +131,13 @@ DBIE_API int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_opti
 DBIE_API int dbie_eval_field(dbie_ctx* ctx, const double* lambda, int32_t L, double* B, double* dB,
                              double* fg, double* tan, void* stream);
 
+/* dbie_eval_field with one lambda shared by the three components at each point (lambda_x = lambda_y
+ * = lambda_z, e.g. a linear force-free trial): lambda is device double [L][N]; the outputs are those of
+ * dbie_eval_field (tan rows are d/d mu of each row for the shared mu = lambda^2). The FP32C bulk sum
+ * then computes one sin/cos pair per kernel pair instead of three. */
+DBIE_API int dbie_eval_field_scalar(dbie_ctx* ctx, const double* lambda, int32_t L, double* B, double* dB,
+                                    double* fg, double* tan, void* stream);
+
 /* Per-point lambda search (Section 2.1, Eqs. 8-12), all points at once, device resident.
  *   lambda_inout : device double [3][N]; start values in, |lambda*| out
  *   B, fg        : device double [3][N] / [2][N] or NULL: field and (f, g) at lambda*

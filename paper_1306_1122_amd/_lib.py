@@ -39,6 +39,8 @@ SIGNATURES = {
     "dbie_init": (c_int32, [POINTER(c_void_p), POINTER(dbie_problem), POINTER(dbie_options), c_void_p]),
     "dbie_eval_field": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p]),
+    "dbie_eval_field_scalar": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_void_p]),
     "dbie_solve_lambda": (c_int32, [c_void_p, c_void_p, POINTER(dbie_solve_opts), c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p]),
     "dbie_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -172,7 +172,7 @@ int ensure_acc(dbie_ctx* c, int64_t L) {
 
 // Bulk sum + finalize for L trials on the given lambda; the building block of every call.
 static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const EvalSet* set,
-                     double* B, double* dB, double* fg, double* tn, hipStream_t s) {
+                     double* B, double* dB, double* fg, double* tn, hipStream_t s, bool scalar = false) {
     int rc = ensure_acc(c, L);
     if (rc) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -189,7 +189,7 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
                                     c->pixf, c->geo, lam, c->N, L, set ? idx : c->perm, set == nullptr, tan,
-                                    tan ? c->shape_tan : c->shape, c->acc, s));
+                                    scalar, tan ? c->shape_tan : c->shape, c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
         c->ev.emplace_back(e0, e1);
@@ -469,6 +469,21 @@ int dbie_eval_field(dbie_ctx* c, const double* lambda, int32_t L, double* B, dou
     if (c->N == 0) return DBIE_OK;
     return eval_core(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, B, dB, fg, tan,
                      (hipStream_t)stream);
+}
+
+int dbie_eval_field_scalar(dbie_ctx* c, const double* lambda, int32_t L, double* B, double* dB, double* fg,
+                           double* tan, void* stream) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    if (L < 1) return fail(c, DBIE_E_INVAL, "L must be >= 1");
+    if (c->N > 0 && (!lambda || !B)) return fail(c, DBIE_E_INVAL, "lambda and B are required");
+    if ((int64_t)L * c->N > ((int64_t)1 << 31) - 1)
+        return fail(c, DBIE_E_INVAL, "L * n_points exceeds 2^31 - 1");
+    if (c->N == 0) return DBIE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* lam3 = (double*)ctx_scratch(c, 3, (size_t)L * 3 * c->N * sizeof(double));
+    if (!lam3) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the lambda workspace");
+    DBIE_HIP(c, launch_expand_scalar(lambda, L, c->N, lam3, s));
+    return eval_core(c, lam3, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, B, dB, fg, tan, s, true);
 }
 
 int dbie_timing(dbie_ctx* c, int32_t enable) {

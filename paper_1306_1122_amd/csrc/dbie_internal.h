@@ -184,6 +184,8 @@ hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bn
                        int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,
                        hipStream_t s);
 
+hipError_t launch_expand_scalar(const double* lam, int32_t L, int64_t N, double* lam3, hipStream_t s);
+
 // The bulk kernels run over a schedule of tiles. Without `idx` a tile is a run of point indices;
 // with `idx` it is a run of entries of the active-point list idx (device schedules of the solver).
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
@@ -196,11 +198,12 @@ struct F32Shape {
     int32_t tp;      // pixels per LDS tile
 };
 
-// remap_xcd: deal contiguous runs of the schedule to the 8 XCDs (static schedules).
+// remap_xcd: deal contiguous runs of the schedule to the 8 XCDs (static schedules). scalar: the
+// three lambda rows of every point are equal (the kernel reads row 0 only).
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, bool remap_xcd, bool tan, F32Shape shape, double* acc,
-                           hipStream_t s);
+                           const int32_t* idx, bool remap_xcd, bool tan, bool scalar, F32Shape shape,
+                           double* acc, hipStream_t s);
 bool field32c_shape_supported(F32Shape shape);
 int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number
 

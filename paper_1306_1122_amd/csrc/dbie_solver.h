@@ -22,6 +22,9 @@ struct GraphKey {
 struct SolverState {
     hipGraphExec_t exec = nullptr;   // captured rounds, replayed while `key` matches
     GraphKey key{};
+    hipStream_t rs = nullptr;        // library stream the captured rounds run on (the caller's stream
+                                     // may be the legacy default stream, which cannot be captured)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     void* block = nullptr;       // one allocation for every per-point solver array
     int64_t bytes = 0;
     int32_t* count_h = nullptr;  // pinned host word: active-point count

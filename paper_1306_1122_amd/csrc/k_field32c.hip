@@ -14,6 +14,7 @@
 //   hardware's accurate range of 256 revolutions), N = t sin t + cos t, H = t (t cos t) - 3 N,
 //   A0 += N rho^-3 B0,  A1 += H rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += H rho^-3 B0 rho^-2
 //   (and with tangents T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy).
+// SCALAR: the three components share one lambda, so t, sin, cos, N and H are computed once per pair.
 // Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
 // FP64 totals, so the error does not grow with the magnetogram size.
 // Near field: pairs whose (FP64-classified) distance is below the near radius are skipped here and
@@ -72,8 +73,46 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
     }
 }
 
+// One pair when the three components share one lambda: the sin/cos, N and H are computed once.
+template <bool TAN, bool FRACT>
+__device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float lt, float lr, float bx, float by,
+                                              float bz, float* acc) {
+    const float r2 = fmaf(dx, dx, q);
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float dxr = dx * ri2;
+    const float dyr = dy * ri2;
+    const float tr = FRACT ? __builtin_amdgcn_fractf(lr * r) : lr * r;
+    const float sn = __builtin_amdgcn_sinf(tr);
+    const float cs = __builtin_amdgcn_cosf(tr);
+    const float t = lt * r;
+    const float n = fmaf(t, sn, cs);
+    const float hh = fmaf(t, t * cs, -3.0f * n);
+    const float nr3 = n * ri3, hr3 = hh * ri3;
+    const float cri = cs * ri;
+    const float b0[3] = {bx, by, bz};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const float hb = hr3 * b0[p];
+        if (TAN) {
+            const float nb = nr3 * b0[p];
+            acc[4 * p + 0] += nb;
+            acc[12 + 3 * p + 0] = fmaf(cri, b0[p], acc[12 + 3 * p + 0]);
+            acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
+            acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
+        } else {
+            acc[4 * p + 0] = fmaf(nr3, b0[p], acc[4 * p + 0]);
+        }
+        acc[4 * p + 1] = fmaf(hb, dxr, acc[4 * p + 1]);
+        acc[4 * p + 2] = fmaf(hb, dyr, acc[4 * p + 2]);
+        acc[4 * p + 3] = fmaf(hb, ri2, acc[4 * p + 3]);
+    }
+}
+
 // One block of kRows x kCols pixels with origin (a0, b0) and `rows` valid rows, for all PPL points.
-template <int PPL, bool TAN, bool SLOW, bool FRACT>
+template <int PPL, bool TAN, bool SLOW, bool FRACT, bool SCALAR>
 __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
                                            const float4 (*sB)[kRows][kCols / 4], float a0, float b0,
                                            int rows, float (&part)[PPL][TAN ? kAcc : kAccField]) {
@@ -107,13 +146,16 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
                         in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
                     if (in && ((S.msk[j] >> bit) & 1u)) bx = by = bz = 0.0f;
                 }
-                pair32<TAN, FRACT>(dxc[j][c], dy, q, S.lt[j], S.lr[j], bx, by, bz, part[j]);
+                if (SCALAR)
+                    pair32_scalar<TAN, FRACT>(dxc[j][c], dy, q, S.lt[j][0], S.lr[j][0], bx, by, bz, part[j]);
+                else
+                    pair32<TAN, FRACT>(dxc[j][c], dy, q, S.lt[j], S.lr[j], bx, by, bz, part[j]);
             }
         }
     }
 }
 
-template <int PPL, int WAVES, bool TAN>
+template <int PPL, int WAVES, bool TAN, bool SCALAR>
 __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
                                                          const BoundaryDev* __restrict__ bnd,
@@ -222,11 +264,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
             for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
         const float fa0 = (float)a0, fb0 = (float)b0;
         if (!slow) {
-            if (need_fract) block_loop<PPL, TAN, false, true>(S, sB, fa0, fb0, rows, part);
-            else block_loop<PPL, TAN, false, false>(S, sB, fa0, fb0, rows, part);
+            if (need_fract) block_loop<PPL, TAN, false, true, SCALAR>(S, sB, fa0, fb0, rows, part);
+            else block_loop<PPL, TAN, false, false, SCALAR>(S, sB, fa0, fb0, rows, part);
         } else {
-            if (need_fract) block_loop<PPL, TAN, true, true>(S, sB, fa0, fb0, rows, part);
-            else block_loop<PPL, TAN, true, false>(S, sB, fa0, fb0, rows, part);
+            if (need_fract) block_loop<PPL, TAN, true, true, SCALAR>(S, sB, fa0, fb0, rows, part);
+            else block_loop<PPL, TAN, true, false, SCALAR>(S, sB, fa0, fb0, rows, part);
         }
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
@@ -269,23 +311,28 @@ bool field32c_shape_supported(F32Shape s) {
 
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, bool remap_xcd, bool tan, F32Shape s, double* acc,
-                           hipStream_t st) {
+                           const int32_t* idx, bool remap_xcd, bool tan, bool scalar, F32Shape s,
+                           double* acc, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
     const int remap = remap_xcd ? 1 : 0;
     const dim3 grid((unsigned)n_tiles, (unsigned)L);
-#define DBIE_LAUNCH(P, W)                                                                            \
-    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {                                       \
-        if (tan)                                                                                     \
-            hipLaunchKernelGGL((k_field32c<P, W, true>), grid, dim3(64 * W), 0, st, tiles, n_tiles,  \
-                               bnd, pixf, geo, lam, N, idx, remap, acc);                             \
-        else                                                                                         \
-            hipLaunchKernelGGL((k_field32c<P, W, false>), grid, dim3(64 * W), 0, st, tiles, n_tiles, \
-                               bnd, pixf, geo, lam, N, idx, remap, acc);                             \
-        return hipGetLastError();                                                                    \
+#define DBIE_LAUNCH_ONE(P, W, T, SC)                                                                 \
+    hipLaunchKernelGGL((k_field32c<P, W, T, SC>), grid, dim3(64 * W), 0, st, tiles, n_tiles, bnd, pixf, geo, \
+                       lam, N, idx, remap, acc)
+#define DBIE_LAUNCH(P, W)                                                 \
+    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {            \
+        if (tan) {                                                        \
+            if (scalar) DBIE_LAUNCH_ONE(P, W, true, true);                \
+            else DBIE_LAUNCH_ONE(P, W, true, false);                      \
+        } else {                                                          \
+            if (scalar) DBIE_LAUNCH_ONE(P, W, false, true);               \
+            else DBIE_LAUNCH_ONE(P, W, false, false);                     \
+        }                                                                 \
+        return hipGetLastError();                                         \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)
 #undef DBIE_LAUNCH
+#undef DBIE_LAUNCH_ONE
     return hipErrorInvalidValue;
 }
 

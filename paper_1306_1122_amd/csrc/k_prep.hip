@@ -70,6 +70,21 @@ __global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, floa
     pixf[bd.pixf_off + e] = v;
 }
 
+// lam3[t][p][i] = lam[t][i] for p = x, y, z (one lambda shared by the three components).
+__global__ void k_expand_scalar(const double* __restrict__ lam, int64_t LN, int64_t N, double* __restrict__ lam3) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= LN) return;
+    const int64_t t = e / N, i = e - t * N;
+    const double v = lam[e];
+    for (int p = 0; p < 3; ++p) lam3[(t * 3 + p) * N + i] = v;
+}
+
+hipError_t launch_expand_scalar(const double* lam, int32_t L, int64_t N, double* lam3, hipStream_t s) {
+    const int64_t LN = (int64_t)L * N;
+    hipLaunchKernelGGL(k_expand_scalar, dim3((unsigned)((LN + 255) / 256)), dim3(256), 0, s, lam, LN, N, lam3);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
                        const double* xyz, int64_t N, Geo geo, double near_r2, int fp64_only,
                        int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,

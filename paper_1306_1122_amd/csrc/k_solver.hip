@@ -677,6 +677,9 @@ int64_t pad8(int64_t x) { return (x + 7) / 8 * 8; }
 
 void solver_free(SolverState& s) {
     if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    if (s.ev_in) (void)hipEventDestroy(s.ev_in);
+    if (s.ev_out) (void)hipEventDestroy(s.ev_out);
+    if (s.rs) (void)hipStreamDestroy(s.rs);
     (void)hipFree(s.block);
     if (s.count_h) (void)hipHostFree(s.count_h);
     s = SolverState{};
@@ -810,19 +813,19 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, b.round, (int64_t)1, 0);
     SOLVE_HIP(hipGetLastError());
     // one round: bulk sum + finalize over the active list, update, compaction, round counter
-    auto enqueue_round = [&]() -> int {
-        int r = eval_set(c, b.C.lam_cur, fp64, lmm, &set, b.C.Bw, b.C.dBw, nullptr, lmm ? b.C.tanw : nullptr, s);
+    auto enqueue_round = [&](hipStream_t q) -> int {
+        int r = eval_set(c, b.C.lam_cur, fp64, lmm, &set, b.C.Bw, b.C.dBw, nullptr, lmm ? b.C.tanw : nullptr, q);
         if (r) return r;
         if (lmm)
-            hipLaunchKernelGGL(k_lm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list, b.n_active,
+            hipLaunchKernelGGL(k_lm_update, dim3(gN), dim3(256), 0, q, cfg, bnd, geo.bidx, N, b.list, b.n_active,
                                b.round, b.C, b.lm);
         else
-            hipLaunchKernelGGL(k_nm_update, dim3(gN), dim3(256), 0, s, cfg, bnd, geo.bidx, N, b.list, b.n_active,
+            hipLaunchKernelGGL(k_nm_update, dim3(gN), dim3(256), 0, q, cfg, bnd, geo.bidx, N, b.list, b.n_active,
                                b.round, b.C, b.nm);
         hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = compact(b, perm, N, nb, per32, s);
+        if (e == hipSuccess) e = compact(b, perm, N, nb, per32, q);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, s, b.round);
+            hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, q, b.round);
             e = hipGetLastError();
         }
         return e == hipSuccess ? DBIE_OK : ctx_fail(c, DBIE_E_DEVICE, hipGetErrorString(e));
@@ -844,7 +847,17 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     // events (timing or tracing).
     const bool graphs = opt->use_graph && !tracing && !ctx_timing(c) && opt->max_trials >= check_every;
     hipGraphExec_t exec = nullptr;
+    hipStream_t rs = s;   // the stream the rounds run on
     if (graphs) {
+        SolverState& S0 = ctx_solver(c);
+        if (!S0.rs) {
+            SOLVE_HIP(hipStreamCreateWithFlags(&S0.rs, hipStreamNonBlocking));
+            SOLVE_HIP(hipEventCreateWithFlags(&S0.ev_in, hipEventDisableTiming));
+            SOLVE_HIP(hipEventCreateWithFlags(&S0.ev_out, hipEventDisableTiming));
+        }
+        rs = S0.rs;
+        SOLVE_HIP(hipEventRecord(S0.ev_in, s));
+        SOLVE_HIP(hipStreamWaitEvent(rs, S0.ev_in, 0));
         rc = ensure_acc(c, 1);   // no allocation may happen inside the capture
         if (rc) return rc;
         GraphKey key;
@@ -856,7 +869,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         key.step = opt->init_step;
         key.cap = opt->lambda_cap;
         key.block = ctx_solver(c).block;
-        key.stream = s;
+        key.stream = rs;
         key.per32 = per32;
         key.perm = perm;
         SolverState& S = ctx_solver(c);
@@ -866,10 +879,10 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
             if (S.exec) (void)hipGraphExecDestroy(S.exec);
             S.exec = nullptr;
             hipGraph_t g = nullptr;
-            SOLVE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            SOLVE_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
             int rc2 = DBIE_OK;
-            for (int k = 0; k < check_every && rc2 == DBIE_OK; ++k) rc2 = enqueue_round();
-            const hipError_t ee = hipStreamEndCapture(s, &g);
+            for (int k = 0; k < check_every && rc2 == DBIE_OK; ++k) rc2 = enqueue_round(rs);
+            const hipError_t ee = hipStreamEndCapture(rs, &g);
             if (rc2) {
                 if (g) (void)hipGraphDestroy(g);
                 return rc2;
@@ -885,10 +898,10 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     while (rounds < opt->max_trials) {
         const int32_t k = std::min(check_every, opt->max_trials - rounds);
         if (exec && k == check_every) {
-            SOLVE_HIP(hipGraphLaunch(exec, s));
+            SOLVE_HIP(hipGraphLaunch(exec, rs));
         } else {
             for (int32_t j = 0; j < k; ++j) {
-                rc = enqueue_round();
+                rc = enqueue_round(rs);
                 if (rc) return rc;
                 if (tracing) {
                     hipEvent_t e = nullptr;
@@ -900,10 +913,14 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         }
         rounds += k;
         if (rounds < opt->max_trials) {
-            SOLVE_HIP(hipMemcpyAsync(ctx_solver(c).count_h, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            SOLVE_HIP(hipStreamSynchronize(s));
+            SOLVE_HIP(hipMemcpyAsync(ctx_solver(c).count_h, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, rs));
+            SOLVE_HIP(hipStreamSynchronize(rs));
             if (*ctx_solver(c).count_h == 0) break;
         }
+    }
+    if (rs != s) {
+        SOLVE_HIP(hipEventRecord(ctx_solver(c).ev_out, rs));
+        SOLVE_HIP(hipStreamWaitEvent(s, ctx_solver(c).ev_out, 0));
     }
     ctx_solver(c).last_rounds = rounds;
     ctx_solver(c).last_conv = b.C.conv;

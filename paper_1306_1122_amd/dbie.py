@@ -161,6 +161,29 @@ def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, t
     return out
 
 
+def dbie_eval_field_scalar(ctx: Context, lam: torch.Tensor, want_dB: bool = True, want_fg: bool = True,
+                           want_tan: bool = False, stream=None):
+    """lam: [N] or [L, N], one lambda shared by the three components of each point."""
+    N = ctx.n_points
+    squeeze = lam.dim() == 1
+    lam2 = lam.unsqueeze(0) if squeeze else lam
+    Lt = int(lam2.shape[0])
+    _need(lam2, "lambda", (Lt, N))
+    dev = lam.device
+    z = lambda *s: torch.empty(*s, dtype=torch.float64, device=dev)  # noqa: E731
+    B = z(Lt, 3, N)
+    dB = z(Lt, 9, N) if want_dB else None
+    fg = z(Lt, 2, N) if want_fg else None
+    tan = z(Lt, 12, N) if want_tan else None
+    rc = _lib().dbie_eval_field_scalar(ctx.handle, _ptr(lam2), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
+                                       _stream(stream))
+    _check(rc, ctx, "dbie_eval_field_scalar")
+    out = dict(B=B, dB=dB, fg=fg, tan=tan)
+    if squeeze:
+        out = {k: (v[0] if v is not None else v) for k, v in out.items()}
+    return out
+
+
 def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "nm", max_trials: int = 50,
                       eps: float = 1e-4, init_step: float = 0.0, lambda_cap: float = 0.0,
                       fp64_accept: bool = True, B=None, fg=None, status=None, trials=None,

@@ -200,3 +200,28 @@ def test_zero_points_and_invalid_points():
     nanp = T(np.array([[np.nan], [0.0], [1.0]]))
     with pytest.raises(D.DbieError, match="non-finite"):
         D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], nanp)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_scalar_lambda_fast_path(precision):
+    """One lambda shared by the three components: the fast path against the oracle and against the
+    general path with the lambda repeated."""
+    w = config2(nz=8)
+    bd = w.boundaries[0]
+    ctx = ctx_for(w.boundaries, w.xyz, precision)
+    rng = np.random.default_rng(61)
+    lam1 = rng.uniform(-0.1, 0.1, size=(2, w.n_points))
+    out = D.dbie_eval_field_scalar(ctx, T(lam1), want_tan=True)
+    gen = D.dbie_eval_field(ctx, T(np.repeat(lam1[:, None, :], 3, axis=1)), want_tan=True)
+    torch.cuda.synchronize()
+    for k in ("B", "dB", "tan", "fg"):
+        if precision == "fp64":
+            assert torch.equal(out[k], gen[k]), k
+        else:
+            assert rel(out[k].cpu(), gen[k].cpu()) <= 1e-6, k
+    idx = z_stratified_subsample(w.xyz, 128, seed=9)
+    for t in range(2):
+        lam3 = np.repeat(lam1[t][None, idx], 3, axis=0)
+        B, dB, tan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], lam3, tangents=True)
+        for name, ref in (("B", B), ("dB", dB), ("tan", tan)):
+            assert rel(out[name][t][:, idx].cpu(), ref) <= TOL[precision], (t, name)
