@@ -109,6 +109,20 @@ def per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s):
     return out
 
 
+def adjoint_and_scalar(D, ctx, lam, pairs):
+    """dbie_grad (B0 adjoint + lambda gradient, FP32C) and the single-lambda evaluation on the
+    benchmark workload."""
+    import torch
+    N = ctx.n_points
+    g = torch.ones(3, N, dtype=torch.float64, device=lam.device)
+    gd = torch.ones(9, N, dtype=torch.float64, device=lam.device)
+    ms_adj = _timed(lambda: D.dbie_grad(ctx, lam, gB=g, gdB=gd, want_glambda=False), 2)
+    lam1 = lam[0].contiguous()
+    ms_sc = _timed(lambda: D.dbie_eval_field_scalar(ctx, lam1), 3)
+    return dict(adjoint_gB0_ms=ms_adj, adjoint_pairs_per_s=pairs / (ms_adj * 1e-3),
+                scalar_lambda_field_grad_ms=ms_sc, scalar_lambda_pairs_per_s=pairs / (ms_sc * 1e-3))
+
+
 def time_to_solution(D, dev, n_sample=65536):
     """Plain form (FP64 Nelder-Mead, 200 trials) vs fast form (FP32C Levenberg-Marquardt, 20 trials,
     FP64 acceptance) on a z-stratified sample of the 256x256x128 bipole grid, from lambda = 0.
@@ -209,7 +223,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -286,6 +300,7 @@ def main():
     extras = {}
     if not args.no_extras:
         for name, fn in (("per_trial_rates", lambda: per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s)),
+                         ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs)),
                          ("time_to_solution", lambda: time_to_solution(D, dev)),
                          ("batched_64_magnetograms", lambda: batched(D, dev)),
                          ("active_region_512x256_arcs", lambda: active_region(D, dev))):
