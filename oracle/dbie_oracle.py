@@ -461,3 +461,79 @@ def solve_point_lm(prob: PointProblem, lam0, budget: int, eps: float, lam_cap: f
     if st == ST_J_ZERO:
         st = ST_BUDGET
     return np.sqrt(mu), st, trials, rho
+
+
+# ------------------------------------------------------------------------------------------------
+# Eq. (15): 9-node quadratic boundary elements with Gauss-Legendre quadrature
+# ------------------------------------------------------------------------------------------------
+def _lagrange3(xi):
+    """Quadratic Lagrange shape functions on the nodes -1, 0, 1 (rows) at the abscissae xi."""
+    xi = np.asarray(xi, np.float64)
+    return np.stack([0.5 * xi * (xi - 1.0), 1.0 - xi * xi, 0.5 * xi * (xi + 1.0)])
+
+
+def field_quad9(B0, x0, y0, h, xyz, lam, G: int = 4, tangents: bool = False, chunk: int = 16):
+    """Eq. (15): B_p(i) = sum_e sum_j [int int K N_j J dxi deta] B0_p(node j of e).
+
+    The magnetogram's nodes (pixel centres) are grouped into 9-node elements: element (m, n) holds
+    the nodes a = 2m..2m+2, b = 2n..2n+2 (so nx and ny must be odd); on it x = x0 + (2m+1+xi) h,
+    y = y0 + (2n+1+eta) h, J = h^2 and N_j(xi, eta) = L_alpha(xi) L_beta(eta) with the quadratic Lagrange
+    polynomials. Each element integral uses G x G Gauss-Legendre points. The frozen-lambda gradient
+    rows and mu-tangents follow as in `field` (derivatives of K with respect to the point)."""
+    B0 = np.asarray(B0, np.float64)
+    ny, nx = B0.shape[1:]
+    if nx % 2 == 0 or ny % 2 == 0 or nx < 3 or ny < 3:
+        raise ValueError("9-node elements need odd nx, ny >= 3")
+    ex, ey = (nx - 1) // 2, (ny - 1) // 2
+    xg, wg = np.polynomial.legendre.leggauss(G)
+    Lg = _lagrange3(xg)                                  # [3 nodes, G points]
+    npts = xyz.shape[1]
+    B = np.zeros((3, npts))
+    dB = np.zeros((9, npts))
+    tan = np.zeros((12, npts)) if tangents else None
+    # every element-node-Gauss contribution as one list of (position, weight x B0 of the node)
+    # m, n: element; alpha, beta: node in the element; g, q: Gauss point
+    m = np.arange(ex)[:, None, None, None, None, None]
+    n = np.arange(ey)[None, :, None, None, None, None]
+    al = np.arange(3)[None, None, :, None, None, None]
+    be = np.arange(3)[None, None, None, :, None, None]
+    g = np.arange(G)[None, None, None, None, :, None]
+    q = np.arange(G)[None, None, None, None, None, :]
+    shp = (ex, ey, 3, 3, G, G)
+    gx = np.broadcast_to(x0 + (2 * m + 1 + xg[g]) * h, shp).ravel()
+    gy = np.broadcast_to(y0 + (2 * n + 1 + xg[q]) * h, shp).ravel()
+    wN = np.broadcast_to(wg[g] * wg[q] * Lg[al, g] * Lg[be, q] * h * h, shp).ravel()
+    na = np.broadcast_to(2 * m + al, shp).ravel()
+    nb = np.broadcast_to(2 * n + be, shp).ravel()
+    bw = [wN * B0[p][nb, na] for p in range(3)]          # weight of each term times the node value
+    for s in range(0, npts, chunk):
+        e = min(npts, s + chunk)
+        xi = xyz[0, s:e, None]
+        yi = xyz[1, s:e, None]
+        zi = xyz[2, s:e, None]
+        dx = gx[None, :] - xi
+        dy = gy[None, :] - yi
+        r2 = dx * dx + dy * dy + zi * zi
+        r = np.sqrt(r2)
+        z = zi[:, 0]
+        for p in range(3):
+            t = lam[p, s:e, None] * r
+            sn, cs = np.sin(t), np.cos(t)
+            N = t * sn + cs
+            F = N / (r2 * r)
+            Gd = (t * t * cs - 3.0 * N) / (r2 * r2 * r)
+            b = bw[p][None, :] / TWO_PI
+            B[p, s:e] = z * np.sum(F * b, axis=1)
+            dB[3 * p + 0, s:e] = -z * np.sum(Gd * dx * b, axis=1)
+            dB[3 * p + 1, s:e] = -z * np.sum(Gd * dy * b, axis=1)
+            dB[3 * p + 2, s:e] = np.sum((F + z[:, None] ** 2 * Gd) * b, axis=1)
+            if tangents:
+                dF = cs / (2.0 * r)
+                dG = -N / (2.0 * r2 * r)
+                tan[p, s:e] = z * np.sum(dF * b, axis=1)
+                tan[3 + 3 * p + 0, s:e] = -z * np.sum(dG * dx * b, axis=1)
+                tan[3 + 3 * p + 1, s:e] = -z * np.sum(dG * dy * b, axis=1)
+                tan[3 + 3 * p + 2, s:e] = np.sum((dF + z[:, None] ** 2 * dG) * b, axis=1)
+    if tangents:
+        return B, dB, tan
+    return B, dB
