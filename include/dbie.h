@@ -97,6 +97,11 @@ typedef struct {
     double dv_over_dsigma_h;     /* dV / dSigma of Eq. 9 in units of h (1/6: cube of side h) */
     int32_t tune;                /* 1: choose FP32C tile shapes by timing candidates at init */
     const char* tune_cache;      /* optional path of a text cache of tuned shapes (NULL: none) */
+    int32_t quad_points;         /* 0: nodal sum over the pixel centres, weight h^2 (Eq. 16).
+                                  * 2, 3 or 4: 9-node quadratic elements (Eq. 15), each element
+                                  * integral by quad_points x quad_points Gauss-Legendre points; every
+                                  * magnetogram then needs odd nx, ny >= 3 (element (m, n) holds the
+                                  * nodes 2m..2m+2 x 2n..2n+2). Elements need DBIE_FP64. */
 } dbie_options;
 
 typedef struct {
@@ -109,7 +114,7 @@ typedef struct {
     int32_t use_graph;    /* 1: replay the rounds from a captured HIP graph (bitwise the same results) */
 } dbie_solve_opts;
 
-/* Fill defaults: FP32C, radius 2, dV/dSigma = 1/6, no tuning / Nelder-Mead, 50 trials, eps 1e-4,
+/* Fill defaults: FP32C, radius 2, dV/dSigma = 1/6, no tuning, nodal sum / Nelder-Mead, 50 trials, eps 1e-4,
  * default step and cap, FP64 acceptance on, graph replay on. Return DBIE_OK, or DBIE_E_INVAL for NULL. */
 DBIE_API int dbie_default_options(dbie_options* opt);
 DBIE_API int dbie_default_solve_opts(dbie_solve_opts* opt);
@@ -168,10 +173,12 @@ DBIE_API int dbie_grad(dbie_ctx* ctx, const double* lambda, const double* gB, co
 DBIE_API int dbie_timing(dbie_ctx* ctx, int32_t enable);
 DBIE_API int dbie_timing_read(dbie_ctx* ctx, double* total_ms, int64_t* launches);
 
-/* Choose the FP32C tile shape (points per lane, waves per workgroup, pixels per LDS tile) for both
- * the plain pass and the pass with tangents. Only the shapes the library was built with are
- * accepted (DBIE_E_UNSUPPORTED otherwise; DBIE_E_UNSUPPORTED for an FP64 context). */
-DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int32_t tile_pixels);
+/* Choose the FP32C tile shape (points per lane, waves per workgroup, pixels per LDS block, and
+ * persistent != 0 for a persistent grid that pulls tiles from a device counter) for both the plain
+ * pass and the pass with tangents. Only the shapes the library was built with are accepted
+ * (DBIE_E_UNSUPPORTED otherwise; DBIE_E_UNSUPPORTED for an FP64 context). */
+DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int32_t tile_pixels,
+                                 int32_t persistent);
 
 /* Solve tracing (time to solution): with enable != 0, dbie_solve_lambda records a HIP event on its
  * stream at the start and after every round. dbie_solve_trace_read synchronises and returns, for
@@ -186,8 +193,10 @@ DBIE_API int dbie_solve_trace_read(dbie_ctx* ctx, double* t_ms, int32_t* converg
  * NULL. */
 DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixels, int32_t* ppl,
                         int32_t* waves, int32_t* tile_pixels);
-/* The tile shape of the FP32C pass with mu-tangents (the LM solver's pass). */
+/* The tile shape of the FP32C pass with mu-tangents (the LM solver's pass), and whether each pass
+ * runs in the persistent form. */
 DBIE_API int dbie_query_tan(const dbie_ctx* ctx, int32_t* ppl, int32_t* waves, int32_t* tile_pixels);
+DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t* with_tangents);
 
 DBIE_API void dbie_destroy(dbie_ctx* ctx);
 

@@ -27,6 +27,29 @@ hipError_t dalloc(T** p, size_t n) {
     return hipMalloc((void**)p, n * sizeof(T));
 }
 
+// Gauss-Legendre points and weights on [-1, 1]: Newton's method on P_n from the three-term recurrence
+// (n P_n = (2n - 1) x P_{n-1} - (n - 1) P_{n-2}), started at cos(pi (k + 3/4) / (n + 1/2)); the weight
+// is 2 / ((1 - x^2) P_n'(x)^2). Points ascending.
+void gauss_legendre(int n, double* x, double* w) {
+    for (int k = 0; k < n; ++k) {
+        double t = std::cos(M_PI * (k + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        x[n - 1 - k] = t;
+        w[n - 1 - k] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
 }  // namespace
 
 struct dbie_ctx {
@@ -39,6 +62,13 @@ struct dbie_ctx {
     std::vector<int64_t> seg;
     BoundaryDev* bnd_d = nullptr;
     double* B0d = nullptr;      // FP64 planes, concatenated per boundary
+    // quadrature grid of the FP64 path (BoundaryDev::gcols/grows): positions, and the weighted field
+    // (the B0 planes themselves for the nodal rule; a separate allocation for 9-node elements)
+    double* gpos = nullptr;
+    double* gB = nullptr;
+    double* qlw = nullptr;      // 9-node elements: lw[3 g + a] = w_g L_a(xi_g) (device, 3 G doubles)
+    int32_t G = 0;              // Gauss points per element side; 0 = nodal rule
+    int64_t ngrid_total = 0;
     float* pixf = nullptr;      // FP32 pixel blocks (Bx, By, Bz planes per block), FP32C only
     double* xyz = nullptr;
     Geo geo{};
@@ -55,8 +85,9 @@ struct dbie_ctx {
     int64_t n_tiles32 = 0;
     Tile* tiles32t = nullptr;    // static schedule of the FP32C pass with mu-tangents
     int64_t n_tiles32t = 0;
-    F32Shape shape{1, 8, kRows * kCols};
-    F32Shape shape_tan{1, 4, kRows * kCols};
+    F32Shape shape{1, 8, kRows * kCols, 0};
+    F32Shape shape_tan{1, 4, kRows * kCols, 0};
+    int32_t* work = nullptr;    // tile counter of the persistent FP32C form
     double* acc = nullptr;      // [L][kAcc][N]
     int64_t acc_L = 0;
     SolverState solver{};
@@ -89,7 +120,11 @@ int hip_fail(dbie_ctx* c, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
     } while (0)
 
-std::vector<Tile> build_schedule(const std::vector<int64_t>& seg, int32_t per_tile) {
+// Tiles of per_tile consecutive points of one boundary. With `cost` (pixels per boundary) the tiles
+// are ordered by decreasing work (points x pixels; ties by position), so that the workgroups
+// dispatched last are the cheapest ones.
+std::vector<Tile> build_schedule(const std::vector<int64_t>& seg, int32_t per_tile,
+                                 const std::vector<int64_t>* cost = nullptr) {
     std::vector<Tile> t;
     for (size_t b = 0; b + 1 < seg.size(); ++b) {
         for (int64_t s = seg[b]; s < seg[b + 1]; s += per_tile) {
@@ -100,6 +135,10 @@ std::vector<Tile> build_schedule(const std::vector<int64_t>& seg, int32_t per_ti
             t.push_back(x);
         }
     }
+    if (cost)
+        std::stable_sort(t.begin(), t.end(), [&](const Tile& x, const Tile& y) {
+            return (int64_t)x.count * (*cost)[x.b] > (int64_t)y.count * (*cost)[y.b];
+        });
     while (t.size() % 8 != 0 || t.empty()) t.push_back(Tile{0, 0, 0});
     return t;
 }
@@ -119,6 +158,9 @@ void free_ctx(dbie_ctx* c) {
     if (!c) return;
     (void)hipFree(c->bnd_d);
     (void)hipFree(c->B0d);
+    (void)hipFree(c->gpos);
+    if (c->gB != c->B0d) (void)hipFree(c->gB);
+    (void)hipFree(c->qlw);
     (void)hipFree(c->pixf);
     (void)hipFree(c->xyz);
     (void)hipFree(c->geo_block);
@@ -129,6 +171,7 @@ void free_ctx(dbie_ctx* c) {
     (void)hipFree(c->tiles64);
     (void)hipFree(c->tiles32);
     (void)hipFree(c->tiles32t);
+    (void)hipFree(c->work);
     (void)hipFree(c->acc);
     solver_free(c->solver);
     for (int k = 0; k < 4; ++k) (void)hipFree(c->scratch[k]);
@@ -143,7 +186,9 @@ void free_ctx(dbie_ctx* c) {
 
 int set_tiles32(dbie_ctx* c, F32Shape s, bool tan) {
     const int32_t per = s.ppl * s.waves * 64;
-    std::vector<Tile> t = build_schedule(c->seg, per);
+    std::vector<int64_t> cost;
+    for (const BoundaryDev& b : c->bnd_h) cost.push_back((int64_t)b.ntx * b.nty);
+    std::vector<Tile> t = build_schedule(c->seg, per, &cost);
     Tile* d = nullptr;
     DBIE_HIP(c, dalloc(&d, t.size()));
     DBIE_HIP(c, hipMemcpy(d, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
@@ -184,11 +229,11 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const int32_t* idx = set ? set->idx : nullptr;
     if (fp64)
         DBIE_HIP(c, launch_field64(set ? set->tiles64 : c->tiles64, set ? set->n_tiles64 : c->n_tiles64,
-                                   c->bnd_d, c->B0d, c->geo, lam, c->N, L, idx, tan, c->acc, s));
+                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, idx, tan, c->acc, s));
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
-                                    c->pixf, c->geo, lam, c->N, L, set ? idx : c->perm, set == nullptr, tan,
+                                    c->pixf, c->geo, lam, c->N, L, set ? idx : c->perm, c->work, tan,
                                     scalar, tan ? c->shape_tan : c->shape, c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
@@ -230,6 +275,7 @@ bool ctx_timing(const dbie_ctx* c) { return c->timing; }
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
+QuadGrid ctx_grid(const dbie_ctx* c) { return QuadGrid{c->gpos, c->gB, c->qlw, c->G, c->ngrid_total}; }
 int ctx_precision(const dbie_ctx* c) { return c->opt.precision; }
 double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
 SolverState& ctx_solver(dbie_ctx* c) { return c->solver; }
@@ -246,6 +292,7 @@ int dbie_default_options(dbie_options* o) {
     o->dv_over_dsigma_h = 1.0 / 6.0;
     o->tune = 0;
     o->tune_cache = nullptr;
+    o->quad_points = 0;
     return DBIE_OK;
 }
 
@@ -274,6 +321,10 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         return fail(nullptr, DBIE_E_INVAL, "nearfield_radius_h must lie in [0, 2]");
     if (!(o.dv_over_dsigma_h > 0.0) || !std::isfinite(o.dv_over_dsigma_h))
         return fail(nullptr, DBIE_E_INVAL, "dv_over_dsigma_h must be positive and finite");
+    if (o.quad_points != 0 && (o.quad_points < 2 || o.quad_points > 4))
+        return fail(nullptr, DBIE_E_INVAL, "quad_points must be 0 (nodal sum) or 2, 3, 4 (9-node elements)");
+    if (o.quad_points != 0 && o.precision != DBIE_FP64)
+        return fail(nullptr, DBIE_E_INVAL, "9-node elements (quad_points > 0) need DBIE_FP64");
     const int32_t nb = prob->n_boundaries;
     if (nb < 1 || !prob->boundaries) return fail(nullptr, DBIE_E_INVAL, "need at least one boundary");
     if (prob->n_points < 0) return fail(nullptr, DBIE_E_INVAL, "n_points < 0");
@@ -300,6 +351,8 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         if (!(bd.h > 0.0) || !std::isfinite(bd.h) || !std::isfinite(bd.x0) || !std::isfinite(bd.y0))
             return fail(nullptr, DBIE_E_INVAL, "boundary h must be positive; x0, y0, h finite");
         if (!bd.B0) return fail(nullptr, DBIE_E_INVAL, "boundary B0 is NULL");
+        if (o.quad_points && (bd.nx < 3 || bd.ny < 3 || bd.nx % 2 == 0 || bd.ny % 2 == 0))
+            return fail(nullptr, DBIE_E_INVAL, "9-node elements need odd nx, ny >= 3");
     }
 
     dbie_ctx* c = new dbie_ctx();
@@ -310,7 +363,12 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     c->seg = seg;
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetDevice(&c->device);
-    int64_t off = 0, offf = 0;
+    int64_t off = 0, offf = 0, goff = 0, gpoff = 0;
+    const int G = o.quad_points;
+    c->G = G;
+    double xg[4], wg[4];
+    if (G) gauss_legendre(G, xg, wg);
+    std::vector<double> gpos_h;
     for (int32_t b = 0; b < nb; ++b) {
         const dbie_boundary& bd = prob->boundaries[b];
         BoundaryDev d{};
@@ -325,11 +383,30 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         d.x0 = bd.x0;
         d.y0 = bd.y0;
         d.h = bd.h;
+        if (G) {
+            d.gcols = G * (bd.nx - 1) / 2;
+            d.grows = G * (bd.ny - 1) / 2;
+            d.gpl_off = goff;
+            goff += 3 * (int64_t)d.gcols * d.grows;
+        } else {
+            d.gcols = bd.nx;
+            d.grows = bd.ny;
+            d.gpl_off = off;
+        }
+        d.gpos_off = gpoff;
+        gpoff += d.gcols + d.grows;
+        // grid positions in pixels from node (0, 0): the nodes, or the Gauss points 2m + 1 + xi_g
+        for (int axis = 0; axis < 2; ++axis) {
+            const int32_t n = axis ? d.grows : d.gcols;
+            for (int32_t k = 0; k < n; ++k)
+                gpos_h.push_back(G ? (double)(2 * (k / G) + 1) + xg[k % G] : (double)k);
+        }
         off += 3 * (int64_t)d.npix;
         offf += 3 * (int64_t)d.npix_pad;
         c->bnd_h.push_back(d);
     }
     c->npix_total = off / 3;
+    c->ngrid_total = G ? goff / 3 : off / 3;
     auto bail = [&](int rc) {
         std::string m = c->err;
         free_ctx(c);
@@ -349,7 +426,29 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         DBIE_INIT_HIP(hipMemcpyAsync(c->B0d + c->bnd_h[b].pix_off, prob->boundaries[b].B0,
                                      3 * (size_t)c->bnd_h[b].npix * sizeof(double),
                                      hipMemcpyDeviceToDevice, s));
-    if (o.precision == DBIE_FP32C) DBIE_INIT_HIP(dalloc(&c->pixf, (size_t)offf));
+    DBIE_INIT_HIP(dalloc(&c->gpos, gpos_h.size()));
+    DBIE_INIT_HIP(hipMemcpy(c->gpos, gpos_h.data(), gpos_h.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (G) {
+        // weighted field at the Gauss points: w_g w_q sum_ab L_a(xi_g) L_b(xi_q) B0(node)
+        double lw[12];
+        for (int g = 0; g < G; ++g) {
+            const double x = xg[g];
+            lw[3 * g + 0] = wg[g] * 0.5 * x * (x - 1.0);
+            lw[3 * g + 1] = wg[g] * (1.0 - x) * (1.0 + x);
+            lw[3 * g + 2] = wg[g] * 0.5 * x * (x + 1.0);
+        }
+        DBIE_INIT_HIP(dalloc(&c->qlw, 3 * (size_t)G));
+        DBIE_INIT_HIP(hipMemcpy(c->qlw, lw, 3 * (size_t)G * sizeof(double), hipMemcpyHostToDevice));
+        DBIE_INIT_HIP(dalloc(&c->gB, (size_t)goff));
+        for (int32_t b = 0; b < nb; ++b)
+            DBIE_INIT_HIP(launch_quad_weights(c->bnd_h[b], c->B0d, c->qlw, G, c->gB, s));
+    } else {
+        c->gB = c->B0d;
+    }
+    if (o.precision == DBIE_FP32C) {
+        DBIE_INIT_HIP(dalloc(&c->pixf, (size_t)offf));
+        DBIE_INIT_HIP(dalloc(&c->work, 1));
+    }
     const int64_t N = c->N;
     const size_t Nn = (size_t)std::max<int64_t>(N, 1);
     DBIE_INIT_HIP(dalloc(&c->xyz, 3 * Nn));
@@ -521,10 +620,10 @@ int dbie_query(const dbie_ctx* c, int64_t* n_points, int64_t* n_pixels, int32_t*
     return DBIE_OK;
 }
 
-int dbie_set_tile_shape(dbie_ctx* c, int32_t ppl, int32_t waves, int32_t tile_pixels) {
+int dbie_set_tile_shape(dbie_ctx* c, int32_t ppl, int32_t waves, int32_t tile_pixels, int32_t persistent) {
     if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
     if (c->opt.precision != DBIE_FP32C) return fail(c, DBIE_E_UNSUPPORTED, "tile shapes apply to FP32C contexts");
-    const F32Shape sh{ppl, waves, tile_pixels};
+    const F32Shape sh{ppl, waves, tile_pixels, persistent};
     int rc = dbie::set_shape(c, sh, false);
     if (!rc) rc = dbie::set_shape(c, sh, true);
     return rc;
@@ -532,6 +631,7 @@ int dbie_set_tile_shape(dbie_ctx* c, int32_t ppl, int32_t waves, int32_t tile_pi
 
 int dbie_query_tan(const dbie_ctx* c, int32_t* ppl, int32_t* waves, int32_t* tile_pixels) {
     if (!c) return DBIE_E_INVAL;
+    // (whether either pass is persistent is reported by dbie_query_persistent)
     if (ppl) *ppl = c->shape_tan.ppl;
     if (waves) *waves = c->shape_tan.waves;
     if (tile_pixels) *tile_pixels = c->shape_tan.tp;
@@ -562,6 +662,13 @@ int dbie_solve_trace_read(dbie_ctx* c, double* t_ms, int32_t* converged, int32_t
     return DBIE_OK;
 }
 
+int dbie_query_persistent(const dbie_ctx* c, int32_t* plain, int32_t* with_tangents) {
+    if (!c) return DBIE_E_INVAL;
+    if (plain) *plain = c->shape.persist;
+    if (with_tangents) *with_tangents = c->shape_tan.persist;
+    return DBIE_OK;
+}
+
 void dbie_destroy(dbie_ctx* c) { free_ctx(c); }
 
 const char* dbie_last_error(const dbie_ctx* c) {
@@ -580,7 +687,7 @@ F32Shape get_shape(const dbie_ctx* c, bool tan) { return tan ? c->shape_tan : c-
 
 // Time every instantiated shape on this problem (one full evaluation each, after a warm-up) and keep
 // the fastest, separately for the plain pass and the pass with tangents. The optional cache is a
-// text file of lines "<n_points> <n_pixels> <tan> <ppl> <waves> <tile_pixels>".
+// text file of lines "<n_points> <n_pixels> <tan> <ppl> <waves> <tile_pixels> <persistent>".
 int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s) {
     if (c->N == 0) return DBIE_OK;
     for (int tan = 0; tan < 2; ++tan) {
@@ -589,10 +696,10 @@ int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s) {
             FILE* f = fopen(cache_path, "r");
             if (f) {
                 long long n, p;
-                int t, a, b, d;
-                while (fscanf(f, "%lld %lld %d %d %d %d", &n, &p, &t, &a, &b, &d) == 6) {
-                    if (n == c->N && p == c->npix_total && t == tan && field32c_shape_supported(F32Shape{a, b, d})) {
-                        int rc = set_tiles32(c, F32Shape{a, b, d}, tan != 0);
+                int t, a, b, d, e;
+                while (fscanf(f, "%lld %lld %d %d %d %d %d", &n, &p, &t, &a, &b, &d, &e) == 7) {
+                    if (n == c->N && p == c->npix_total && t == tan && field32c_shape_supported(F32Shape{a, b, d, e})) {
+                        int rc = set_tiles32(c, F32Shape{a, b, d, e}, tan != 0);
                         if (rc) { fclose(f); return rc; }
                         cached = true;
                     }
@@ -640,8 +747,8 @@ int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s) {
         if (cache_path) {
             FILE* f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%lld %lld %d %d %d %d\n", (long long)c->N, (long long)c->npix_total, tan, bs.ppl,
-                        bs.waves, bs.tp);
+                fprintf(f, "%lld %lld %d %d %d %d %d\n", (long long)c->N, (long long)c->npix_total, tan, bs.ppl,
+                        bs.waves, bs.tp, bs.persist);
                 fclose(f);
             }
         }

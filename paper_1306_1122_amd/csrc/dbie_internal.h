@@ -31,6 +31,12 @@ constexpr int kCols = 8;
 struct BoundaryDev {
     int32_t nx, ny;
     int32_t npix;       // nx * ny
+    // Quadrature grid of the FP64 path: gcols x grows points at the positions gpos[gpos_off + c]
+    // (columns) and gpos[gpos_off + gcols + r] (rows), in pixels from node (0, 0), carrying the
+    // weighted field gB[gpl_off + p * gcols * grows + r * gcols + c]. For the nodal rule (Eq. 16) it
+    // is the pixel grid itself; for 9-node elements (Eq. 15) the Gauss points of the elements.
+    int32_t gcols, grows;
+    int64_t gpos_off, gpl_off;
     int32_t ntx, nty;   // FP32C pixel blocks along x and y (ceil(nx / kCols), ceil(ny / kRows))
     int32_t npix_pad;   // ntx * nty * kRows * kCols
     int64_t pix_off;    // offset of this boundary in the FP64 planes (3 planes of npix each)
@@ -189,20 +195,29 @@ hipError_t launch_expand_scalar(const double* lam, int32_t L, int64_t N, double*
 // The bulk kernels run over a schedule of tiles. Without `idx` a tile is a run of point indices;
 // with `idx` it is a run of entries of the active-point list idx (device schedules of the solver).
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
-                          const double* B0d, Geo geo, const double* lam, int64_t N, int32_t L,
-                          const int32_t* idx, bool tan, double* acc, hipStream_t s);
+                          const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
+                          int32_t L, const int32_t* idx, bool tan, double* acc, hipStream_t s);
+
+// The weighted field of the 9-node element quadrature grid: gB = w_g w_q sum L_a(xi_g) L_b(xi_q) B0
+// (lw[3 * g + a] = w_g L_a(xi_g), G points per element side).
+hipError_t launch_quad_weights(const BoundaryDev& bd, const double* B0d, const double* lw, int G, double* gB,
+                               hipStream_t s);
+// Transpose of the interpolation: gradient at the nodes from the gradient at the grid points.
+hipError_t launch_quad_transpose(const BoundaryDev& bd, const double* gW, const double* lw, int G, double* gB0,
+                                 hipStream_t s);
 
 struct F32Shape {
-    int32_t ppl;     // points per lane
-    int32_t waves;   // waves per workgroup
-    int32_t tp;      // pixels per LDS tile
+    int32_t ppl;      // points per lane
+    int32_t waves;    // waves per workgroup
+    int32_t tp;       // pixels per LDS block
+    int32_t persist;  // 1: persistent grid pulling tiles from a device counter
 };
 
-// remap_xcd: deal contiguous runs of the schedule to the 8 XCDs (static schedules). scalar: the
-// three lambda rows of every point are equal (the kernel reads row 0 only).
+// work: a device int the persistent form uses as its tile counter (cleared by a kernel inside the
+// launch). scalar: the three lambda rows of every point are equal (the kernel reads row 0 only).
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, bool remap_xcd, bool tan, bool scalar, F32Shape shape,
+                           const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape shape,
                            double* acc, hipStream_t s);
 bool field32c_shape_supported(F32Shape shape);
 int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number

@@ -61,6 +61,14 @@ const int32_t* ctx_perm(const dbie_ctx* c);   // FP32C point order or NULL (iden
 int32_t ctx_nb(const dbie_ctx* c);
 const int64_t* ctx_seg(const dbie_ctx* c);
 const double* ctx_B0d(const dbie_ctx* c);
+struct QuadGrid {
+    const double* pos;   // grid positions (BoundaryDev::gpos_off)
+    const double* gB;    // weighted field on the grid (BoundaryDev::gpl_off)
+    const double* lw;    // 9-node elements: w_g L_a(xi_g), 3 G doubles; NULL for the nodal rule
+    int32_t G;           // Gauss points per element side; 0 = nodal rule
+    int64_t n_total;     // grid points over all boundaries
+};
+QuadGrid ctx_grid(const dbie_ctx* c);
 int ctx_precision(const dbie_ctx* c);
 double ctx_dvds(const dbie_ctx* c);
 SolverState& ctx_solver(dbie_ctx* c);

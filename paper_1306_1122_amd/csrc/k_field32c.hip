@@ -1,7 +1,7 @@
 // FP32 bulk kernel sum with compensated accumulation (the FP32C path).
 //
-// Work decomposition: one workgroup per schedule tile (<= PPL * 64 * WAVES points of one
-// magnetogram) and one grid row per lambda trial. Lane l of the workgroup owns points l, l + NT, ...
+// Work decomposition: one schedule tile (<= PPL * 64 * WAVES points of one magnetogram) at a time
+// per workgroup, one grid row per lambda trial; static schedules are ordered by decreasing cost. Lane l of the workgroup owns points l, l + NT, ...
 // of the tile, so a wavefront holds 64 consecutive points (the library orders points so that these
 // are spatially coherent). The magnetogram streams through LDS in blocks of kRows x kCols pixels
 // (three planes Bx, By, Bz, tile-major in HBM); every lane reads the same LDS address (broadcast).
@@ -20,6 +20,7 @@
 // Near field: pairs whose (FP64-classified) distance is below the near radius are skipped here and
 // summed in FP64 by the finalize pass. Blocks that cannot contain such a pair for any point of the
 // wavefront take the unmasked loop; the test is uniform over the wavefront.
+#include <algorithm>
 #include <climits>
 
 #include "dbie_internal.h"
@@ -155,26 +156,16 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
     }
 }
 
+// One schedule tile: the sums of its points over every pixel block of their magnetogram.
 template <int PPL, int WAVES, bool TAN, bool SCALAR>
-__global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
-                                                         int64_t n_tiles,
-                                                         const BoundaryDev* __restrict__ bnd,
-                                                         const float* __restrict__ pixf, Geo geo,
-                                                         const double* __restrict__ lam, int64_t N,
-                                                         const int32_t* __restrict__ idx, int xcd_remap,
-                                                         double* __restrict__ acc) {
+__device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* __restrict__ bnd,
+                                              const float* __restrict__ pixf, const Geo& geo,
+                                              const double* __restrict__ lam, int64_t N,
+                                              const int32_t* __restrict__ idx, double* __restrict__ acc,
+                                              float4 (*sB)[kRows][kCols / 4]) {
     constexpr int NT = 64 * WAVES;
     constexpr int NA = TAN ? kAcc : kAccField;
     constexpr int BQ = kRows * kCols / 4;   // float4 per plane of a block
-    __shared__ float4 sB[3][kRows][kCols / 4];
-
-    // XCD-aware order (static schedules): workgroups are dealt round-robin to the 8 XCDs; give each
-    // XCD a contiguous run of the schedule so that its L2 sees few magnetograms. Schedules are padded
-    // to a multiple of 8 tiles (empty tiles have count 0), which makes this remap a permutation.
-    // Schedules built on the device over an active-point list keep the identity order.
-    const int64_t per = (int64_t)gridDim.x / 8;
-    const int64_t bx = blockIdx.x;
-    const Tile t = tiles[xcd_remap ? (bx & 7) * per + (bx >> 3) : bx];
     if (t.count == 0) return;
     const int64_t trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
@@ -283,6 +274,34 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
     }
 }
 
+// Either one workgroup per tile (work == NULL), or persistent: a grid sized to the resident
+// workgroups pulls tile indices from the device counter `work` (cleared by a kernel before the
+// launch) until the schedule is exhausted; every workgroup reaches the exit test after each tile.
+template <int PPL, int WAVES, bool TAN, bool SCALAR>
+__global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
+                                                         int64_t n_tiles,
+                                                         const BoundaryDev* __restrict__ bnd,
+                                                         const float* __restrict__ pixf, Geo geo,
+                                                         const double* __restrict__ lam, int64_t N,
+                                                         const int32_t* __restrict__ idx,
+                                                         int32_t* __restrict__ work,
+                                                         double* __restrict__ acc) {
+    __shared__ float4 sB[3][kRows][kCols / 4];
+    if (!work) {
+        field32c_tile<PPL, WAVES, TAN, SCALAR>(tiles[blockIdx.x], bnd, pixf, geo, lam, N, idx, acc, sB);
+        return;
+    }
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(work, 1);
+        __syncthreads();
+        const int64_t ti = next;
+        __syncthreads();
+        if (ti >= n_tiles) break;
+        field32c_tile<PPL, WAVES, TAN, SCALAR>(tiles[ti], bnd, pixf, geo, lam, N, idx, acc, sB);
+    }
+}
+
 // The instantiated shapes (points per lane, waves per workgroup); the pixel block is kRows x kCols.
 // (shapes whose tangent variant would spill registers to scratch are left out)
 #define DBIE_F32_SHAPES(X) \
@@ -293,15 +312,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
 
 int field32c_shapes(F32Shape* out, int max) {
     int n = 0;
-#define DBIE_LIST(P, W)                                  \
-    if (n < max) out[n] = F32Shape{P, W, kRows * kCols}; \
-    ++n;
-    DBIE_F32_SHAPES(DBIE_LIST)
+    for (int persist = 0; persist < 2; ++persist) {
+#define DBIE_LIST(P, W)                                           \
+        if (n < max) out[n] = F32Shape{P, W, kRows * kCols, persist}; \
+        ++n;
+        DBIE_F32_SHAPES(DBIE_LIST)
 #undef DBIE_LIST
+    }
     return n;
 }
 
 bool field32c_shape_supported(F32Shape s) {
+    if (s.persist != 0 && s.persist != 1) return false;
 #define DBIE_CHK(P, W) \
     if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) return true;
     DBIE_F32_SHAPES(DBIE_CHK)
@@ -309,30 +331,50 @@ bool field32c_shape_supported(F32Shape s) {
     return false;
 }
 
+__global__ void k_clear_work(int32_t* __restrict__ w) { *w = 0; }
+
+template <int P, int W, bool T, bool SC>
+static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
+                             Geo geo, const double* lam, int64_t N, int32_t L, const int32_t* idx,
+                             int32_t* work, double* acc, hipStream_t st) {
+    unsigned gx = (unsigned)n_tiles;
+    if (work) {
+        // resident workgroups of this kernel on the device
+        static int per_cu = 0, cus = 0;
+        if (per_cu == 0) {
+            int dev = 0, nb = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field32c<P, W, T, SC>, 64 * W, 0);
+            per_cu = nb > 0 ? nb : 1;
+            if (cus <= 0) cus = 1;
+        }
+        gx = (unsigned)std::min<int64_t>(n_tiles, (int64_t)per_cu * cus);
+        hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(1), 0, st, work);
+    }
+    hipLaunchKernelGGL((k_field32c<P, W, T, SC>), dim3(gx, (unsigned)L), dim3(64 * W), 0, st, tiles, n_tiles, bnd,
+                       pixf, geo, lam, N, idx, work, acc);
+    return hipGetLastError();
+}
+
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, bool remap_xcd, bool tan, bool scalar, F32Shape s,
+                           const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape s,
                            double* acc, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
-    const int remap = remap_xcd ? 1 : 0;
-    const dim3 grid((unsigned)n_tiles, (unsigned)L);
-#define DBIE_LAUNCH_ONE(P, W, T, SC)                                                                 \
-    hipLaunchKernelGGL((k_field32c<P, W, T, SC>), grid, dim3(64 * W), 0, st, tiles, n_tiles, bnd, pixf, geo, \
-                       lam, N, idx, remap, acc)
-#define DBIE_LAUNCH(P, W)                                                 \
-    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {            \
-        if (tan) {                                                        \
-            if (scalar) DBIE_LAUNCH_ONE(P, W, true, true);                \
-            else DBIE_LAUNCH_ONE(P, W, true, false);                      \
-        } else {                                                          \
-            if (scalar) DBIE_LAUNCH_ONE(P, W, false, true);               \
-            else DBIE_LAUNCH_ONE(P, W, false, false);                     \
-        }                                                                 \
-        return hipGetLastError();                                         \
+    // a persistent launch with L trials would share one counter between the grid rows
+    int32_t* w = (s.persist && L == 1) ? work : nullptr;
+#define DBIE_LAUNCH(P, W)                                                                                  \
+    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {                                             \
+        if (tan) {                                                                                         \
+            if (scalar) return launch_one<P, W, true, true>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st); \
+            return launch_one<P, W, true, false>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st);           \
+        }                                                                                                  \
+        if (scalar) return launch_one<P, W, false, true>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st);   \
+        return launch_one<P, W, false, false>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st);              \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)
 #undef DBIE_LAUNCH
-#undef DBIE_LAUNCH_ONE
     return hipErrorInvalidValue;
 }
 

@@ -1,5 +1,6 @@
-// FP64 bulk kernel sum (every pair in FP64): the Eq. (16) nodal sum of the Eq. (6) kernel and its
-// frozen-lambda gradient rows (Eq. 13 limit), optionally with the mu-tangent rows.
+// FP64 bulk kernel sum (every pair in FP64): the Eq. (16) nodal sum of the Eq. (6) kernel (or the
+// Eq. (15) element quadrature, over its grid of Gauss points) and its frozen-lambda gradient rows
+// (Eq. 13 limit), optionally with the mu-tangent rows.
 //
 // Grid: one workgroup per schedule tile (a run of <= tile points of one magnetogram) and one
 // grid row per lambda trial. Each lane owns one point; the magnetogram streams through LDS in
@@ -14,7 +15,8 @@ constexpr int kTP64 = 128;
 template <bool TAN>
 __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
                                                  const BoundaryDev* __restrict__ bnd,
-                                                 const double* __restrict__ B0d, Geo geo,
+                                                 const double* __restrict__ gpos,
+                                                 const double* __restrict__ gB, Geo geo,
                                                  const double* __restrict__ lam, int64_t N,
                                                  const int32_t* __restrict__ idx,
                                                  double* __restrict__ acc) {
@@ -23,8 +25,10 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
     const Tile t = tiles[blockIdx.x];
     const int trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
-    const double* B0 = B0d + bd.pix_off;
-    const int32_t npix = bd.npix;
+    const double* B0 = gB + bd.gpl_off;
+    const double* cpos = gpos + bd.gpos_off;
+    const double* rpos = cpos + bd.gcols;
+    const int32_t npix = bd.gcols * bd.grows;
     for (int c0 = 0; c0 < t.count; c0 += blockDim.x) {
         const int j = c0 + (int)threadIdx.x;
         const bool live = j < t.count;
@@ -43,8 +47,8 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
             __syncthreads();
             for (int k = threadIdx.x; k < kn; k += blockDim.x) {
                 const int kk = k0 + k;
-                sa[k] = (double)(kk % bd.nx);
-                sb[k] = (double)(kk / bd.nx);
+                sa[k] = cpos[kk % bd.gcols];
+                sb[k] = rpos[kk / bd.gcols];
                 sx[k] = B0[kk];
                 sy[k] = B0[npix + kk];
                 sz[k] = B0[2 * npix + kk];
@@ -66,14 +70,14 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
 }
 
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
-                          const double* B0d, Geo geo, const double* lam, int64_t N, int32_t L,
-                          const int32_t* idx, bool tan, double* acc, hipStream_t s) {
+                          const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
+                          int32_t L, const int32_t* idx, bool tan, double* acc, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)n_tiles, (unsigned)L);
     if (tan)
-        hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, idx, acc);
+        hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx, acc);
     else
-        hipLaunchKernelGGL(k_field64<false>, grid, dim3(256), 0, s, tiles, bnd, B0d, geo, lam, N, idx, acc);
+        hipLaunchKernelGGL(k_field64<false>, grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx, acc);
     return hipGetLastError();
 }
 

@@ -108,3 +108,67 @@ hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bn
 }
 
 }  // namespace dbie
+
+namespace dbie {
+
+// Weighted field at the element Gauss points: column c = G m + g, row r = G n + q of element
+// (m, n) whose nodes are a = 2m..2m+2, b = 2n..2n+2.
+__global__ void k_quad_weights(BoundaryDev bd, const double* __restrict__ B0d, const double* __restrict__ lw,
+                               int G, double* __restrict__ gB) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gn = (int64_t)bd.gcols * bd.grows;
+    if (e >= gn) return;
+    const int c = (int)(e % bd.gcols), r = (int)(e / bd.gcols);
+    const int m = c / G, g = c - m * G, n = r / G, q = r - n * G;
+    for (int p = 0; p < 3; ++p) {
+        const double* B = B0d + bd.pix_off + (int64_t)p * bd.npix;
+        double acc = 0.0;
+        for (int be = 0; be < 3; ++be)
+            for (int al = 0; al < 3; ++al)
+                acc += lw[3 * g + al] * lw[3 * q + be] * B[(int64_t)(2 * n + be) * bd.nx + 2 * m + al];
+        gB[bd.gpl_off + p * gn + e] = acc;
+    }
+}
+
+// gB0 at node (a, b) = sum over the (up to 4) elements holding it and their Gauss points of the
+// interpolation weight times the gradient at the point.
+__global__ void k_quad_transpose(BoundaryDev bd, const double* __restrict__ gW, const double* __restrict__ lw,
+                                 int G, double* __restrict__ gB0) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= bd.npix) return;
+    const int a = (int)(k % bd.nx), b = (int)(k / bd.nx);
+    const int64_t gn = (int64_t)bd.gcols * bd.grows;
+    const int ex = (bd.nx - 1) / 2, ey = (bd.ny - 1) / 2;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int m = max(0, (a - 1) / 2); m <= min(ex - 1, a / 2); ++m) {
+        const int al = a - 2 * m;
+        if (al < 0 || al > 2) continue;
+        for (int n = max(0, (b - 1) / 2); n <= min(ey - 1, b / 2); ++n) {
+            const int be = b - 2 * n;
+            if (be < 0 || be > 2) continue;
+            for (int q = 0; q < G; ++q)
+                for (int g = 0; g < G; ++g) {
+                    const double wgt = lw[3 * g + al] * lw[3 * q + be];
+                    const int64_t e = (int64_t)(G * n + q) * bd.gcols + G * m + g;
+                    for (int p = 0; p < 3; ++p) acc[p] += wgt * gW[bd.gpl_off + p * gn + e];
+                }
+        }
+    }
+    for (int p = 0; p < 3; ++p) gB0[bd.pix_off + (int64_t)p * bd.npix + k] = acc[p];
+}
+
+hipError_t launch_quad_weights(const BoundaryDev& bd, const double* B0d, const double* lw, int G, double* gB,
+                               hipStream_t s) {
+    const int64_t gn = (int64_t)bd.gcols * bd.grows;
+    hipLaunchKernelGGL(k_quad_weights, dim3((unsigned)((gn + 255) / 256)), dim3(256), 0, s, bd, B0d, lw, G, gB);
+    return hipGetLastError();
+}
+
+hipError_t launch_quad_transpose(const BoundaryDev& bd, const double* gW, const double* lw, int G, double* gB0,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_quad_transpose, dim3((unsigned)((bd.npix + 255) / 256)), dim3(256), 0, s, bd, gW, lw, G,
+                       gB0);
+    return hipGetLastError();
+}
+
+}  // namespace dbie

@@ -7,6 +7,8 @@
 //   gx_p = -w gX_p / (2pi h),                  gy_p = -w gY_p / (2pi h)
 // (gX, gY, gZ = dLoss/d(dB_p/dx, dy, dz)),
 //   gB0_p(k) = sum_i [ N rho^-3 alpha_p + H rho^-5 (beta_p + gx_p (a_k - u_i) + gy_p (b_k - v_i)) ].
+// With 9-node elements (Eq. 15) the FP64 transpose runs over the Gauss points (positions a_k, b_k
+// of the quadrature grid) and the interpolation transpose then carries it to the nodes.
 // Pixels are the outputs; the points of the pixel's magnetogram stream through LDS in tiles. Every
 // output is written by exactly one lane: deterministic, no atomics. FP64 in an FP64 context; in an
 // FP32C context the far pairs in FP32 (cascaded into FP64) and the near pairs in FP64.
@@ -50,14 +52,16 @@ __global__ void k_vjp_coef(int64_t N, const BoundaryDev* __restrict__ bnd, Geo g
 __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptiles,
                                                const BoundaryDev* __restrict__ bnd,
                                                const int64_t* __restrict__ seg, Geo geo, int64_t N,
-                                               const double* __restrict__ coef, double* __restrict__ gB0) {
+                                               const double* __restrict__ gpos,
+                                               const double* __restrict__ coef, double* __restrict__ gW) {
     __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef][kVjpPts];
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
+    const int32_t ngrid = bd.gcols * bd.grows;
     const int32_t k = pt.start + (int32_t)threadIdx.x;
-    const bool live = k < bd.npix;
-    const double a = live ? (double)(k % bd.nx) : 0.0;
-    const double bb = live ? (double)(k / bd.nx) : 0.0;
+    const bool live = k < ngrid;
+    const double a = live ? gpos[bd.gpos_off + k % bd.gcols] : 0.0;
+    const double bb = live ? gpos[bd.gpos_off + bd.gcols + k / bd.gcols] : 0.0;
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t p0 = seg[pt.b], p1 = seg[pt.b + 1];
     for (int64_t i0 = p0; i0 < p1; i0 += kVjpPts) {
@@ -98,8 +102,8 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
         for (int p = 0; p < 3; ++p) acc[p] += part[p];
     }
     if (live) {
-        const int64_t o = bd.pix_off + k;
-        for (int p = 0; p < 3; ++p) gB0[o + (int64_t)p * bd.npix] = acc[p];
+        const int64_t o = bd.gpl_off + k;
+        for (int p = 0; p < 3; ++p) gW[o + (int64_t)p * ngrid] = acc[p];
     }
 }
 
@@ -320,20 +324,23 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
     }
     if (gB0) {
         // pixel tiles of every boundary, and the point segments on the device
+        const QuadGrid grid = ctx_grid(c);
         std::vector<PixTile> pt, pt32;
         for (int32_t b = 0; b < nb; ++b) {
             const BoundaryDev& bd = ctx_bnd_host(c, b);
-            for (int32_t k = 0; k < bd.npix; k += 256) pt.push_back(PixTile{b, k});
+            for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256) pt.push_back(PixTile{b, k});
             for (int32_t k = 0; k < bd.npix; k += 256 * kVjpPix) pt32.push_back(PixTile{b, k});
         }
         const size_t szc = (size_t)std::max<int64_t>(N, 1) * kVjpCoef * sizeof(double);
         const size_t szt = ((pt.size() + pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
         const size_t szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
-        char* w = (char*)ctx_scratch(c, 1, szc + szt + szs);
+        const size_t szg = grid.G ? (size_t)grid.n_total * 3 * sizeof(double) : 0;
+        char* w = (char*)ctx_scratch(c, 1, szc + szt + szs + szg);
         if (!w) return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the adjoint workspace");
         double* coef = (double*)w;
         PixTile* ptd = (PixTile*)(w + szc);
         int64_t* segd = (int64_t*)(w + szc + szt);
+        double* gW = grid.G ? (double*)(w + szc + szt + szs) : gB0;
         PixTile* ptd32 = ptd + pt.size();
         GRAD_HIP(hipMemcpyAsync(ptd, pt.data(), pt.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
         GRAD_HIP(hipMemcpyAsync(ptd32, pt32.data(), pt32.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
@@ -341,8 +348,11 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
         if (N > 0)
             hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
         if (ctx_precision(c) == DBIE_FP64) {
-            hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N, coef,
-                               gB0);
+            hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N,
+                               grid.pos, coef, gW);
+            if (grid.G)
+                for (int32_t b = 0; b < nb; ++b)
+                    GRAD_HIP(launch_quad_transpose(ctx_bnd_host(c, b), gW, grid.lw, grid.G, gB0, s));
         } else {
             hipLaunchKernelGGL(k_vjp32c<kVjpPix>, dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32, bnd, segd,
                                ctx_perm(c), geo, N, coef, gB0);

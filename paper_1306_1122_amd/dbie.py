@@ -93,8 +93,10 @@ def dbie_default_solve_opts() -> L.dbie_solve_opts:
 def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[int]] = None,
               precision: str = "fp32c", nearfield_radius_h: float = 2.0,
               dv_over_dsigma_h: float = 1.0 / 6.0, tune: bool = False,
-              tune_cache: Optional[str] = None, stream=None) -> Context:
-    """boundaries: list of dict(B0=[3, ny, nx] float64 CUDA tensor, x0=, y0=, h=); xyz: [3, N]."""
+              tune_cache: Optional[str] = None, quad_points: int = 0, stream=None) -> Context:
+    """boundaries: list of dict(B0=[3, ny, nx] float64 CUDA tensor, x0=, y0=, h=); xyz: [3, N].
+    quad_points = 0 selects the nodal sum (Eq. 16); 2..4 the 9-node elements of Eq. (15) with that many
+    Gauss points per element side."""
     lib = _lib()
     nb = len(boundaries)
     arr = (L.dbie_boundary * nb)()
@@ -127,6 +129,7 @@ def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[
     opt.dv_over_dsigma_h = float(dv_over_dsigma_h)
     opt.tune = int(bool(tune))
     opt.tune_cache = tune_cache.encode() if tune_cache else None
+    opt.quad_points = int(quad_points)
     h = ctypes.c_void_p()
     rc = lib.dbie_init(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), _stream(stream))
     if rc != L.DBIE_OK:
@@ -268,9 +271,15 @@ def dbie_query_tan(ctx: Context) -> Dict[str, int]:
     return dict(ppl=p.value, waves=w.value, tile_pixels=t.value)
 
 
-def dbie_set_tile_shape(ctx: Context, ppl: int, waves: int, tile_pixels: int):
-    _check(_lib().dbie_set_tile_shape(ctx.handle, int(ppl), int(waves), int(tile_pixels)), ctx,
-           "dbie_set_tile_shape")
+def dbie_set_tile_shape(ctx: Context, ppl: int, waves: int, tile_pixels: int, persistent: bool = False):
+    _check(_lib().dbie_set_tile_shape(ctx.handle, int(ppl), int(waves), int(tile_pixels), int(bool(persistent))),
+           ctx, "dbie_set_tile_shape")
+
+
+def dbie_query_persistent(ctx: Context) -> Dict[str, bool]:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib().dbie_query_persistent(ctx.handle, ctypes.byref(a), ctypes.byref(b)), ctx, "dbie_query_persistent")
+    return dict(plain=bool(a.value), with_tangents=bool(b.value))
 
 
 def dbie_solve_trace(ctx: Context, enable: bool = True):

@@ -45,6 +45,7 @@ def test_defaults(lib):
     assert lib.dbie_default_options(ctypes.byref(o)) == 0
     assert o.precision == L.DBIE_FP32C and o.nearfield_radius_h == 2.0
     assert abs(o.dv_over_dsigma_h - 1 / 6) < 1e-16
+    assert o.quad_points == 0
     s = L.dbie_solve_opts()
     assert lib.dbie_default_solve_opts(ctypes.byref(s)) == 0
     assert s.max_trials == 50 and s.eps == 1e-4 and s.method == L.DBIE_NELDER_MEAD
@@ -80,6 +81,9 @@ def _problem(nx=4, ny=3, h=1.0, n=5, nb=1, seg=None):
     ("seg_missing", "seg is required"),
     ("seg_order", "non-decreasing"),
     ("seg_end", "end at n_points"),
+    ("quad_points", "quad_points must be"),
+    ("quad_fp32c", "need DBIE_FP64"),
+    ("quad_even", "odd nx, ny"),
 ])
 def test_init_argument_checks(lib, case, msg):
     p, keep = _problem()
@@ -112,6 +116,12 @@ def test_init_argument_checks(lib, case, msg):
     elif case == "seg_end":
         p, keep = _problem(nb=2, seg=[0, 2, 4])
         args[1] = ctypes.byref(p)
+    elif case == "quad_points":
+        o.precision, o.quad_points = L.DBIE_FP64, 1
+    elif case == "quad_fp32c":
+        o.quad_points = 2
+    elif case == "quad_even":
+        o.precision, o.quad_points = L.DBIE_FP64, 4   # the default magnetogram is 4 x 3
     rc = lib.dbie_init(*args)
     assert rc == L.DBIE_E_INVAL
     assert msg in lib.dbie_last_error(None).decode()

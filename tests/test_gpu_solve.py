@@ -169,3 +169,28 @@ def test_graph_replay_equals_eager_rounds(method, prec):
         torch.cuda.synchronize()
         for k in ("lam", "status", "trials", "B", "fg"):
             assert torch.equal(eager[k], graph[k]), (rep, k)
+
+
+def test_lowlou_comparison_metrics_are_reported():
+    """DBIE on the Low & Lou boundary against the exact field at the 512 interior points, with the
+    comparison metrics of Schrijver et al. (2006): C_vec, C_cs, E'_n, E'_m, eps. Reported, not gated
+    (boundary truncation, quadrature and lambda non-uniqueness): parity unpinned. Sanity only: the
+    field points the right way on average and the searches improve on lambda = 0."""
+    w = config1()
+    ll = w.meta["ll"]
+    exact = ll.field(*w.xyz)
+    rows = {}
+    for name, prec, meth, bud in (("lambda=0", "fp64", None, 0), ("FP64 Nelder-Mead", "fp64", "nm", 50),
+                                  ("FP32C Levenberg-Marquardt", "fp32c", "lm", 20)):
+        _, bd, ctx = lowlou_ctx(prec)
+        lam = torch.zeros(3, w.n_points, dtype=torch.float64, device="cuda:0")
+        if meth is None:
+            B = D.dbie_eval_field(ctx, lam)["B"]
+        else:
+            B = D.dbie_solve_lambda(ctx, lam, method=meth, max_trials=bud)["B"]
+        torch.cuda.synchronize()
+        rows[name] = oracle.schrijver_metrics(exact, B.cpu().numpy())
+    for name, m in rows.items():
+        print(name, {k: round(v, 3) for k, v in m.items()}, flush=True)
+    for m in rows.values():
+        assert m["C_vec"] > 0.5 and m["C_cs"] > 0.0

@@ -116,3 +116,24 @@ def test_tuner_picks_an_instantiated_shape_and_results_do_not_change():
     assert D.dbie_query(ctx)["ppl"] == 1 and D.dbie_query(ctx)["waves"] == 8
     with pytest.raises(D.DbieError, match="not instantiated"):
         D.dbie_set_tile_shape(ctx, 3, 4, 256)
+
+
+def test_persistent_form_equals_grid_launch(batched):
+    """The persistent grid (tiles pulled from a device counter) and one workgroup per tile compute
+    every tile identically: bitwise equal outputs, for evaluation and for a solve."""
+    w = batched
+    keep = 12
+    seg = w.seg[: keep + 1]
+    bds = [dict(B0=T(b.B0), x0=b.x0, y0=b.y0, h=b.h) for b in w.boundaries[:keep]]
+    xyz, lam = w.xyz[:, : seg[-1]], w.lam[:, : seg[-1]]
+    ctx = D.dbie_init(bds, T(xyz), seg=seg, precision="fp32c")
+    outs = []
+    for persistent in (False, True, False):
+        D.dbie_set_tile_shape(ctx, 1, 4, 256, persistent)
+        assert D.dbie_query_persistent(ctx)["plain"] == persistent
+        outs.append(D.dbie_eval_field(ctx, T(lam), want_tan=True))
+        outs.append(D.dbie_solve_lambda(ctx, T(np.abs(lam)), method="lm", max_trials=6, fp64_accept=False))
+    for k in ("B", "dB", "tan", "fg"):
+        assert torch.equal(outs[0][k], outs[2][k]) and torch.equal(outs[0][k], outs[4][k]), k
+    for k in ("lam", "status", "trials", "B", "fg"):
+        assert torch.equal(outs[1][k], outs[3][k]) and torch.equal(outs[1][k], outs[5][k]), k
