@@ -101,7 +101,9 @@ typedef struct {
                                   * 2, 3 or 4: 9-node quadratic elements (Eq. 15), each element
                                   * integral by quad_points x quad_points Gauss-Legendre points; every
                                   * magnetogram then needs odd nx, ny >= 3 (element (m, n) holds the
-                                  * nodes 2m..2m+2 x 2n..2n+2). Elements need DBIE_FP64. */
+                                  * nodes 2m..2m+2 x 2n..2n+2). With DBIE_FP32C the elements
+                                  * that come closer than nearfield_radius_h * h to a point (3 x 3
+                                  * element window) are summed in FP64, every other pair in FP32. */
 } dbie_options;
 
 typedef struct {
@@ -197,6 +199,34 @@ DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixel
  * runs in the persistent form. */
 DBIE_API int dbie_query_tan(const dbie_ctx* ctx, int32_t* ppl, int32_t* waves, int32_t* tile_pixels);
 DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t* with_tangents);
+
+/* Field-line tracing (the paper's field-line figures; current lines from J = curl B, Eq. 14).
+ * Lambda at a point comes from trilinear interpolation of a regular grid (coordinates clamped to
+ * the grid): node (i, j, k) at (x0 + i dx, y0 + j dy, z0 + k dz), lambda device double [3][nz][ny][nx]
+ * (lambda_x, lambda_y, lambda_z planes); nx = ny = nz = 1 gives one constant lambda triple. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double x0, y0, z0;
+    double dx, dy, dz;
+    const double* lambda;
+} dbie_lambda_grid;
+
+enum { DBIE_TRACE_FIELD = 0, DBIE_TRACE_CURRENT = 1 };
+
+/* Trace one line from each point of the context (the seeds) by fourth-order Runge-Kutta in arc length
+ * with step ds (length units): dx/ds = sense * v / |v|, v = B (DBIE_TRACE_FIELD) or v = curl B at
+ * frozen lambda (DBIE_TRACE_CURRENT), sense = +1 or -1. Every stage evaluates the context's own
+ * discretisation and precision at the stage points (geometry and near field re-classified on the
+ * device). A line stops, keeping its last point, when one of a step's four stage points would leave
+ * box = {x_lo, y_lo, z_lo, x_hi, y_hi, z_hi} (z_lo > 0) or its direction is undefined; a seed
+ * outside the box gives a line of one point.
+ *   xyz_out : device double [n_steps + 1][3][N]; point k of line i at [k][0..2][i], NaN after the end
+ *   count   : device int32 [N], points per line (>= 1)
+ * The context's points are moved during the call and restored before it returns; the call
+ * synchronises `stream`. Uses the context's workspace (not concurrently with other calls on it). */
+DBIE_API int dbie_trace_lines(dbie_ctx* ctx, const dbie_lambda_grid* lambda_grid, const double* box, double ds,
+                              int32_t n_steps, int32_t mode, double sense, double* xyz_out, int32_t* count,
+                              void* stream);
 
 DBIE_API void dbie_destroy(dbie_ctx* ctx);
 

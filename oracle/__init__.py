@@ -8,3 +8,4 @@ from .dbie_oracle import (kernel, pixel_centres, field, field_only, field_fd, cu
                           default_nm_step, solve_point_nm, solve_point_lm, lm_direction, levenberg_marquardt,
                           field_quad9, ST_CONVERGED, ST_BUDGET, ST_DEGENERATE, ST_J_ZERO, ST_NONFINITE)
 from .metrics import schrijver_metrics
+from .trace import trilinear, dbie_direction, rk4_trace

@@ -10,6 +10,7 @@ DBIE_OK, DBIE_E_INVAL, DBIE_E_DEVICE, DBIE_E_WORKSPACE, DBIE_E_UNSUPPORTED = 0, 
 DBIE_FP64, DBIE_FP32C = 0, 1
 DBIE_NELDER_MEAD, DBIE_LEVENBERG_MARQUARDT = 0, 1
 DBIE_ST_CONVERGED, DBIE_ST_BUDGET, DBIE_ST_DEGENERATE, DBIE_ST_J_ZERO, DBIE_ST_NONFINITE = 0, 1, 2, 3, 4
+DBIE_TRACE_FIELD, DBIE_TRACE_CURRENT = 0, 1
 
 
 class dbie_boundary(ctypes.Structure):
@@ -30,6 +31,11 @@ class dbie_options(ctypes.Structure):
 class dbie_solve_opts(ctypes.Structure):
     _fields_ = [("method", c_int32), ("max_trials", c_int32), ("eps", c_double), ("init_step", c_double),
                 ("lambda_cap", c_double), ("fp64_accept", c_int32), ("use_graph", c_int32)]
+
+
+class dbie_lambda_grid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("x0", c_double), ("y0", c_double),
+                ("z0", c_double), ("dx", c_double), ("dy", c_double), ("dz", c_double), ("lam", c_void_p)]
 
 
 # name -> (restype, argtypes)
@@ -53,6 +59,8 @@ SIGNATURES = {
     "dbie_set_tile_shape": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
     "dbie_query_persistent": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "dbie_solve_trace": (c_int32, [c_void_p, c_int32]),
+    "dbie_trace_lines": (c_int32, [c_void_p, POINTER(dbie_lambda_grid), POINTER(c_double), c_double, c_int32,
+                                   c_int32, c_double, c_void_p, c_void_p, c_void_p]),
     "dbie_solve_trace_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32,
                                         POINTER(c_int32)]),
     "dbie_destroy": (None, [c_void_p]),

@@ -67,13 +67,14 @@ struct dbie_ctx {
     double* gpos = nullptr;
     double* gB = nullptr;
     double* qlw = nullptr;      // 9-node elements: lw[3 g + a] = w_g L_a(xi_g) (device, 3 G doubles)
+    float4* gposf = nullptr;    // 9-node elements, FP32C: split grid positions (BoundaryDev::gposf_off)
     int32_t G = 0;              // Gauss points per element side; 0 = nodal rule
     int64_t ngrid_total = 0;
     float* pixf = nullptr;      // FP32 pixel blocks (Bx, By, Bz planes per block), FP32C only
     double* xyz = nullptr;
     Geo geo{};
     void* geo_block = nullptr;  // one allocation holding every geometry array
-    int32_t* near_ptr = nullptr;   // adjoint near lists (FP32C): CSR by global pixel index
+    int32_t* near_ptr = nullptr;   // adjoint near lists (FP32C): CSR by global grid-point index
     int32_t* near_pts = nullptr;
     int32_t* pix_bnd = nullptr;
     int64_t near_pairs = 0;
@@ -161,6 +162,7 @@ void free_ctx(dbie_ctx* c) {
     (void)hipFree(c->gpos);
     if (c->gB != c->B0d) (void)hipFree(c->gB);
     (void)hipFree(c->qlw);
+    (void)hipFree(c->gposf);
     (void)hipFree(c->pixf);
     (void)hipFree(c->xyz);
     (void)hipFree(c->geo_block);
@@ -233,14 +235,15 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
-                                    c->pixf, c->geo, lam, c->N, L, set ? idx : c->perm, c->work, tan,
+                                    c->pixf, c->gposf, c->geo, lam, c->N, L, set ? idx : c->perm, c->work, tan,
                                     scalar, tan ? c->shape_tan : c->shape, c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
         c->ev.emplace_back(e0, e1);
     }
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
-    DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->geo, lam, idx, c->N, set ? set->n_dev : nullptr, c->N,
+    DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, idx, c->N,
+                                set ? set->n_dev : nullptr, c->N,
                                 L, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
     return DBIE_OK;
 }
@@ -269,17 +272,23 @@ void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes) {
 }
 bool solver_tracing(const dbie_ctx* c) { return c->trace; }
 NearLists ctx_near_lists(const dbie_ctx* c) {
-    return NearLists{c->npix_total, c->near_pairs, c->near_ptr, c->near_pts, c->pix_bnd};
+    return NearLists{c->ngrid_total, c->near_pairs, c->near_ptr, c->near_pts, c->pix_bnd};
 }
 bool ctx_timing(const dbie_ctx* c) { return c->timing; }
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
-QuadGrid ctx_grid(const dbie_ctx* c) { return QuadGrid{c->gpos, c->gB, c->qlw, c->G, c->ngrid_total}; }
+QuadGrid ctx_grid(const dbie_ctx* c) { return QuadGrid{c->gpos, c->gB, c->qlw, c->G, c->ngrid_total, c->gposf}; }
 int ctx_precision(const dbie_ctx* c) { return c->opt.precision; }
 double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
 SolverState& ctx_solver(dbie_ctx* c) { return c->solver; }
 int ctx_fail(dbie_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+double* ctx_xyz(dbie_ctx* c) { return c->xyz; }
+hipError_t ctx_prep_points(dbie_ctx* c, int32_t* flag, hipStream_t s) {
+    const double r = (c->opt.precision == DBIE_FP32C) ? c->opt.nearfield_radius_h : 0.0;
+    return launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->gB, c->xyz, c->N, c->geo, r * r, 1, flag, nullptr,
+                       c->bnd_h.data(), c->nb, s);
+}
 
 }  // namespace dbie
 
@@ -323,8 +332,6 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         return fail(nullptr, DBIE_E_INVAL, "dv_over_dsigma_h must be positive and finite");
     if (o.quad_points != 0 && (o.quad_points < 2 || o.quad_points > 4))
         return fail(nullptr, DBIE_E_INVAL, "quad_points must be 0 (nodal sum) or 2, 3, 4 (9-node elements)");
-    if (o.quad_points != 0 && o.precision != DBIE_FP64)
-        return fail(nullptr, DBIE_E_INVAL, "9-node elements (quad_points > 0) need DBIE_FP64");
     const int32_t nb = prob->n_boundaries;
     if (nb < 1 || !prob->boundaries) return fail(nullptr, DBIE_E_INVAL, "need at least one boundary");
     if (prob->n_points < 0) return fail(nullptr, DBIE_E_INVAL, "n_points < 0");
@@ -369,20 +376,19 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     double xg[4], wg[4];
     if (G) gauss_legendre(G, xg, wg);
     std::vector<double> gpos_h;
+    std::vector<float> gposf_h;
     for (int32_t b = 0; b < nb; ++b) {
         const dbie_boundary& bd = prob->boundaries[b];
         BoundaryDev d{};
         d.nx = bd.nx;
         d.ny = bd.ny;
         d.npix = bd.nx * bd.ny;
-        d.ntx = (bd.nx + kCols - 1) / kCols;
-        d.nty = (bd.ny + kRows - 1) / kRows;
-        d.npix_pad = d.ntx * d.nty * kRows * kCols;
         d.pix_off = off;
         d.pixf_off = offf;
         d.x0 = bd.x0;
         d.y0 = bd.y0;
         d.h = bd.h;
+        d.G = G;
         if (G) {
             d.gcols = G * (bd.nx - 1) / 2;
             d.grows = G * (bd.ny - 1) / 2;
@@ -393,6 +399,10 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
             d.grows = bd.ny;
             d.gpl_off = off;
         }
+        // the FP32C blocks tile the quadrature grid (the pixels for the nodal rule)
+        d.ntx = (d.gcols + kCols - 1) / kCols;
+        d.nty = (d.grows + kRows - 1) / kRows;
+        d.npix_pad = d.ntx * d.nty * kRows * kCols;
         d.gpos_off = gpoff;
         gpoff += d.gcols + d.grows;
         // grid positions in pixels from node (0, 0): the nodes, or the Gauss points 2m + 1 + xi_g
@@ -400,6 +410,22 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
             const int32_t n = axis ? d.grows : d.gcols;
             for (int32_t k = 0; k < n; ++k)
                 gpos_h.push_back(G ? (double)(2 * (k / G) + 1) + xg[k % G] : (double)k);
+        }
+        if (G && o.precision == DBIE_FP32C) {
+            // split FP32 positions of the padded columns and rows; padding repeats the last point
+            d.gposf_off = (int64_t)gposf_h.size() / 4;
+            for (int axis = 0; axis < 2; ++axis) {
+                const int32_t n = axis ? d.grows : d.gcols, npad = axis ? d.nty * kRows : d.ntx * kCols;
+                for (int32_t k = 0; k < npad; ++k) {
+                    const int32_t kk = std::min(k, n - 1);
+                    const double p = (double)(2 * (kk / G) + 1) + xg[kk % G];
+                    const double fl = std::floor(p);
+                    gposf_h.push_back((float)fl);
+                    gposf_h.push_back((float)(p - fl));
+                    gposf_h.push_back((float)(kk / G));
+                    gposf_h.push_back(0.0f);
+                }
+            }
         }
         off += 3 * (int64_t)d.npix;
         offf += 3 * (int64_t)d.npix_pad;
@@ -445,6 +471,10 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     } else {
         c->gB = c->B0d;
     }
+    if (!gposf_h.empty()) {
+        DBIE_INIT_HIP(dalloc(&c->gposf, gposf_h.size() / 4));
+        DBIE_INIT_HIP(hipMemcpy(c->gposf, gposf_h.data(), gposf_h.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     if (o.precision == DBIE_FP32C) {
         DBIE_INIT_HIP(dalloc(&c->pixf, (size_t)offf));
         DBIE_INIT_HIP(dalloc(&c->work, 1));
@@ -488,7 +518,7 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     DBIE_INIT_HIP(dalloc(&bad, 1));
     DBIE_INIT_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
     const double r = (o.precision == DBIE_FP32C) ? o.nearfield_radius_h : 0.0;
-    DBIE_INIT_HIP(launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->B0d, c->xyz, N, c->geo, r * r,
+    DBIE_INIT_HIP(launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->gB, c->xyz, N, c->geo, r * r,
                               o.precision != DBIE_FP32C, bad, c->pixf, c->bnd_h.data(), nb, s));
     int32_t bad_h = 0;
     DBIE_INIT_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -521,26 +551,38 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
             DBIE_INIT_HIP(dalloc(&c->perm, (size_t)N));
             DBIE_INIT_HIP(hipMemcpy(c->perm, perm.data(), N * sizeof(int32_t), hipMemcpyHostToDevice));
         }
-        // the near pairs by pixel for the adjoint (counting sort by pixel; points ascending)
-        const int64_t P = c->npix_total;
+        // the near pairs by grid point (pixel, or Gauss point of a 9-node element) for the adjoint
+        // (counting sort by grid point; points ascending)
+        const int64_t P = c->ngrid_total;
         std::vector<int32_t> ptr(P + 1, 0), pixb(P);
         for (int32_t b = 0; b < nb; ++b)
-            for (int64_t k = 0; k < c->bnd_h[b].npix; ++k) pixb[c->bnd_h[b].pix_off / 3 + k] = b;
-        auto pair_pixel = [&](int64_t i, int bit) -> int64_t {
-            int32_t b = 0;
-            while (!(i >= seg[b] && i < seg[b + 1])) ++b;
-            const BoundaryDev& bd = c->bnd_h[b];
-            const int32_t pa = wa[i] + bit % kNearSide - kNearWin, pb = wb[i] + bit / kNearSide - kNearWin;
-            return bd.pix_off / 3 + (int64_t)pb * bd.nx + pa;
+            for (int64_t k = 0; k < (int64_t)c->bnd_h[b].gcols * c->bnd_h[b].grows; ++k)
+                pixb[c->bnd_h[b].gpl_off / 3 + k] = b;
+        std::vector<int32_t> pbnd(N);
+        for (int32_t b = 0; b < nb; ++b)
+            for (int64_t i = seg[b]; i < seg[b + 1]; ++i) pbnd[i] = b;
+        // calls f(global grid index) for every grid point of pair bit `bit` of point i
+        auto for_pair = [&](int64_t i, int bit, auto&& f) {
+            const BoundaryDev& bd = c->bnd_h[pbnd[i]];
+            const int64_t base = bd.gpl_off / 3;
+            if (G) {
+                const int32_t m = wa[i] + bit % kNearSideQ - kNearWinQ, n = wb[i] + bit / kNearSideQ - kNearWinQ;
+                for (int q = 0; q < G; ++q)
+                    for (int g = 0; g < G; ++g) f(base + (int64_t)(G * n + q) * bd.gcols + G * m + g);
+            } else {
+                const int32_t pa = wa[i] + bit % kNearSide - kNearWin, pb = wb[i] + bit / kNearSide - kNearWin;
+                f(base + (int64_t)pb * bd.nx + pa);
+            }
         };
         for (int64_t i = 0; i < N; ++i)
-            for (uint32_t m = mask[i]; m; m &= m - 1u) ++ptr[pair_pixel(i, __builtin_ctz(m)) + 1];
+            for (uint32_t m = mask[i]; m; m &= m - 1u) for_pair(i, __builtin_ctz(m), [&](int64_t g) { ++ptr[g + 1]; });
         for (int64_t g = 0; g < P; ++g) ptr[g + 1] += ptr[g];
         c->near_pairs = ptr[P];
         if (c->near_pairs > 0) {
             std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1), pts(c->near_pairs);
             for (int64_t i = 0; i < N; ++i)
-                for (uint32_t m = mask[i]; m; m &= m - 1u) pts[fill[pair_pixel(i, __builtin_ctz(m))]++] = (int32_t)i;
+                for (uint32_t m = mask[i]; m; m &= m - 1u)
+                    for_pair(i, __builtin_ctz(m), [&](int64_t g) { pts[fill[g]++] = (int32_t)i; });
             DBIE_INIT_HIP(dalloc(&c->near_ptr, (size_t)P + 1));
             DBIE_INIT_HIP(dalloc(&c->near_pts, (size_t)c->near_pairs));
             DBIE_INIT_HIP(dalloc(&c->pix_bnd, (size_t)P));

@@ -25,6 +25,10 @@ constexpr int kAccTan = 9;      // rows 12 + 3p + j: T0, T1, T2 of component p
 constexpr int kAcc = kAccField + kAccTan;
 constexpr int kNearWin = 2;     // near-field window half-width in pixels (radius <= 2 h)
 constexpr int kNearSide = 2 * kNearWin + 1;
+// 9-node elements: the near window is 3 x 3 elements (of side 2 h) around element (floor(u/2),
+// floor(v/2)), which holds every element closer than 2 h horizontally; one mask bit per element.
+constexpr int kNearWinQ = 1;
+constexpr int kNearSideQ = 2 * kNearWinQ + 1;
 constexpr int kRows = 32;       // FP32C pixel block: kRows x kCols pixels, tile-major in HBM
 constexpr int kCols = 8;
 
@@ -37,7 +41,11 @@ struct BoundaryDev {
     // is the pixel grid itself; for 9-node elements (Eq. 15) the Gauss points of the elements.
     int32_t gcols, grows;
     int64_t gpos_off, gpl_off;
-    int32_t ntx, nty;   // FP32C pixel blocks along x and y (ceil(nx / kCols), ceil(ny / kRows))
+    int32_t G;          // Gauss points per element side; 0 = nodal rule
+    // FP32C grid positions (9-node elements only): float4 {integer part, fraction, element index, 0}
+    // for the ntx * kCols padded columns, then the nty * kRows padded rows, from gposf_off
+    int64_t gposf_off;
+    int32_t ntx, nty;   // FP32C blocks along x and y (ceil(gcols / kCols), ceil(grows / kRows))
     int32_t npix_pad;   // ntx * nty * kRows * kCols
     int64_t pix_off;    // offset of this boundary in the FP64 planes (3 planes of npix each)
     int64_t pixf_off;   // offset of this boundary in the FP32 blocks (3 * npix_pad floats)
@@ -185,7 +193,7 @@ __device__ __forceinline__ void residual_jacobian_fp64(const double B[3], const 
 }
 
 // ---- launchers (each defined next to its kernels) ---------------------------------------------
-hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
+hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* gB,
                        const double* xyz, int64_t N, Geo geo, double near_r2, int check_only_fp64,
                        int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,
                        hipStream_t s);
@@ -216,14 +224,15 @@ struct F32Shape {
 // work: a device int the persistent form uses as its tile counter (cleared by a kernel inside the
 // launch). scalar: the three lambda rows of every point are equal (the kernel reads row 0 only).
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
-                           const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape shape,
+                           const float* pixf, const float4* gposf, Geo geo, const double* lam, int64_t N,
+                           int32_t L, const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape shape,
                            double* acc, hipStream_t s);
 bool field32c_shape_supported(F32Shape shape);
 int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number
 
 // Over idx[0 .. n) (n = *n_dev when n_dev is given, else n_idx), or over every point without idx.
-hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, const double* lam,
+hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const double* gpos, const double* gB,
+                           Geo geo, const double* lam,
                            const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
                            const double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,

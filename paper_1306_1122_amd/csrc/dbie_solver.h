@@ -67,21 +67,26 @@ struct QuadGrid {
     const double* lw;    // 9-node elements: w_g L_a(xi_g), 3 G doubles; NULL for the nodal rule
     int32_t G;           // Gauss points per element side; 0 = nodal rule
     int64_t n_total;     // grid points over all boundaries
+    const float4* posf;  // FP32C split positions (BoundaryDev::gposf_off); NULL for the nodal rule
 };
 QuadGrid ctx_grid(const dbie_ctx* c);
 int ctx_precision(const dbie_ctx* c);
 double ctx_dvds(const dbie_ctx* c);
 SolverState& ctx_solver(dbie_ctx* c);
 int ctx_fail(dbie_ctx* c, int code, const char* msg);
+double* ctx_xyz(dbie_ctx* c);   // the context's own copy of the points (device [3][N])
+// Re-run the per-point geometry and near-field classification on the current ctx_xyz (same kernel
+// as dbie_init; invalid points are flagged in *flag and given safe geometry).
+hipError_t ctx_prep_points(dbie_ctx* c, int32_t* flag, hipStream_t s);
 // Library-owned scratch block `slot` of at least `bytes` (grown on need); NULL on failure.
 void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes);
 // Near-field pairs grouped by pixel (global pixel index over all magnetograms), for the adjoint.
 struct NearLists {
-    int64_t npix_total;
+    int64_t npix_total;      // quadrature grid points over all boundaries (the pixels for the nodal rule)
     int64_t n_pairs;
     const int32_t* ptr;      // [npix_total + 1]
-    const int32_t* pts;      // [n_pairs] point indices, ascending per pixel
-    const int32_t* pix_bnd;  // [npix_total] magnetogram of each pixel
+    const int32_t* pts;      // [n_pairs] point indices, ascending per grid point
+    const int32_t* pix_bnd;  // [npix_total] magnetogram of each grid point
 };
 NearLists ctx_near_lists(const dbie_ctx* c);
 bool solver_tracing(const dbie_ctx* c);

@@ -113,17 +113,23 @@ __device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float
 }
 
 // One block of kRows x kCols pixels with origin (a0, b0) and `rows` valid rows, for all PPL points.
-template <int PPL, bool TAN, bool SLOW, bool FRACT, bool SCALAR>
+// GRID (9-node elements): the block's columns and rows sit at the positions sC, sR ({integer part,
+// fraction, element index}) instead of at a0 + c, b0 + r, and the near mask is per element.
+template <int PPL, bool TAN, bool SLOW, bool FRACT, bool SCALAR, bool GRID>
 __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
-                                           const float4 (*sB)[kRows][kCols / 4], float a0, float b0,
-                                           int rows, float (&part)[PPL][TAN ? kAcc : kAccField]) {
+                                           const float4 (*sB)[kRows][kCols / 4], const float4* sC,
+                                           const float4* sR, float a0, float b0, int rows,
+                                           float (&part)[PPL][TAN ? kAcc : kAccField]) {
     static_assert(kCols == 8, "the row body reads two float4 per plane");
     float dxc[PPL][kCols];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         const float base = a0 + S.xn[j];   // exact: integers
 #pragma unroll
-        for (int c = 0; c < kCols; ++c) dxc[j][c] = (base + (float)c) - S.xf[j];
+        for (int c = 0; c < kCols; ++c) {
+            if (GRID) dxc[j][c] = (sC[c].x + S.xn[j]) + (sC[c].y - S.xf[j]);
+            else dxc[j][c] = (base + (float)c) - S.xf[j];
+        }
     }
     for (int r = 0; r < rows; ++r) {
         const float4 X0 = sB[0][r][0], X1 = sB[0][r][1];
@@ -133,14 +139,22 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
         const float bys[kCols] = {Y0.x, Y0.y, Y0.z, Y0.w, Y1.x, Y1.y, Y1.z, Y1.w};
         const float bzs[kCols] = {Z0.x, Z0.y, Z0.z, Z0.w, Z1.x, Z1.y, Z1.z, Z1.w};
         const float brow = b0 + (float)r;
+        float4 rp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (GRID) rp = sR[r];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            const float dy = (brow + S.yn[j]) - S.yf[j];
+            const float dy = GRID ? (rp.x + S.yn[j]) + (rp.y - S.yf[j]) : (brow + S.yn[j]) - S.yf[j];
             const float q = fmaf(dy, dy, S.w2[j]);
 #pragma unroll
             for (int c = 0; c < kCols; ++c) {
                 float bx = bxs[c], by = bys[c], bz = bzs[c];
-                if (SLOW) {
+                if (SLOW && GRID) {
+                    const float da = sC[c].z - S.fa[j], db = rp.z - S.fb[j];
+                    const bool in = fabsf(da) <= (float)kNearWinQ && fabsf(db) <= (float)kNearWinQ;
+                    const int bit =
+                        in ? (int)(da + (float)kNearWinQ) + kNearSideQ * (int)(db + (float)kNearWinQ) : 0;
+                    if (in && ((S.msk[j] >> bit) & 1u)) bx = by = bz = 0.0f;
+                } else if (SLOW) {
                     const float da = (a0 + (float)c) - S.fa[j], db = brow - S.fb[j];
                     const bool in = fabsf(da) <= (float)kNearWin && fabsf(db) <= (float)kNearWin;
                     const int bit =
@@ -157,12 +171,12 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
 }
 
 // One schedule tile: the sums of its points over every pixel block of their magnetogram.
-template <int PPL, int WAVES, bool TAN, bool SCALAR>
+template <int PPL, int WAVES, bool TAN, bool SCALAR, bool GRID>
 __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* __restrict__ bnd,
-                                              const float* __restrict__ pixf, const Geo& geo,
-                                              const double* __restrict__ lam, int64_t N,
+                                              const float* __restrict__ pixf, const float4* __restrict__ gposf,
+                                              const Geo& geo, const double* __restrict__ lam, int64_t N,
                                               const int32_t* __restrict__ idx, double* __restrict__ acc,
-                                              float4 (*sB)[kRows][kCols / 4]) {
+                                              float4 (*sB)[kRows][kCols / 4], float4* sC, float4* sR) {
     constexpr int NT = 64 * WAVES;
     constexpr int NA = TAN ? kAcc : kAccField;
     constexpr int BQ = kRows * kCols / 4;   // float4 per plane of a block
@@ -204,7 +218,9 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
         {
             // farthest pixel centre of the (column-padded) magnetogram from this point
             const float uf = -S.xn[j] + S.xf[j], vf = -S.yn[j] + S.yf[j];
-            const float dxm = fmaxf(fabsf(uf), fabsf((float)(bd.ntx * kCols - 1) - uf)) + 1.0f;
+            // (grid positions, padding included, lie in [0, nx - 1] x [0, ny - 1])
+            const float xe = GRID ? (float)(bd.nx - 1) : (float)(bd.ntx * kCols - 1);
+            const float dxm = fmaxf(fabsf(uf), fabsf(xe - uf)) + 1.0f;
             const float dym = fmaxf(fabsf(vf), fabsf((float)(bd.ny - 1) - vf)) + 1.0f;
             const float rmax = sqrtf(dxm * dxm + dym * dym + S.w2[j]);
             const float lmax = fmaxf(fabsf(S.lr[j][0]), fmaxf(fabsf(S.lr[j][1]), fabsf(S.lr[j][2])));
@@ -212,10 +228,12 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
             rv_w = (rv == rv) ? fmaxf(rv_w, rv) : __builtin_inff();   // NaN lambda forces FRACT
         }
         if (S.msk[j]) {
-            amin = min(amin, wa - kNearWin);
-            amax = max(amax, wa + kNearWin);
-            bmin = min(bmin, wb - kNearWin);
-            bmax = max(bmax, wb + kNearWin);
+            // the window box, in pixels (nodal) or in elements (GRID)
+            const int hw = GRID ? kNearWinQ : kNearWin;
+            amin = min(amin, wa - hw);
+            amax = max(amax, wa + hw);
+            bmin = min(bmin, wb - hw);
+            bmax = max(bmax, wb + hw);
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -240,26 +258,40 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
     for (int k = 0; k < nblk; ++k) {
         const int ty = k / bd.ntx, tx = k - ty * bd.ntx;
         const int a0 = tx * kCols, b0 = ty * kRows;
-        const int rows = min(kRows, bd.ny - b0);
+        const int rows = min(kRows, (GRID ? bd.grows : bd.ny) - b0);
         __syncthreads();
         for (int q = tid; q < 3 * BQ; q += NT) {
             const int pl = q / BQ, o = q - pl * BQ;
             sB[pl][o / (kCols / 4)][o % (kCols / 4)] = P[(int64_t)k * 3 * BQ + q];
         }
+        if (GRID) {
+            const float4* gp = gposf + bd.gposf_off;
+            if (tid < kCols) sC[tid] = gp[a0 + tid];
+            else if (tid < kCols + kRows) sR[tid - kCols] = gp[(int64_t)bd.ntx * kCols + b0 + tid - kCols];
+        }
         __syncthreads();
         bool slow = false;
-        if (any_near) slow = !(b0 + rows - 1 < bmin || b0 > bmax || a0 + kCols - 1 < amin || a0 > amax);
+        if (any_near) {
+            if (GRID) {
+                // the block's element range (padding columns and rows repeat the last element)
+                const int ea0 = a0 / bd.G, ea1 = min(a0 + kCols - 1, bd.gcols - 1) / bd.G;
+                const int eb0 = b0 / bd.G, eb1 = (b0 + rows - 1) / bd.G;
+                slow = !(eb1 < bmin || eb0 > bmax || ea1 < amin || ea0 > amax);
+            } else {
+                slow = !(b0 + rows - 1 < bmin || b0 > bmax || a0 + kCols - 1 < amin || a0 > amax);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
 #pragma unroll
             for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
         const float fa0 = (float)a0, fb0 = (float)b0;
         if (!slow) {
-            if (need_fract) block_loop<PPL, TAN, false, true, SCALAR>(S, sB, fa0, fb0, rows, part);
-            else block_loop<PPL, TAN, false, false, SCALAR>(S, sB, fa0, fb0, rows, part);
+            if (need_fract) block_loop<PPL, TAN, false, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+            else block_loop<PPL, TAN, false, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
         } else {
-            if (need_fract) block_loop<PPL, TAN, true, true, SCALAR>(S, sB, fa0, fb0, rows, part);
-            else block_loop<PPL, TAN, true, false, SCALAR>(S, sB, fa0, fb0, rows, part);
+            if (need_fract) block_loop<PPL, TAN, true, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+            else block_loop<PPL, TAN, true, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
         }
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
@@ -277,18 +309,21 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 // Either one workgroup per tile (work == NULL), or persistent: a grid sized to the resident
 // workgroups pulls tile indices from the device counter `work` (cleared by a kernel before the
 // launch) until the schedule is exhausted; every workgroup reaches the exit test after each tile.
-template <int PPL, int WAVES, bool TAN, bool SCALAR>
+template <int PPL, int WAVES, bool TAN, bool SCALAR, bool GRID>
 __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
                                                          const BoundaryDev* __restrict__ bnd,
-                                                         const float* __restrict__ pixf, Geo geo,
+                                                         const float* __restrict__ pixf,
+                                                         const float4* __restrict__ gposf, Geo geo,
                                                          const double* __restrict__ lam, int64_t N,
                                                          const int32_t* __restrict__ idx,
                                                          int32_t* __restrict__ work,
                                                          double* __restrict__ acc) {
     __shared__ float4 sB[3][kRows][kCols / 4];
+    __shared__ float4 sC[GRID ? kCols : 1], sR[GRID ? kRows : 1];
     if (!work) {
-        field32c_tile<PPL, WAVES, TAN, SCALAR>(tiles[blockIdx.x], bnd, pixf, geo, lam, N, idx, acc, sB);
+        field32c_tile<PPL, WAVES, TAN, SCALAR, GRID>(tiles[blockIdx.x], bnd, pixf, gposf, geo, lam, N, idx, acc, sB,
+                                                     sC, sR);
         return;
     }
     __shared__ int next;
@@ -298,7 +333,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict_
         const int64_t ti = next;
         __syncthreads();
         if (ti >= n_tiles) break;
-        field32c_tile<PPL, WAVES, TAN, SCALAR>(tiles[ti], bnd, pixf, geo, lam, N, idx, acc, sB);
+        field32c_tile<PPL, WAVES, TAN, SCALAR, GRID>(tiles[ti], bnd, pixf, gposf, geo, lam, N, idx, acc, sB, sC,
+                                                     sR);
     }
 }
 
@@ -333,10 +369,10 @@ bool field32c_shape_supported(F32Shape s) {
 
 __global__ void k_clear_work(int32_t* __restrict__ w) { *w = 0; }
 
-template <int P, int W, bool T, bool SC>
+template <int P, int W, bool T, bool SC, bool GR>
 static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
-                             Geo geo, const double* lam, int64_t N, int32_t L, const int32_t* idx,
-                             int32_t* work, double* acc, hipStream_t st) {
+                             const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L,
+                             const int32_t* idx, int32_t* work, double* acc, hipStream_t st) {
     unsigned gx = (unsigned)n_tiles;
     if (work) {
         // resident workgroups of this kernel on the device
@@ -345,33 +381,41 @@ static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryD
             int dev = 0, nb = 0;
             (void)hipGetDevice(&dev);
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field32c<P, W, T, SC>, 64 * W, 0);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field32c<P, W, T, SC, GR>, 64 * W, 0);
             per_cu = nb > 0 ? nb : 1;
             if (cus <= 0) cus = 1;
         }
         gx = (unsigned)std::min<int64_t>(n_tiles, (int64_t)per_cu * cus);
         hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(1), 0, st, work);
     }
-    hipLaunchKernelGGL((k_field32c<P, W, T, SC>), dim3(gx, (unsigned)L), dim3(64 * W), 0, st, tiles, n_tiles, bnd,
-                       pixf, geo, lam, N, idx, work, acc);
+    hipLaunchKernelGGL((k_field32c<P, W, T, SC, GR>), dim3(gx, (unsigned)L), dim3(64 * W), 0, st, tiles, n_tiles,
+                       bnd, pixf, gposf, geo, lam, N, idx, work, acc);
     return hipGetLastError();
 }
 
+template <int P, int W, bool GR>
+static hipError_t launch_variant(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
+                                 const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L,
+                                 const int32_t* idx, int32_t* w, bool tan, bool scalar, double* acc, hipStream_t st) {
+    if (tan) {
+        if (scalar) return launch_one<P, W, true, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
+        return launch_one<P, W, true, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
+    }
+    if (scalar) return launch_one<P, W, false, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
+    return launch_one<P, W, false, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
+}
+
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
-                           const float* pixf, Geo geo, const double* lam, int64_t N, int32_t L,
-                           const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape s,
+                           const float* pixf, const float4* gposf, Geo geo, const double* lam, int64_t N,
+                           int32_t L, const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape s,
                            double* acc, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
     // a persistent launch with L trials would share one counter between the grid rows
     int32_t* w = (s.persist && L == 1) ? work : nullptr;
 #define DBIE_LAUNCH(P, W)                                                                                  \
     if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {                                             \
-        if (tan) {                                                                                         \
-            if (scalar) return launch_one<P, W, true, true>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st); \
-            return launch_one<P, W, true, false>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st);           \
-        }                                                                                                  \
-        if (scalar) return launch_one<P, W, false, true>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st);   \
-        return launch_one<P, W, false, false>(tiles, n_tiles, bnd, pixf, geo, lam, N, L, idx, w, acc, st);              \
+        if (gposf) return launch_variant<P, W, true>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, tan, scalar, acc, st); \
+        return launch_variant<P, W, false>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, tan, scalar, acc, st);         \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)
 #undef DBIE_LAUNCH

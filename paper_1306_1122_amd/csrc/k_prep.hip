@@ -7,8 +7,9 @@ namespace dbie {
 // One thread per point of the schedule. Computes u, v, w (FP64), the split FP32 coordinates
 // (exact integer part + fraction rounded once, so that a_k - u is formed with one rounding in
 // FP32), and the near mask: pixel (a, b) of the 5x5 window around (round(u), round(v)) is "near"
-// when it exists and rho^2 = (a-u)^2 + (b-v)^2 + w^2 < near_r2, tested here in FP64 once. The FP32
-// bulk pass skips exactly these pairs and the FP64 near pass sums exactly these pairs.
+// when it exists and rho^2 = (a-u)^2 + (b-v)^2 + w^2 < near_r2, tested here in FP64 once (for 9-node
+// elements, whole elements of a 3x3 element window). The FP32 bulk pass skips exactly these pairs
+// and the FP64 near pass sums exactly these pairs.
 __global__ void k_prep_points(const Tile* __restrict__ tiles, const BoundaryDev* __restrict__ bnd,
                               const double* __restrict__ xyz, int64_t N, Geo geo, double near_r2,
                               int32_t* __restrict__ bad_flag) {
@@ -33,11 +34,33 @@ __global__ void k_prep_points(const Tile* __restrict__ tiles, const BoundaryDev*
         geo.yi_int[i] = (float)fv;
         geo.yi_frac[i] = (float)(vv - fv);
         geo.wf[i] = (float)ww;
+        geo.bidx[i] = t.b;
+        uint32_t mask = 0u;
+        if (bd.G > 0) {
+            // 9-node elements: element (m, n) covers nodes 2m..2m+2 x 2n..2n+2; it is near when the
+            // distance from the point to that rectangle (with the height) is below the radius
+            const int32_t wa = (int32_t)floor(0.5 * uu), wb = (int32_t)floor(0.5 * vv);
+            geo.win_a[i] = wa;
+            geo.win_b[i] = wb;
+            const int32_t ex = (bd.nx - 1) / 2, ey = (bd.ny - 1) / 2;
+            if (ww * ww < near_r2) {
+                for (int jj = -kNearWinQ; jj <= kNearWinQ; ++jj) {
+                    for (int ii = -kNearWinQ; ii <= kNearWinQ; ++ii) {
+                        const int32_t m = wa + ii, n = wb + jj;
+                        if (m < 0 || m >= ex || n < 0 || n >= ey) continue;
+                        const double dx = fmax(0.0, fmax(2.0 * m - uu, uu - (2.0 * m + 2.0)));
+                        const double dy = fmax(0.0, fmax(2.0 * n - vv, vv - (2.0 * n + 2.0)));
+                        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, ww * ww));
+                        if (r2 < near_r2) mask |= 1u << ((ii + kNearWinQ) + kNearSideQ * (jj + kNearWinQ));
+                    }
+                }
+            }
+            geo.near_mask[i] = mask;
+            continue;
+        }
         const int32_t wa = (int32_t)rint(uu), wb = (int32_t)rint(vv);
         geo.win_a[i] = wa;
         geo.win_b[i] = wb;
-        geo.bidx[i] = t.b;
-        uint32_t mask = 0u;
         if (ww * ww < near_r2) {
             for (int jj = -kNearWin; jj <= kNearWin; ++jj) {
                 for (int ii = -kNearWin; ii <= kNearWin; ++ii) {
@@ -53,9 +76,10 @@ __global__ void k_prep_points(const Tile* __restrict__ tiles, const BoundaryDev*
     }
 }
 
-// FP32 pixel blocks of one boundary: block k = (ty, tx) holds three planes (Bx, By, Bz) of
-// kRows x kCols floats for pixels (tx kCols + c, ty kRows + r); pixels beyond the magnetogram hold zero.
-__global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, float* __restrict__ pixf) {
+// FP32 blocks of one boundary's quadrature grid (the pixels for the nodal rule): block k = (ty, tx)
+// holds three planes (Bx, By, Bz) of kRows x kCols floats for grid points (tx kCols + c, ty kRows + r)
+// of the weighted field; points beyond the grid hold zero.
+__global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ gB, float* __restrict__ pixf) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     constexpr int BP = kRows * kCols;
     if (e >= 3 * (int64_t)bd.npix_pad) return;
@@ -66,7 +90,8 @@ __global__ void k_fill_pixf(BoundaryDev bd, const double* __restrict__ B0d, floa
     const int ty = (int)(k / bd.ntx), tx = (int)(k - (int64_t)ty * bd.ntx);
     const int a = tx * kCols + c, b = ty * kRows + r;
     float v = 0.0f;
-    if (a < bd.nx && b < bd.ny) v = (float)B0d[bd.pix_off + (int64_t)pl * bd.npix + (int64_t)b * bd.nx + a];
+    if (a < bd.gcols && b < bd.grows)
+        v = (float)gB[bd.gpl_off + (int64_t)pl * bd.gcols * bd.grows + (int64_t)b * bd.gcols + a];
     pixf[bd.pixf_off + e] = v;
 }
 
@@ -85,7 +110,7 @@ hipError_t launch_expand_scalar(const double* lam, int32_t L, int64_t N, double*
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
+hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* gB,
                        const double* xyz, int64_t N, Geo geo, double near_r2, int fp64_only,
                        int32_t* bad_flag, float* pixf, const BoundaryDev* bnd_host, int32_t nb,
                        hipStream_t s) {
@@ -99,7 +124,7 @@ hipError_t launch_prep(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bn
         for (int32_t b = 0; b < nb; ++b) {
             const int64_t P = 3 * (int64_t)bnd_host[b].npix_pad;
             hipLaunchKernelGGL(k_fill_pixf, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
-                               bnd_host[b], B0d, pixf);
+                               bnd_host[b], gB, pixf);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -46,9 +46,38 @@ __device__ __forceinline__ void add_near(const BoundaryDev& bd, const double* B0
     }
 }
 
+// 9-node elements: every Gauss point of each element flagged near, at its FP64 position, with the
+// FP64 weighted field of the quadrature grid.
+template <bool TAN>
+__device__ __forceinline__ void add_near_grid(const BoundaryDev& bd, const double* __restrict__ gpos,
+                                              const double* __restrict__ gB, uint32_t mask, int32_t wa,
+                                              int32_t wb, double u, double v, double w2, const double lm[3],
+                                              double* a) {
+    const double* cpos = gpos + bd.gpos_off;
+    const double* rpos = cpos + bd.gcols;
+    const int64_t ng = (int64_t)bd.gcols * bd.grows;
+    const double* W = gB + bd.gpl_off;
+    while (mask) {
+        const int bit = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const int32_t m = wa + bit % kNearSideQ - kNearWinQ, n = wb + bit / kNearSideQ - kNearWinQ;
+        for (int q = 0; q < bd.G; ++q) {
+            const int32_t r = bd.G * n + q;
+            const double dy = rpos[r] - v;
+            for (int g = 0; g < bd.G; ++g) {
+                const int32_t c = bd.G * m + g;
+                const int64_t k = (int64_t)r * bd.gcols + c;
+                pair_fp64<TAN>(cpos[c] - u, dy, w2, lm, W[k], W[ng + k], W[2 * ng + k], a);
+            }
+        }
+    }
+}
+
 template <bool TAN, bool NEAR>
 __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict__ bnd,
-                                                  const double* __restrict__ B0d, Geo geo,
+                                                  const double* __restrict__ B0d,
+                                                  const double* __restrict__ gpos,
+                                                  const double* __restrict__ gB, Geo geo,
                                                   const double* __restrict__ lam,
                                                   const int32_t* __restrict__ idx, int64_t n_idx,
                                                   const int32_t* __restrict__ n_dev, int64_t N, const double* __restrict__ acc, double dvds,
@@ -73,8 +102,12 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
             double nr[NA];
 #pragma unroll
             for (int r = 0; r < NA; ++r) nr[r] = 0.0;
-            add_near<TAN>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
-                          w * w, lm, nr);
+            if (bd.G > 0)
+                add_near_grid<TAN>(bd, gpos, gB, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i], w * w,
+                                   lm, nr);
+            else
+                add_near<TAN>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
+                              w * w, lm, nr);
 #pragma unroll
             for (int r = 0; r < NA; ++r) a[r] += nr[r];
         }
@@ -98,7 +131,8 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
     }
 }
 
-hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, const double* lam,
+hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const double* gpos, const double* gB,
+                           Geo geo, const double* lam,
                            const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
                            const double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
@@ -106,7 +140,8 @@ hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, Geo geo, c
     if (n_idx == 0) return hipSuccess;
     const dim3 grid((unsigned)((n_idx + 255) / 256), (unsigned)L);
 #define DBIE_FIN(T, NR)                                                                            \
-    hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, geo, lam, idx, n_idx, n_dev, N, \
+    hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, gpos, gB, geo, lam, idx, n_idx, \
+                       n_dev, N, \
                        acc, dvds, B, dB, fg, tanout)
     if (tan) {
         if (add_near) DBIE_FIN(true, true);

@@ -115,16 +115,24 @@ constexpr int kVjp32Pts = 64;
 constexpr int kVjp32F = 26;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^2, Lambda[3], Lambda/2pi[3],
                               // alpha[3], beta[3], gx[3], gy[3], window a, window b, mask (as bits)
 
-template <int PPX, bool SLOW>
+// GRID (9-node elements): output j sits at (a + af, b + bf) (integer part + fraction) and belongs to
+// element (ea, eb); the near mask is per element of the 3x3 window.
+template <int PPX, bool SLOW, bool GRID>
 __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e, const float a[PPX],
-                                            const float b[PPX], float (&acc)[PPX][3]) {
+                                            const float b[PPX], const float af[PPX], const float bf[PPX],
+                                            const float ea[PPX], const float eb[PPX], float (&acc)[PPX][3]) {
     const float X = sp[0][e], xf = sp[1][e], Y = sp[2][e], yf = sp[3][e], w2 = sp[4][e];
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
-        const float dx = (a[j] - X) - xf;
-        const float dy = (b[j] - Y) - yf;
+        const float dx = GRID ? (a[j] - X) + (af[j] - xf) : (a[j] - X) - xf;
+        const float dy = GRID ? (b[j] - Y) + (bf[j] - yf) : (b[j] - Y) - yf;
         float keep = 1.0f;
-        if (SLOW) {
+        if (SLOW && GRID) {
+            const float da = ea[j] - sp[23][e], db = eb[j] - sp[24][e];
+            const bool in = fabsf(da) <= (float)kNearWinQ && fabsf(db) <= (float)kNearWinQ;
+            const int bit = in ? (int)(da + (float)kNearWinQ) + kNearSideQ * (int)(db + (float)kNearWinQ) : 0;
+            if (in && ((__float_as_uint(sp[25][e]) >> bit) & 1u)) keep = 0.0f;
+        } else if (SLOW) {
             const float da = a[j] - sp[23][e], db = b[j] - sp[24][e];
             const bool in = fabsf(da) <= (float)kNearWin && fabsf(db) <= (float)kNearWin;
             const int bit = in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
@@ -150,24 +158,40 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
     }
 }
 
-template <int PPX>
+// Outputs are the quadrature grid points (the pixels for the nodal rule), written to gW at the
+// grid's plane offsets.
+template <int PPX, bool GRID>
 __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptiles,
                                                 const BoundaryDev* __restrict__ bnd,
                                                 const int64_t* __restrict__ seg, const int32_t* __restrict__ perm,
-                                                Geo geo, int64_t N, const double* __restrict__ coef,
-                                                double* __restrict__ gB0) {
+                                                const float4* __restrict__ gposf, Geo geo, int64_t N,
+                                                const double* __restrict__ coef, double* __restrict__ gW) {
     __shared__ float sp[kVjp32F][kVjp32Pts];
     __shared__ int any_near;
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
-    float a[PPX], b[PPX];
+    const int32_t ngrid = bd.gcols * bd.grows;
+    float a[PPX], b[PPX], af[PPX], bf[PPX], ea[PPX], eb[PPX];
     bool live[PPX];
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
         const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
-        live[j] = k < bd.npix;
-        a[j] = live[j] ? (float)(k % bd.nx) : 0.0f;
-        b[j] = live[j] ? (float)(k / bd.nx) : 0.0f;
+        live[j] = k < ngrid;
+        const int32_t kc = live[j] ? k % bd.gcols : 0, kr = live[j] ? k / bd.gcols : 0;
+        if (GRID) {
+            const float4 pc = gposf[bd.gposf_off + kc];
+            const float4 pr = gposf[bd.gposf_off + (int64_t)bd.ntx * kCols + kr];
+            a[j] = pc.x;
+            af[j] = pc.y;
+            ea[j] = pc.z;
+            b[j] = pr.x;
+            bf[j] = pr.y;
+            eb[j] = pr.z;
+        } else {
+            a[j] = (float)kc;
+            b[j] = (float)kr;
+            af[j] = bf[j] = ea[j] = eb[j] = 0.0f;
+        }
     }
     double tot[PPX][3];
     float part[PPX][3];
@@ -208,9 +232,9 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
         for (int j = 0; j < PPX; ++j)
             for (int p = 0; p < 3; ++p) part[j][p] = 0.0f;
         if (any_near) {
-            for (int e = 0; e < n; ++e) vjp32_point<PPX, true>(sp, e, a, b, part);
+            for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID>(sp, e, a, b, af, bf, ea, eb, part);
         } else {
-            for (int e = 0; e < n; ++e) vjp32_point<PPX, false>(sp, e, a, b, part);
+            for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID>(sp, e, a, b, af, bf, ea, eb, part);
         }
 #pragma unroll
         for (int j = 0; j < PPX; ++j)
@@ -219,24 +243,25 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
         if (!live[j]) continue;
-        const int64_t o = bd.pix_off + pt.start + (int64_t)threadIdx.x + j * 256;
-        for (int p = 0; p < 3; ++p) gB0[o + (int64_t)p * bd.npix] = tot[j][p];
+        const int64_t o = bd.gpl_off + pt.start + (int64_t)threadIdx.x + j * 256;
+        for (int p = 0; p < 3; ++p) gW[o + (int64_t)p * ngrid] = tot[j][p];
     }
 }
 
-// FP64 near pairs of the adjoint: pixel g (global index over all boundaries) gathers the points
+// FP64 near pairs of the adjoint: grid point g (global index over all boundaries) gathers the points
 // listed in near_pts[near_ptr[g] .. near_ptr[g+1]) (sorted by point) and adds to its output.
 __global__ void k_vjp_near(int64_t npix_total, const int32_t* __restrict__ near_ptr,
                            const int32_t* __restrict__ near_pts, const int32_t* __restrict__ pix_bnd,
-                           const BoundaryDev* __restrict__ bnd, Geo geo, int64_t N,
-                           const double* __restrict__ coef, double* __restrict__ gB0) {
+                           const BoundaryDev* __restrict__ bnd, const double* __restrict__ gpos, Geo geo,
+                           int64_t N, const double* __restrict__ coef, double* __restrict__ gW) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= npix_total) return;
     const int32_t s0 = near_ptr[g], s1 = near_ptr[g + 1];
     if (s0 == s1) return;
     const BoundaryDev bd = bnd[pix_bnd[g]];
-    const int64_t k = g - bd.pix_off / 3;
-    const double a = (double)(k % bd.nx), bb = (double)(k / bd.nx);
+    const int64_t k = g - bd.gpl_off / 3;
+    const int64_t ngrid = (int64_t)bd.gcols * bd.grows;
+    const double a = gpos[bd.gpos_off + k % bd.gcols], bb = gpos[bd.gpos_off + bd.gcols + k / bd.gcols];
     double acc[3] = {0.0, 0.0, 0.0};
     for (int32_t q = s0; q < s1; ++q) {
         const int64_t i = near_pts[q];
@@ -258,7 +283,7 @@ __global__ void k_vjp_near(int64_t npix_total, const int32_t* __restrict__ near_
             acc[p] = __builtin_fma(nn * ri3, coef[(3 + p) * N + i], __builtin_fma(hh * ri5, lin, acc[p]));
         }
     }
-    for (int p = 0; p < 3; ++p) gB0[bd.pix_off + (int64_t)p * bd.npix + k] += acc[p];
+    for (int p = 0; p < 3; ++p) gW[bd.gpl_off + (int64_t)p * ngrid + k] += acc[p];
 }
 
 // g_mu_p = gB_p tan[p] + sum_q gdB[3p+q] tan[3+3p+q]; g_lambda = 2 lambda g_mu.
@@ -329,7 +354,7 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
         for (int32_t b = 0; b < nb; ++b) {
             const BoundaryDev& bd = ctx_bnd_host(c, b);
             for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256) pt.push_back(PixTile{b, k});
-            for (int32_t k = 0; k < bd.npix; k += 256 * kVjpPix) pt32.push_back(PixTile{b, k});
+            for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256 * kVjpPix) pt32.push_back(PixTile{b, k});
         }
         const size_t szc = (size_t)std::max<int64_t>(N, 1) * kVjpCoef * sizeof(double);
         const size_t szt = ((pt.size() + pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
@@ -350,17 +375,21 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
         if (ctx_precision(c) == DBIE_FP64) {
             hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N,
                                grid.pos, coef, gW);
-            if (grid.G)
-                for (int32_t b = 0; b < nb; ++b)
-                    GRAD_HIP(launch_quad_transpose(ctx_bnd_host(c, b), gW, grid.lw, grid.G, gB0, s));
         } else {
-            hipLaunchKernelGGL(k_vjp32c<kVjpPix>, dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32, bnd, segd,
-                               ctx_perm(c), geo, N, coef, gB0);
+            if (grid.G)
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, true>), dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32,
+                                   bnd, segd, ctx_perm(c), grid.posf, geo, N, coef, gW);
+            else
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, false>), dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32,
+                                   bnd, segd, ctx_perm(c), grid.posf, geo, N, coef, gW);
             const NearLists nl = ctx_near_lists(c);
             if (nl.n_pairs > 0)
                 hipLaunchKernelGGL(k_vjp_near, dim3((unsigned)((nl.npix_total + 255) / 256)), dim3(256), 0, s,
-                                   nl.npix_total, nl.ptr, nl.pts, nl.pix_bnd, bnd, geo, N, coef, gB0);
+                                   nl.npix_total, nl.ptr, nl.pts, nl.pix_bnd, bnd, grid.pos, geo, N, coef, gW);
         }
+        if (grid.G)
+            for (int32_t b = 0; b < nb; ++b)
+                GRAD_HIP(launch_quad_transpose(ctx_bnd_host(c, b), gW, grid.lw, grid.G, gB0, s));
         GRAD_HIP(hipGetLastError());
         // the host arrays above must stay alive until the copies have been consumed
         GRAD_HIP(hipStreamSynchronize(s));

@@ -299,6 +299,30 @@ def dbie_solve_trace_read(ctx: Context, max_rounds: int = 100000):
     return np.array(t[:m]), np.array(cv[:m], dtype=np.int64)
 
 
+def dbie_trace_lines(ctx: Context, lam_grid: torch.Tensor, origin, spacing, box, ds: float, n_steps: int,
+                     mode: str = "field", sense: float = 1.0, stream=None):
+    """Field (mode="field") or current (mode="current") lines from the context's points.
+    lam_grid: [3, nz, ny, nx] float64 on the device, node (i, j, k) at origin + (i, j, k) * spacing;
+    box = (x_lo, y_lo, z_lo, x_hi, y_hi, z_hi). Returns dict(xyz=[n_steps + 1, 3, N], count=[N])."""
+    if lam_grid.dim() != 4 or lam_grid.shape[0] != 3:
+        raise ValueError("lam_grid must have shape [3, nz, ny, nx]")
+    _need(lam_grid, "lam_grid", tuple(lam_grid.shape))
+    N = ctx.n_points
+    g = L.dbie_lambda_grid()
+    g.nz, g.ny, g.nx = (int(v) for v in lam_grid.shape[1:])
+    g.x0, g.y0, g.z0 = (float(v) for v in origin)
+    g.dx, g.dy, g.dz = (float(v) for v in spacing)
+    g.lam = lam_grid.data_ptr()
+    bx = (ctypes.c_double * 6)(*[float(v) for v in box])
+    xyz = torch.empty(int(n_steps) + 1, 3, N, dtype=torch.float64, device=lam_grid.device)
+    count = torch.empty(N, dtype=torch.int32, device=lam_grid.device)
+    m = {"field": L.DBIE_TRACE_FIELD, "current": L.DBIE_TRACE_CURRENT}[mode]
+    _check(_lib().dbie_trace_lines(ctx.handle, ctypes.byref(g), bx, float(ds), int(n_steps), m, float(sense),
+                                   xyz.data_ptr() if N else None, count.data_ptr() if N else None,
+                                   _stream(stream)), ctx, "dbie_trace_lines")
+    return dict(xyz=xyz, count=count)
+
+
 def dbie_destroy(ctx: Context):
     ctx.close()
 

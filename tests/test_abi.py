@@ -82,7 +82,6 @@ def _problem(nx=4, ny=3, h=1.0, n=5, nb=1, seg=None):
     ("seg_order", "non-decreasing"),
     ("seg_end", "end at n_points"),
     ("quad_points", "quad_points must be"),
-    ("quad_fp32c", "need DBIE_FP64"),
     ("quad_even", "odd nx, ny"),
 ])
 def test_init_argument_checks(lib, case, msg):
@@ -118,8 +117,6 @@ def test_init_argument_checks(lib, case, msg):
         args[1] = ctypes.byref(p)
     elif case == "quad_points":
         o.precision, o.quad_points = L.DBIE_FP64, 1
-    elif case == "quad_fp32c":
-        o.quad_points = 2
     elif case == "quad_even":
         o.precision, o.quad_points = L.DBIE_FP64, 4   # the default magnetogram is 4 x 3
     rc = lib.dbie_init(*args)

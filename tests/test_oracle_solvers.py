@@ -174,3 +174,49 @@ def test_lowlou_field_is_force_free_and_solenoidal():
     gradscale = np.sqrt(np.sum(G * G, axis=(0, 1)))
     assert np.max(np.abs(div) / gradscale) < 1e-7
     assert np.max(f) < 1e-6
+
+
+def test_lowlou_n3_m1_eigenfunction_and_field():
+    """n = 3, m = 1 (the Table 1 case): the first eigenvalue above a = 0. The a = 0 profile for n = 3
+    is (1 - mu^2) dP_3/dmu (2 interior zeros); this one has 3, satisfies the ODE, vanishes at both
+    ends with P'(-1) = 10, and its field is force-free and solenoidal."""
+    ll = LowLou(n=3, m=1, l=0.3, Phi=4 * math.pi / 5)
+    assert 0.0 < ll.a2 < 40.0
+    mu = np.linspace(-1 + 1e-9, 1 - 1e-9, 20001)
+    P, dP = ll.P(mu)
+    assert abs(P[0]) < 1e-7 and abs(P[-1]) < 1e-7 and abs(dP[0] - 10.0) < 1e-6
+    assert int(np.sum(np.sign(P[1:-1]) != np.sign(P[:-2]))) == 3
+    h = 1e-4
+    m = np.linspace(-0.9, 0.9, 19)
+    Pm = ll.P(m)[0]
+    Pp = (ll.P(m + h)[0] - 2 * Pm + ll.P(m - h)[0]) / h ** 2
+    res = (1 - m * m) * Pp + 12 * Pm + ll.a2 * (4.0 / 3.0) * np.sign(Pm) * np.abs(Pm) ** (5.0 / 3.0)
+    assert np.max(np.abs(res)) < 1e-5 * np.max(np.abs(12 * Pm))
+    rng = np.random.default_rng(1)
+    p = rng.uniform([-1, -1, 0.05], [1, 1, 2], size=(25, 3)).T
+    e = 1e-5
+    G = np.zeros((3, 3, p.shape[1]))
+    for k in range(3):
+        d = np.zeros((3, 1))
+        d[k] = e
+        G[:, k] = (ll.field(*(p + d)) - ll.field(*(p - d))) / (2 * e)
+    B = ll.field(*p)
+    div = G[0, 0] + G[1, 1] + G[2, 2]
+    J = np.array([G[2, 1] - G[1, 2], G[0, 2] - G[2, 0], G[1, 0] - G[0, 1]])
+    f = np.linalg.norm(np.cross(J.T, B.T), axis=1) / (np.linalg.norm(J, axis=0) * np.linalg.norm(B, axis=0))
+    assert np.max(np.abs(div) / np.sqrt(np.sum(G * G, axis=(0, 1)))) < 1e-7
+    assert np.max(f) < 1e-6
+
+
+def test_table1_workload_layout():
+    from workloads import lowlou_table1
+    w = lowlou_table1()
+    bd = w.boundaries[0]
+    assert bd.B0.shape == (3, 192, 192) and w.n_points == 63 * 64 * 64
+    h = bd.h
+    # the region's columns are the central 64 boundary nodes; the bottom layer is boundary data
+    jj, ii = w.meta["bottom_idx"]
+    np.testing.assert_allclose(bd.x0 + ii[:64] * h, w.xyz[0, :64], atol=1e-15)
+    exact0 = w.meta["ll"].field(bd.x0 + ii * h, bd.y0 + jj * h, np.zeros(ii.size))
+    np.testing.assert_array_equal(exact0, bd.B0[:, jj, ii])
+    assert abs(w.xyz[2].min() - h) < 1e-15 and abs(w.xyz[2].max() - 63 * h) < 1e-12

@@ -9,7 +9,10 @@ Construction (standard Low & Lou form, re-derived here):
   (1 - mu^2) P'' + n (n + 1) P + a^2 (1 + 1/n) P^(1 + 2/n) = 0,  P(-1) = P(1) = 0,  P'(-1) = P'(-1)_norm
   B_r = -P' / r^(n+2),  B_theta = n P / (r^(n+2) sin theta),  B_phi = a P |P|^(1/n) / (r^(n+2) sin theta)
 The eigenvalue a^2 is found by shooting from both singular end points (regular series start) and
-matching P, P' at mu = 0; m counts the interior zeros of P.
+matching P, P' at mu = 0. m indexes the eigenvalues above a^2 = 0 in increasing order (m = 0 is the
+linear profile a = 0). For integer n the a = 0 profile, (1 - mu^2) dP_n/dmu up to scale, already has
+n - 1 interior zeros and each further eigenvalue adds one, so P_{n,m} has n - 1 + m interior zeros
+(for n = 1 that is m, the usual count).
 The field is placed in a frame tilted by Phi about the y axis, with the source a depth l below z = 0:
   X = x cos Phi - (z + l) sin Phi,  Y = y,  Z = x sin Phi + (z + l) cos Phi.
 """
@@ -52,38 +55,42 @@ class LowLou:
         return solve_ivp(self._rhs, (mu0, 0.0), y0, args=(a2,), rtol=1e-13, atol=1e-15,
                          method="DOP853", dense_output=dense)
 
-    def _zeros_one_sided(self, a2, eps=1e-6):
+    def _end_value(self, a2, eps=1e-6):
         mu0, y0 = self._start(self.dP, -1, eps)
-        s = solve_ivp(self._rhs, (mu0, 1.0 - eps), y0, args=(a2,), rtol=1e-11, atol=1e-13,
-                      method="DOP853", dense_output=True)
-        mu = np.linspace(mu0, 1.0 - eps, 40001)
-        P = s.sol(mu)[0]
-        return s.y[0, -1], int(np.sum(np.sign(P[1:-1]) != np.sign(P[:-2])))
+        return solve_ivp(self._rhs, (mu0, 1.0 - eps), y0, args=(a2,), rtol=1e-11, atol=1e-13,
+                         method="DOP853").y[0, -1]
 
     def _eigen(self, eps=1e-6):
         if self.m == 0:
             return 0.0, self.dP
-        # bracket the m-th eigenvalue by a scan of the one-sided end value, then match two-sided
-        grid = np.arange(0.01, 12.0, 0.02)
+        # bracket the m-th eigenvalue above 0 by the m-th sign change of the one-sided end value
+        # P(1) over a scan in a^2 (started clear of the a = 0 root), then match two-sided
+        grid = np.arange(0.01, 40.0, 0.05)
         prev = None
         bracket = None
+        found = 0
         for a2 in grid:
-            endv, nz = self._zeros_one_sided(a2)
-            if prev is not None and np.sign(endv) != np.sign(prev[1]) and prev[2] == self.m:
-                bracket = (prev[0], a2)
-                break
-            prev = (a2, endv, nz)
+            endv = self._end_value(a2, eps)
+            if prev is not None and np.sign(endv) != np.sign(prev[1]):
+                found += 1
+                if found == self.m:
+                    bracket = (prev[0], a2)
+                    break
+            prev = (a2, endv)
         if bracket is None:
             raise ValueError("eigenvalue bracket not found")
-        a2_0 = brentq(lambda a: self._zeros_one_sided(a)[0], *bracket, xtol=1e-10)
+        a2_0 = brentq(lambda a: self._end_value(a, eps), *bracket, xtol=1e-10)
+        # starting slope at +1 (in s = 1 - mu) from the one-sided profile near that end
+        mu0, y0 = self._start(self.dP, -1, eps)
+        near = solve_ivp(self._rhs, (mu0, 1.0 - 1e-3), y0, args=(a2_0,), rtol=1e-11, atol=1e-13,
+                         method="DOP853").y[0, -1]
+        c0 = near / 1e-3
 
         def F(v):
             a2, c = v
             L = self._side(a2, self.dP, -1, eps).y[:, -1]
             R = self._side(a2, c, +1, eps).y[:, -1]
             return L - R
-        # slope at +1 (in s = 1 - mu) has the sign that makes P vanish there with m interior zeros
-        c0 = self.dP if self.m % 2 == 0 else -self.dP
         sol, info, ier, msg = fsolve(F, [a2_0, c0], xtol=1e-14, full_output=True)
         if ier != 1 and np.max(np.abs(F(sol))) > 1e-10:
             raise RuntimeError("eigenvalue matching failed: " + msg)

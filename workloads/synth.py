@@ -295,4 +295,28 @@ def config5(seed: int = 1005, n_arcs: int = 4096, per_arc: int = 256) -> Workloa
                     np.array([0, xyz.shape[1]], np.int64), lam, meta=dict(bipoles=bips))
 
 
+def lowlou_table1(seed: int = 1006) -> Workload:
+    """The Table 1 comparison case: Low & Lou n=3, m=1, l=0.3, Phi=4pi/5 sampled on a 192x192 pixel
+    lower boundary centred on a 64x64x64-pixel test region. Assumed mapping (the case's own grid
+    definition is not reproduced in the paper): the test region spans [-1, 1]^2 x [0, 2], so
+    h = 1/32; boundary nodes at ((k - 95.5) h, (j - 95.5) h); region nodes at x, y = (i - 31.5) h
+    (the central 64 x 64 boundary nodes) and z = k h, k = 0..63. The points are the layers k >= 1
+    (z > 0); the k = 0 layer is the boundary data itself (meta['bottom_idx'] are its pixels)."""
+    ll = lowlou_case(n=3, m=1, l=0.3, Phi=4.0 * np.pi / 5.0)
+    h = 1.0 / 32.0
+    x0 = -95.5 * h
+    xs = x0 + h * np.arange(192)
+    X, Y = np.meshgrid(xs, xs)
+    B0 = ll.field(X, Y, np.zeros_like(X))
+    rs = (np.arange(64) - 31.5) * h
+    pz, py, px = np.meshgrid(h * np.arange(1, 64), rs, rs, indexing="ij")
+    xyz = np.stack([px.ravel(), py.ravel(), pz.ravel()])
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(-2.0, 2.0, size=(3, xyz.shape[1]))
+    jj, ii = np.meshgrid(np.arange(64) + 64, np.arange(64) + 64, indexing="ij")
+    return Workload("lowlou_n3_192x192_64x64x64", [Boundary(B0, x0, x0, h)], xyz,
+                    np.array([0, xyz.shape[1]], np.int64), lam, fp32=False,
+                    meta=dict(ll=ll, bottom_idx=(jj.ravel(), ii.ravel()), region_xy=rs))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
