@@ -218,6 +218,51 @@ def active_region(D, dev):
                 with_tangents_ms=mst, with_tangents_pairs_per_s=pairs / (mst * 1e-3))
 
 
+def quad9_elements(D, dev):
+    """Eq. (15) 9-node elements on the benchmark magnetogram cropped to 127x127 (odd sides), all
+    1,048,576 points: one evaluation of B and grad B per quadrature order, FP32C with the elements
+    near a point in FP64, against the nodal rule on the same crop."""
+    import torch
+    from workloads import config2
+    w = config2()
+    B0 = np.ascontiguousarray(w.boundaries[0].B0[:, :127, :127])
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    xyz, lam = T(w.xyz), T(w.lam)
+    out = {}
+    for G in (0, 2, 4):
+        ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", quad_points=G)
+        ms = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
+        ctx.close()
+        npts = 127 * 127 if G == 0 else (G * 63) ** 2
+        pairs = w.n_points * npts
+        out["nodal" if G == 0 else "G%d" % G] = dict(quadrature_points=npts, field_grad_ms=ms,
+                                                      pairs_per_s=pairs / (ms * 1e-3))
+    return out
+
+
+def field_lines(D, dev, n_lines=4096, n_steps=100):
+    """RK4 field lines through the FP32C DBIE field of the benchmark magnetogram: 4096 seeds at
+    z = 2..10 pixels, step 0.5 pixel, 100 steps, constant lambda 0.02 per pixel (4 evaluations of
+    4096 points x 16384 pixels per step)."""
+    import torch
+    from workloads import config2
+    w = config2()
+    bd = w.boundaries[0]
+    rng = np.random.default_rng(11)
+    seeds = np.stack([rng.uniform(16, 112, n_lines), rng.uniform(16, 112, n_lines), rng.uniform(2, 10, n_lines)])
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=0.0, y0=0.0, h=1.0)], T(seeds), precision="fp32c")
+    lam = T(np.full((3, 1, 1, 1), 0.02))
+    box = (0.0, 0.0, 0.5, 127.0, 127.0, 64.0)
+    run = lambda: D.dbie_trace_lines(ctx, lam, (0, 0, 0), (1, 1, 1), box, 0.5, n_steps)  # noqa: E731
+    ms = _timed(run, 1)
+    cnt = run()["count"]
+    ctx.close()
+    steps = int(cnt.sum().item()) - n_lines
+    return dict(lines=n_lines, steps_taken=steps, ms=ms, line_steps_per_s=steps / (ms * 1e-3),
+                pairs_per_s=4 * n_steps * n_lines * bd.nx * bd.ny / (ms * 1e-3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,7 +348,9 @@ def main():
                          ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs)),
                          ("time_to_solution", lambda: time_to_solution(D, dev)),
                          ("batched_64_magnetograms", lambda: batched(D, dev)),
-                         ("active_region_512x256_arcs", lambda: active_region(D, dev))):
+                         ("active_region_512x256_arcs", lambda: active_region(D, dev)),
+                         ("quad9_elements_127x127", lambda: quad9_elements(D, dev)),
+                         ("field_lines_4096", lambda: field_lines(D, dev))):
             try:
                 extras[name] = fn()
             except Exception as exc:  # an extra must not hide the headline line
