@@ -271,6 +271,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="", help="comma-separated names of the extras to run (default: all)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB once (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--shape", default="", help="FP32C tile shape ppl,waves,tile_pixels")
@@ -351,6 +352,8 @@ def main():
                          ("active_region_512x256_arcs", lambda: active_region(D, dev)),
                          ("quad9_elements_127x127", lambda: quad9_elements(D, dev)),
                          ("field_lines_4096", lambda: field_lines(D, dev))):
+            if args.extras and name not in args.extras.split(","):
+                continue
             try:
                 extras[name] = fn()
             except Exception as exc:  # an extra must not hide the headline line
