@@ -104,6 +104,12 @@ typedef struct {
                                   * nodes 2m..2m+2 x 2n..2n+2). With DBIE_FP32C the elements
                                   * that come closer than nearfield_radius_h * h to a point (3 x 3
                                   * element window) are summed in FP64, every other pair in FP32. */
+    int32_t pixel_split;         /* FP32C: pixel slices per launch (grid z), each summing an even share of
+                                  * the magnetogram's blocks into its own partial, added in order by the
+                                  * finalize pass. 0 = automatic (about four workgroups per compute
+                                  * unit when the point tiles alone are fewer, else 1), 1..32 fixed.
+                                  * The slicing changes the FP64 summation grouping only (results
+                                  * agree to ~1e-16 relative; bitwise equal for equal slicing). */
 } dbie_options;
 
 typedef struct {
@@ -199,6 +205,8 @@ DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixel
  * runs in the persistent form. */
 DBIE_API int dbie_query_tan(const dbie_ctx* ctx, int32_t* ppl, int32_t* waves, int32_t* tile_pixels);
 DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t* with_tangents);
+/* Pixel slices per FP32C launch (dbie_options.pixel_split, or the automatic choice); 1 for FP64. */
+DBIE_API int dbie_query_split(const dbie_ctx* ctx, int32_t* slices);
 
 /* Field-line tracing (the paper's field-line figures; current lines from J = curl B, Eq. 14).
  * Lambda at a point comes from trilinear interpolation of a regular grid (coordinates clamped to

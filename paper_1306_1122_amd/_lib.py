@@ -25,7 +25,8 @@ class dbie_problem(ctypes.Structure):
 
 class dbie_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("nearfield_radius_h", c_double), ("dv_over_dsigma_h", c_double),
-                ("tune", c_int32), ("tune_cache", c_char_p), ("quad_points", c_int32)]
+                ("tune", c_int32), ("tune_cache", c_char_p), ("quad_points", c_int32),
+                ("pixel_split", c_int32)]
 
 
 class dbie_solve_opts(ctypes.Structure):
@@ -59,6 +60,7 @@ SIGNATURES = {
     "dbie_set_tile_shape": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
     "dbie_query_persistent": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "dbie_solve_trace": (c_int32, [c_void_p, c_int32]),
+    "dbie_query_split": (c_int32, [c_void_p, POINTER(c_int32)]),
     "dbie_trace_lines": (c_int32, [c_void_p, POINTER(dbie_lambda_grid), POINTER(c_double), c_double, c_int32,
                                    c_int32, c_double, c_void_p, c_void_p, c_void_p]),
     "dbie_solve_trace_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32,

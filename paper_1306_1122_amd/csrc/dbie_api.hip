@@ -89,6 +89,8 @@ struct dbie_ctx {
     F32Shape shape{1, 8, kRows * kCols, 0};
     F32Shape shape_tan{1, 4, kRows * kCols, 0};
     int32_t* work = nullptr;    // tile counter of the persistent FP32C form
+    int32_t split = 1;          // FP32C pixel slices per launch (grid z); acc holds split x L slices
+    int32_t cus = 256;          // compute units of the device
     double* acc = nullptr;      // [L][kAcc][N]
     int64_t acc_L = 0;
     SolverState solver{};
@@ -199,6 +201,16 @@ int set_tiles32(dbie_ctx* c, F32Shape s, bool tan) {
     dst = d;
     (tan ? c->n_tiles32t : c->n_tiles32) = (int64_t)t.size();
     (tan ? c->shape_tan : c->shape) = s;
+    // Pixel slices: enough workgroups for about four per compute unit when the point tiles alone
+    // are fewer (few points: late solver rounds, field-line seeds), else one.
+    if (c->opt.pixel_split > 0) {
+        c->split = c->opt.pixel_split;
+    } else {
+        const int64_t nt = std::max<int64_t>(1, std::min(c->n_tiles32 > 0 ? c->n_tiles32 : INT64_MAX,
+                                                         c->n_tiles32t > 0 ? c->n_tiles32t : INT64_MAX));
+        const int64_t want = 4 * (int64_t)c->cus;
+        c->split = (int32_t)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (want + nt - 1) / nt));
+    }
     return DBIE_OK;
 }
 
@@ -207,13 +219,14 @@ int set_tiles32(dbie_ctx* c, F32Shape s, bool tan) {
 namespace dbie {
 
 int ensure_acc(dbie_ctx* c, int64_t L) {
-    if (c->acc && c->acc_L >= L) return DBIE_OK;
+    const int64_t need = L * c->split;   // L trials x pixel slices
+    if (c->acc && c->acc_L >= need) return DBIE_OK;
     (void)hipFree(c->acc);
     c->acc = nullptr;
     c->acc_L = 0;
-    hipError_t e = dalloc(&c->acc, (size_t)(L * kAcc * std::max<int64_t>(c->N, 1)));
+    hipError_t e = dalloc(&c->acc, (size_t)(need * kAcc * std::max<int64_t>(c->N, 1)));
     if (e != hipSuccess) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the accumulator workspace");
-    c->acc_L = L;
+    c->acc_L = need;
     return DBIE_OK;
 }
 
@@ -235,7 +248,7 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
-                                    c->pixf, c->gposf, c->geo, lam, c->N, L, set ? idx : c->perm, c->work, tan,
+                                    c->pixf, c->gposf, c->geo, lam, c->N, L, c->split, set ? idx : c->perm, c->work, tan,
                                     scalar, tan ? c->shape_tan : c->shape, c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
@@ -244,7 +257,7 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
     DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, idx, c->N,
                                 set ? set->n_dev : nullptr, c->N,
-                                L, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
+                                L, fp64 ? 1 : c->split, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
     return DBIE_OK;
 }
 
@@ -284,6 +297,8 @@ double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
 SolverState& ctx_solver(dbie_ctx* c) { return c->solver; }
 int ctx_fail(dbie_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
 double* ctx_xyz(dbie_ctx* c) { return c->xyz; }
+const void* ctx_acc(const dbie_ctx* c) { return c->acc; }
+int32_t ctx_split(const dbie_ctx* c) { return c->split; }
 hipError_t ctx_prep_points(dbie_ctx* c, int32_t* flag, hipStream_t s) {
     const double r = (c->opt.precision == DBIE_FP32C) ? c->opt.nearfield_radius_h : 0.0;
     return launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->gB, c->xyz, c->N, c->geo, r * r, 1, flag, nullptr,
@@ -302,6 +317,7 @@ int dbie_default_options(dbie_options* o) {
     o->tune = 0;
     o->tune_cache = nullptr;
     o->quad_points = 0;
+    o->pixel_split = 0;
     return DBIE_OK;
 }
 
@@ -330,6 +346,8 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         return fail(nullptr, DBIE_E_INVAL, "nearfield_radius_h must lie in [0, 2]");
     if (!(o.dv_over_dsigma_h > 0.0) || !std::isfinite(o.dv_over_dsigma_h))
         return fail(nullptr, DBIE_E_INVAL, "dv_over_dsigma_h must be positive and finite");
+    if (o.pixel_split < 0 || o.pixel_split > kMaxSplit)
+        return fail(nullptr, DBIE_E_INVAL, "pixel_split must lie in [0, 32]");
     if (o.quad_points != 0 && (o.quad_points < 2 || o.quad_points > 4))
         return fail(nullptr, DBIE_E_INVAL, "quad_points must be 0 (nodal sum) or 2, 3, 4 (9-node elements)");
     const int32_t nb = prob->n_boundaries;
@@ -370,6 +388,11 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     c->seg = seg;
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetDevice(&c->device);
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+            c->cus = cus;
+    }
     int64_t off = 0, offf = 0, goff = 0, gpoff = 0;
     const int G = o.quad_points;
     c->G = G;
@@ -708,6 +731,12 @@ int dbie_query_persistent(const dbie_ctx* c, int32_t* plain, int32_t* with_tange
     if (!c) return DBIE_E_INVAL;
     if (plain) *plain = c->shape.persist;
     if (with_tangents) *with_tangents = c->shape_tan.persist;
+    return DBIE_OK;
+}
+
+int dbie_query_split(const dbie_ctx* c, int32_t* slices) {
+    if (!c) return DBIE_E_INVAL;
+    if (slices) *slices = c->opt.precision == DBIE_FP32C ? c->split : 1;
     return DBIE_OK;
 }
 

@@ -29,6 +29,7 @@ constexpr int kNearSide = 2 * kNearWin + 1;
 // floor(v/2)), which holds every element closer than 2 h horizontally; one mask bit per element.
 constexpr int kNearWinQ = 1;
 constexpr int kNearSideQ = 2 * kNearWinQ + 1;
+constexpr int kMaxSplit = 32;   // largest number of FP32C pixel slices per launch
 constexpr int kRows = 32;       // FP32C pixel block: kRows x kCols pixels, tile-major in HBM
 constexpr int kCols = 8;
 
@@ -225,16 +226,17 @@ struct F32Shape {
 // launch). scalar: the three lambda rows of every point are equal (the kernel reads row 0 only).
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, const float4* gposf, Geo geo, const double* lam, int64_t N,
-                           int32_t L, const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape shape,
-                           double* acc, hipStream_t s);
+                           int32_t L, int32_t S, const int32_t* idx, int32_t* work, bool tan, bool scalar,
+                           F32Shape shape, double* acc, hipStream_t s);
 bool field32c_shape_supported(F32Shape shape);
 int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number
 
 // Over idx[0 .. n) (n = *n_dev when n_dev is given, else n_idx), or over every point without idx.
+// acc holds S slices of [L][kAcc][N] (the pixel split of the FP32C pass), summed here in order.
 hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const double* gpos, const double* gB,
                            Geo geo, const double* lam,
                            const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
-                           const double* acc,
+                           int32_t S, const double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s);
 

@@ -16,6 +16,10 @@ struct GraphKey {
     void* block;
     hipStream_t stream;
     const int32_t* perm;
+    // what the captured launches bake in besides the solver's own buffers: the accumulator (it is
+    // reallocated when a call needs more trials or slices), the pixel split and the tile shape
+    const void* acc;
+    int32_t split, ppl, waves, persist;
 };
 
 // Device buffers owned by a context for dbie_solve_lambda (allocated on first use, grown on need).
@@ -74,6 +78,8 @@ int ctx_precision(const dbie_ctx* c);
 double ctx_dvds(const dbie_ctx* c);
 SolverState& ctx_solver(dbie_ctx* c);
 int ctx_fail(dbie_ctx* c, int code, const char* msg);
+const void* ctx_acc(const dbie_ctx* c);
+int32_t ctx_split(const dbie_ctx* c);
 double* ctx_xyz(dbie_ctx* c);   // the context's own copy of the points (device [3][N])
 // Re-run the per-point geometry and near-field classification on the current ctx_xyz (same kernel
 // as dbie_init; invalid points are flagged in *flag and given safe geometry).

@@ -1,7 +1,10 @@
 // FP32 bulk kernel sum with compensated accumulation (the FP32C path).
 //
 // Work decomposition: one schedule tile (<= PPL * 64 * WAVES points of one magnetogram) at a time
-// per workgroup, one grid row per lambda trial; static schedules are ordered by decreasing cost. Lane l of the workgroup owns points l, l + NT, ...
+// per workgroup, one grid row (y) per lambda trial and one grid layer (z) per pixel slice (when the
+// point tiles alone cannot fill the chip, slice z sums its share of the pixel blocks into its own
+// partial, and the finalize pass adds the slices in order); static schedules are ordered by
+// decreasing cost. Lane l of the workgroup owns points l, l + NT, ...
 // of the tile, so a wavefront holds 64 consecutive points (the library orders points so that these
 // are spatially coherent). The magnetogram streams through LDS in blocks of kRows x kCols pixels
 // (three planes Bx, By, Bz, tile-major in HBM); every lane reads the same LDS address (broadcast).
@@ -254,8 +257,11 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
         for (int r = 0; r < NA; ++r) tot[j][r] = 0.0;
 
     const float4* P = reinterpret_cast<const float4*>(pixf + bd.pixf_off);
-    const int nblk = bd.ntx * bd.nty;
-    for (int k = 0; k < nblk; ++k) {
+    // pixel split: slice blockIdx.z of gridDim.z takes an even share of the blocks
+    const int nblk_all = bd.ntx * bd.nty;
+    const int kb0 = (int)((int64_t)blockIdx.z * nblk_all / gridDim.z);
+    const int nblk = (int)((int64_t)(blockIdx.z + 1) * nblk_all / gridDim.z);
+    for (int k = kb0; k < nblk; ++k) {
         const int ty = k / bd.ntx, tx = k - ty * bd.ntx;
         const int a0 = tx * kCols, b0 = ty * kRows;
         const int rows = min(kRows, (GRID ? bd.grows : bd.ny) - b0);
@@ -302,7 +308,7 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
     for (int j = 0; j < PPL; ++j) {
         if (!live[j]) continue;
 #pragma unroll
-        for (int r = 0; r < NA; ++r) acc[(trial * kAcc + r) * N + pid[j]] = tot[j][r];
+        for (int r = 0; r < NA; ++r) acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + pid[j]] = tot[j][r];
     }
 }
 
@@ -371,7 +377,7 @@ __global__ void k_clear_work(int32_t* __restrict__ w) { *w = 0; }
 
 template <int P, int W, bool T, bool SC, bool GR>
 static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
-                             const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L,
+                             const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L, int32_t S,
                              const int32_t* idx, int32_t* work, double* acc, hipStream_t st) {
     unsigned gx = (unsigned)n_tiles;
     if (work) {
@@ -388,34 +394,35 @@ static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryD
         gx = (unsigned)std::min<int64_t>(n_tiles, (int64_t)per_cu * cus);
         hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(1), 0, st, work);
     }
-    hipLaunchKernelGGL((k_field32c<P, W, T, SC, GR>), dim3(gx, (unsigned)L), dim3(64 * W), 0, st, tiles, n_tiles,
-                       bnd, pixf, gposf, geo, lam, N, idx, work, acc);
+    hipLaunchKernelGGL((k_field32c<P, W, T, SC, GR>), dim3(gx, (unsigned)L, (unsigned)S), dim3(64 * W), 0, st,
+                       tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, idx, work, acc);
     return hipGetLastError();
 }
 
 template <int P, int W, bool GR>
 static hipError_t launch_variant(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
-                                 const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L,
+                                 const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L, int32_t S,
                                  const int32_t* idx, int32_t* w, bool tan, bool scalar, double* acc, hipStream_t st) {
     if (tan) {
-        if (scalar) return launch_one<P, W, true, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
-        return launch_one<P, W, true, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
+        if (scalar) return launch_one<P, W, true, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
+        return launch_one<P, W, true, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
     }
-    if (scalar) return launch_one<P, W, false, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
-    return launch_one<P, W, false, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, acc, st);
+    if (scalar) return launch_one<P, W, false, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
+    return launch_one<P, W, false, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
 }
 
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                            const float* pixf, const float4* gposf, Geo geo, const double* lam, int64_t N,
-                           int32_t L, const int32_t* idx, int32_t* work, bool tan, bool scalar, F32Shape s,
-                           double* acc, hipStream_t st) {
+                           int32_t L, int32_t S, const int32_t* idx, int32_t* work, bool tan, bool scalar,
+                           F32Shape s, double* acc, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
-    // a persistent launch with L trials would share one counter between the grid rows
-    int32_t* w = (s.persist && L == 1) ? work : nullptr;
+    if (S < 1) return hipErrorInvalidValue;
+    // a persistent launch with L trials or S slices would share one counter between the grid rows
+    int32_t* w = (s.persist && L == 1 && S == 1) ? work : nullptr;
 #define DBIE_LAUNCH(P, W)                                                                                  \
     if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {                                             \
-        if (gposf) return launch_variant<P, W, true>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, tan, scalar, acc, st); \
-        return launch_variant<P, W, false>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, idx, w, tan, scalar, acc, st);         \
+        if (gposf) return launch_variant<P, W, true>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, tan, scalar, acc, st); \
+        return launch_variant<P, W, false>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, tan, scalar, acc, st);         \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)
 #undef DBIE_LAUNCH

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
                                                   const double* __restrict__ gB, Geo geo,
                                                   const double* __restrict__ lam,
                                                   const int32_t* __restrict__ idx, int64_t n_idx,
-                                                  const int32_t* __restrict__ n_dev, int64_t N, const double* __restrict__ acc, double dvds,
+                                                  const int32_t* __restrict__ n_dev, int64_t N, int32_t L,
+                                                  int32_t S, const double* __restrict__ acc, double dvds,
                                                   double* __restrict__ Bo, double* __restrict__ dBo,
                                                   double* __restrict__ fgo, double* __restrict__ tno) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,6 +93,11 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
     double a[NA];
 #pragma unroll
     for (int r = 0; r < NA; ++r) a[r] = acc[(trial * kAcc + r) * N + i];
+    for (int z = 1; z < S; ++z) {
+        const double* az = acc + ((int64_t)z * L + trial) * kAcc * N;
+#pragma unroll
+        for (int r = 0; r < NA; ++r) a[r] += az[r * N + i];
+    }
     const double w = geo.w[i];
     if (NEAR) {
         const uint32_t mask = geo.near_mask[i];
@@ -134,15 +140,14 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
 hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const double* gpos, const double* gB,
                            Geo geo, const double* lam,
                            const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
-                           const double* acc,
+                           int32_t S, const double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s) {
     if (n_idx == 0) return hipSuccess;
     const dim3 grid((unsigned)((n_idx + 255) / 256), (unsigned)L);
 #define DBIE_FIN(T, NR)                                                                            \
     hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, gpos, gB, geo, lam, idx, n_idx, \
-                       n_dev, N, \
-                       acc, dvds, B, dB, fg, tanout)
+                       n_dev, N, L, S, acc, dvds, B, dB, fg, tanout)
     if (tan) {
         if (add_near) DBIE_FIN(true, true);
         else DBIE_FIN(true, false);

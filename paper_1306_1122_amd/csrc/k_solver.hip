@@ -872,6 +872,11 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         key.stream = rs;
         key.per32 = per32;
         key.perm = perm;
+        key.acc = ctx_acc(c);
+        key.split = ctx_split(c);
+        key.ppl = sh.ppl;
+        key.waves = sh.waves;
+        key.persist = sh.persist;
         SolverState& S = ctx_solver(c);
         if (S.exec && std::memcmp(&S.key, &key, sizeof(GraphKey)) == 0) {
             exec = S.exec;

@@ -93,7 +93,8 @@ def dbie_default_solve_opts() -> L.dbie_solve_opts:
 def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[int]] = None,
               precision: str = "fp32c", nearfield_radius_h: float = 2.0,
               dv_over_dsigma_h: float = 1.0 / 6.0, tune: bool = False,
-              tune_cache: Optional[str] = None, quad_points: int = 0, stream=None) -> Context:
+              tune_cache: Optional[str] = None, quad_points: int = 0, pixel_split: int = 0,
+              stream=None) -> Context:
     """boundaries: list of dict(B0=[3, ny, nx] float64 CUDA tensor, x0=, y0=, h=); xyz: [3, N].
     quad_points = 0 selects the nodal sum (Eq. 16); 2..4 the 9-node elements of Eq. (15) with that many
     Gauss points per element side."""
@@ -130,6 +131,7 @@ def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[
     opt.tune = int(bool(tune))
     opt.tune_cache = tune_cache.encode() if tune_cache else None
     opt.quad_points = int(quad_points)
+    opt.pixel_split = int(pixel_split)
     h = ctypes.c_void_p()
     rc = lib.dbie_init(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), _stream(stream))
     if rc != L.DBIE_OK:
@@ -321,6 +323,12 @@ def dbie_trace_lines(ctx: Context, lam_grid: torch.Tensor, origin, spacing, box,
                                    xyz.data_ptr() if N else None, count.data_ptr() if N else None,
                                    _stream(stream)), ctx, "dbie_trace_lines")
     return dict(xyz=xyz, count=count)
+
+
+def dbie_query_split(ctx: Context) -> int:
+    v = ctypes.c_int32()
+    _check(_lib().dbie_query_split(ctx.handle, ctypes.byref(v)), ctx, "dbie_query_split")
+    return int(v.value)
 
 
 def dbie_destroy(ctx: Context):

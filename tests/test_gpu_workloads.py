@@ -32,9 +32,11 @@ def batched():
 
 
 def test_batched_one_launch_equals_separate_launches(batched):
+    """Bitwise, with the same pixel slicing on both sides (one slice: the automatic choice would give
+    the small separate contexts several, which regroups the FP64 sums)."""
     w = batched
     bds = [dict(B0=T(b.B0), x0=b.x0, y0=b.y0, h=b.h) for b in w.boundaries]
-    ctx = D.dbie_init(bds, T(w.xyz), seg=w.seg, precision="fp32c")
+    ctx = D.dbie_init(bds, T(w.xyz), seg=w.seg, precision="fp32c", pixel_split=1)
     lam = T(w.lam)
     out = D.dbie_eval_field(ctx, lam, want_tan=True)
     again = D.dbie_eval_field(ctx, lam, want_tan=True)
@@ -44,7 +46,7 @@ def test_batched_one_launch_equals_separate_launches(batched):
     rng = np.random.default_rng(41)
     for b in rng.choice(len(w.boundaries), 6, replace=False):
         s0, s1 = int(w.seg[b]), int(w.seg[b + 1])
-        c1 = D.dbie_init([bds[b]], T(w.xyz[:, s0:s1]), precision="fp32c")
+        c1 = D.dbie_init([bds[b]], T(w.xyz[:, s0:s1]), precision="fp32c", pixel_split=1)
         one = D.dbie_eval_field(c1, T(w.lam[:, s0:s1]), want_tan=True)
         for k in ("B", "dB", "tan", "fg"):
             assert torch.equal(one[k], out[k][:, s0:s1]), (b, k)
@@ -137,3 +139,52 @@ def test_persistent_form_equals_grid_launch(batched):
         assert torch.equal(outs[0][k], outs[2][k]) and torch.equal(outs[0][k], outs[4][k]), k
     for k in ("lam", "status", "trials", "B", "fg"):
         assert torch.equal(outs[1][k], outs[3][k]) and torch.equal(outs[1][k], outs[5][k]), k
+
+
+@pytest.mark.parametrize("G", [0, 2])
+def test_pixel_slices_match_one_slice_and_the_oracle(G):
+    """Few points (the slices fill the chip): every slicing agrees with one slice to FP64 rounding of
+    the regrouped sums, and with the oracle to the FP32C bar; each is deterministic."""
+    rng = np.random.default_rng(51)
+    nx, ny = 77, 45
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    n = 1500
+    xyz = np.stack([rng.uniform(-2, nx + 1, n), rng.uniform(-2, ny + 1, n), rng.uniform(0.4, 30, n)])
+    lam = rng.uniform(-0.5, 0.5, size=(3, n))
+    outs = {}
+    for S in (1, 2, 7, 32, 0):
+        ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision="fp32c", pixel_split=S,
+                          quad_points=G)
+        assert D.dbie_query_split(ctx) == S or (S == 0 and D.dbie_query_split(ctx) >= 1)
+        a = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+        b = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+        for k in ("B", "dB", "tan", "fg"):
+            assert torch.equal(a[k], b[k]), (S, k)
+        outs[S] = a
+    print("automatic slices:", D.dbie_query_split(ctx), flush=True)
+    for S, o in outs.items():
+        for k in ("B", "dB", "tan"):
+            assert rel(o[k].cpu(), outs[1][k].cpu()) <= 1e-13, (S, k)
+    if G == 0:
+        B, dB, tan = oracle.field(B0, 0.0, 0.0, 1.0, xyz, lam, tangents=True)
+    else:
+        B, dB, tan = oracle.field_quad9(B0, 0.0, 0.0, 1.0, xyz, lam, G=G, tangents=True)
+    for k, ref in (("B", B), ("dB", dB), ("tan", tan)):
+        assert rel(outs[0][k].cpu(), ref) <= 1e-5, k
+
+
+def test_captured_solve_survives_a_reallocated_accumulator():
+    """A solve replays its captured rounds; an evaluation with more trials in between reallocates the
+    accumulator, so the next solve must capture again (same results, bitwise)."""
+    rng = np.random.default_rng(52)
+    B0 = rng.normal(size=(3, 40, 40)).astype(np.float32).astype(np.float64)
+    n = 3000
+    xyz = np.stack([rng.uniform(0, 39, n), rng.uniform(0, 39, n), rng.uniform(0.5, 20, n)])
+    ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision="fp32c")
+    lam0 = rng.uniform(0, 0.2, size=(3, n))
+    a = D.dbie_solve_lambda(ctx, T(lam0), method="lm", max_trials=10, fp64_accept=False)
+    D.dbie_eval_field(ctx, T(rng.uniform(-1, 1, size=(6, 3, n))))
+    b = D.dbie_solve_lambda(ctx, T(lam0), method="lm", max_trials=10, fp64_accept=False)
+    c = D.dbie_solve_lambda(ctx, T(lam0), method="lm", max_trials=10, fp64_accept=False, use_graph=False)
+    for k in ("lam", "status", "trials", "B", "fg"):
+        assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k]), k
