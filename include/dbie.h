@@ -208,6 +208,20 @@ DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t*
 /* Pixel slices per FP32C launch (dbie_options.pixel_split, or the automatic choice); 1 for FP64. */
 DBIE_API int dbie_query_split(const dbie_ctx* ctx, int32_t* slices);
 
+/* Caller-owned work memory (no operation of the paper: device-memory plumbing for callers that manage
+ * their own pools). dbie_workspace_bytes returns the bytes one workspace needs for every call on this
+ * context with one trial per evaluation (L = 1): dbie_eval_field(_scalar), dbie_solve_lambda with
+ * either method and up to 1e6 trials, dbie_grad and dbie_trace_lines (DBIE_E_INVAL for NULL). The
+ * figure depends on the tile shape: ask again after dbie_set_tile_shape.
+ * dbie_set_workspace hands the context `dev` (device memory, 256-byte aligned, >= that many bytes;
+ * else DBIE_E_INVAL / DBIE_E_WORKSPACE); the library frees the work memory it had allocated itself
+ * (after synchronising the device) and allocates none after that: a call needing more (L > 1 trials)
+ * returns DBIE_E_WORKSPACE. dev = NULL goes back to library-allocated work memory. The buffer stays
+ * the caller's: it must outlive its use by the context (until replaced or dbie_destroy), and calls on
+ * one context must not overlap. */
+DBIE_API int64_t dbie_workspace_bytes(const dbie_ctx* ctx);
+DBIE_API int dbie_set_workspace(dbie_ctx* ctx, void* dev, int64_t bytes);
+
 /* Field-line tracing (the paper's field-line figures; current lines from J = curl B, Eq. 14).
  * Lambda at a point comes from trilinear interpolation of a regular grid (coordinates clamped to
  * the grid): node (i, j, k) at (x0 + i dx, y0 + j dy, z0 + k dz), lambda device double [3][nz][ny][nx]

@@ -91,8 +91,12 @@ struct dbie_ctx {
     int32_t* work = nullptr;    // tile counter of the persistent FP32C form
     int32_t split = 1;          // FP32C pixel slices per launch (grid z); acc holds split x L slices
     int32_t cus = 256;          // compute units of the device
-    double* acc = nullptr;      // [L][kAcc][N]
-    int64_t acc_L = 0;
+    double* acc = nullptr;      // [split][L][kAcc][N]
+    int64_t acc_L = 0;          // slices x trials the accumulator holds
+    bool acc_owned = true;      // false: it lies in the caller's workspace
+    char* ws = nullptr;         // caller-owned workspace (dbie_set_workspace), or NULL
+    int64_t ws_bytes = 0;
+    size_t ws_off[kWsRegions] = {}, ws_size[kWsRegions] = {};
     SolverState solver{};
     void* scratch[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t scratch_bytes[4] = {0, 0, 0, 0};
@@ -176,7 +180,7 @@ void free_ctx(dbie_ctx* c) {
     (void)hipFree(c->tiles32);
     (void)hipFree(c->tiles32t);
     (void)hipFree(c->work);
-    (void)hipFree(c->acc);
+    if (c->acc_owned) (void)hipFree(c->acc);
     solver_free(c->solver);
     for (int k = 0; k < 4; ++k) (void)hipFree(c->scratch[k]);
     for (auto e : c->trace_ev) (void)hipEventDestroy(e);
@@ -221,9 +225,20 @@ namespace dbie {
 int ensure_acc(dbie_ctx* c, int64_t L) {
     const int64_t need = L * c->split;   // L trials x pixel slices
     if (c->acc && c->acc_L >= need) return DBIE_OK;
-    (void)hipFree(c->acc);
+    if (c->ws) {
+        const size_t per = (size_t)kAcc * std::max<int64_t>(c->N, 1) * sizeof(double);
+        void* r = ctx_ws_region(c, kWsAcc, (size_t)need * per);
+        if (r == kWsTooSmall)
+            return fail(c, DBIE_E_WORKSPACE, "the caller's workspace holds the sums of one trial per call");
+        c->acc = (double*)r;
+        c->acc_L = (int64_t)(c->ws_size[kWsAcc] / per);
+        c->acc_owned = false;
+        return DBIE_OK;
+    }
+    if (c->acc_owned) (void)hipFree(c->acc);
     c->acc = nullptr;
     c->acc_L = 0;
+    c->acc_owned = true;
     hipError_t e = dalloc(&c->acc, (size_t)(need * kAcc * std::max<int64_t>(c->N, 1)));
     if (e != hipSuccess) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the accumulator workspace");
     c->acc_L = need;
@@ -273,8 +288,20 @@ const BoundaryDev& ctx_bnd_host(const dbie_ctx* c, int b) { return c->bnd_h[b]; 
 int64_t ctx_n(const dbie_ctx* c) { return c->N; }
 const int32_t* ctx_perm(const dbie_ctx* c) { return c->perm; }
 const int64_t* ctx_seg(const dbie_ctx* c) { return c->seg.data(); }
+void* const kWsTooSmall = (void*)&kWsTooSmall;
+
+void* ctx_ws_region(dbie_ctx* c, int region, size_t bytes) {
+    if (!c->ws) return nullptr;
+    if (region < 0 || region >= kWsRegions || bytes > c->ws_size[region]) return kWsTooSmall;
+    return c->ws + c->ws_off[region];
+}
+
 void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes) {
     if (slot < 0 || slot >= 4) return nullptr;
+    if (c->ws) {
+        void* r = ctx_ws_region(c, kWsSlot0 + slot, bytes);
+        return r == kWsTooSmall ? nullptr : r;
+    }
     if (c->scratch[slot] && c->scratch_bytes[slot] >= bytes) return c->scratch[slot];
     (void)hipFree(c->scratch[slot]);
     c->scratch[slot] = nullptr;
@@ -299,6 +326,21 @@ int ctx_fail(dbie_ctx* c, int code, const char* msg) { return fail(c, code, msg)
 double* ctx_xyz(dbie_ctx* c) { return c->xyz; }
 const void* ctx_acc(const dbie_ctx* c) { return c->acc; }
 int32_t ctx_split(const dbie_ctx* c) { return c->split; }
+
+// Regions of a caller-owned workspace, each a multiple of 256 bytes: the sums of one trial (all
+// pixel slices), the solver block (any method, up to 1e6 trials, any tile shape), and scratch slots
+// 0 (dbie_grad's evaluation, dbie_trace_lines), 1 (dbie_grad's gB0 part), 2 (tuning, in dbie_init
+// only: none) and 3 (the expanded lambda of one single-lambda trial).
+void ws_sizes(const dbie_ctx* c, size_t sz[kWsRegions]) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t n = (size_t)std::max<int64_t>(c->N, 1);
+    sz[kWsAcc] = up((size_t)kAcc * n * (size_t)c->split * sizeof(double));
+    sz[kWsSolver] = up(solver_workspace_bytes(c));
+    sz[kWsSlot0 + 0] = up(std::max(24 * n * sizeof(double), 27 * n * sizeof(double) + (2 * n + 64) * sizeof(int32_t)));
+    sz[kWsSlot0 + 1] = up(grad_workspace_bytes(c));
+    sz[kWsSlot0 + 2] = 0;
+    sz[kWsSlot0 + 3] = up(3 * n * sizeof(double));
+}
 hipError_t ctx_prep_points(dbie_ctx* c, int32_t* flag, hipStream_t s) {
     const double r = (c->opt.precision == DBIE_FP32C) ? c->opt.nearfield_radius_h : 0.0;
     return launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->gB, c->xyz, c->N, c->geo, r * r, 1, flag, nullptr,
@@ -731,6 +773,52 @@ int dbie_query_persistent(const dbie_ctx* c, int32_t* plain, int32_t* with_tange
     if (!c) return DBIE_E_INVAL;
     if (plain) *plain = c->shape.persist;
     if (with_tangents) *with_tangents = c->shape_tan.persist;
+    return DBIE_OK;
+}
+
+int64_t dbie_workspace_bytes(const dbie_ctx* c) {
+    if (!c) return DBIE_E_INVAL;
+    size_t sz[kWsRegions];
+    ws_sizes(c, sz);
+    size_t t = 0;
+    for (int r = 0; r < kWsRegions; ++r) t += sz[r];
+    return (int64_t)t;
+}
+
+int dbie_set_workspace(dbie_ctx* c, void* dev, int64_t bytes) {
+    if (!c) return DBIE_E_INVAL;
+    if (dev && ((uintptr_t)dev % 256 != 0)) return fail(c, DBIE_E_INVAL, "workspace must be 256-byte aligned");
+    size_t sz[kWsRegions];
+    ws_sizes(c, sz);
+    size_t total = 0;
+    for (int r = 0; r < kWsRegions; ++r) total += sz[r];
+    if (dev && bytes < (int64_t)total) return fail(c, DBIE_E_WORKSPACE, "workspace smaller than dbie_workspace_bytes");
+    // nothing may still use the buffers being given up
+    DBIE_HIP(c, hipDeviceSynchronize());
+    if (c->acc_owned) (void)hipFree(c->acc);
+    c->acc = nullptr;
+    c->acc_L = 0;
+    c->acc_owned = true;
+    for (int k = 0; k < 4; ++k) {
+        if (!c->ws) (void)hipFree(c->scratch[k]);
+        c->scratch[k] = nullptr;
+        c->scratch_bytes[k] = 0;
+    }
+    SolverState& S = c->solver;
+    if (S.exec) (void)hipGraphExecDestroy(S.exec);
+    S.exec = nullptr;
+    if (S.block_owned) (void)hipFree(S.block);
+    S.block = nullptr;
+    S.bytes = 0;
+    S.block_owned = false;
+    c->ws = (char*)dev;
+    c->ws_bytes = dev ? bytes : 0;
+    size_t off = 0;
+    for (int r = 0; r < kWsRegions; ++r) {
+        c->ws_off[r] = off;
+        c->ws_size[r] = dev ? sz[r] : 0;
+        off += sz[r];
+    }
     return DBIE_OK;
 }
 

@@ -31,6 +31,7 @@ struct SolverState {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     void* block = nullptr;       // one allocation for every per-point solver array
     int64_t bytes = 0;
+    bool block_owned = false;    // false: the block lies in the caller's workspace
     int32_t* count_h = nullptr;  // pinned host word: active-point count
     int32_t last_rounds = 0;     // rounds of the last solve
     int32_t* last_conv = nullptr;  // device: points converged in each round of the last solve
@@ -85,7 +86,15 @@ double* ctx_xyz(dbie_ctx* c);   // the context's own copy of the points (device 
 // as dbie_init; invalid points are flagged in *flag and given safe geometry).
 hipError_t ctx_prep_points(dbie_ctx* c, int32_t* flag, hipStream_t s);
 // Library-owned scratch block `slot` of at least `bytes` (grown on need); NULL on failure.
-void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes);
+void* ctx_scratch(dbie_ctx* c, int slot, size_t bytes);   // NULL if it cannot be provided
+// Caller-owned workspace (dbie_set_workspace): the region of one consumer, NULL when no workspace is
+// set (the library allocates), kWsTooSmall when the region cannot hold `bytes`.
+enum { kWsAcc = 0, kWsSolver = 1, kWsSlot0 = 2, kWsRegions = 6 };
+extern void* const kWsTooSmall;
+void* ctx_ws_region(dbie_ctx* c, int region, size_t bytes);
+size_t solver_workspace_bytes(const dbie_ctx* c);
+size_t grad_workspace_bytes(const dbie_ctx* c);   // dbie_grad's gB0 part (scratch slot 1)
+void ws_sizes(const dbie_ctx* c, size_t sz[kWsRegions]);
 // Near-field pairs grouped by pixel (global pixel index over all magnetograms), for the adjoint.
 struct NearLists {
     int64_t npix_total;      // quadrature grid points over all boundaries (the pixels for the nodal rule)

@@ -680,9 +680,54 @@ void solver_free(SolverState& s) {
     if (s.ev_in) (void)hipEventDestroy(s.ev_in);
     if (s.ev_out) (void)hipEventDestroy(s.ev_out);
     if (s.rs) (void)hipStreamDestroy(s.rs);
-    (void)hipFree(s.block);
+    if (s.block_owned) (void)hipFree(s.block);
     if (s.count_h) (void)hipHostFree(s.count_h);
     s = SolverState{};
+}
+
+// The solver block: every per-point array and the device schedules, 256-byte aligned, for N points,
+// nb magnetograms, max_rounds trials and per32 points per FP32C tile.
+struct SolverOffsets {
+    size_t lam, best, bphi, bst, tr, st, act, B, dB, tan, fg, conv, V, F, Xr, Fr, ph, aux;
+    size_t mu, mut, phi, rho, u, jac, nu, lph, list, bsum, nact, rnd, cnt, rank, o32, o64, seg, t32, t64;
+    int64_t max32, max64;
+    int32_t nblk;
+    size_t bytes;
+};
+
+static SolverOffsets solver_layout(int64_t N, int32_t nb, int32_t max_rounds, int32_t per32) {
+    SolverOffsets o;
+    o.max32 = pad8((N + per32 - 1) / per32 + nb);
+    o.max64 = pad8((N + 255) / 256 + nb);
+    o.nblk = (int32_t)((N + kCompactBlock - 1) / kCompactBlock);
+    Layout L;
+    const size_t n = (size_t)N;
+    o.lam = L.take<double>(3 * n), o.best = L.take<double>(3 * n), o.bphi = L.take<double>(n);
+    o.bst = L.take<int32_t>(n), o.tr = L.take<int32_t>(n), o.st = L.take<int32_t>(n), o.act = L.take<int32_t>(n);
+    o.B = L.take<double>(3 * n), o.dB = L.take<double>(9 * n), o.tan = L.take<double>(12 * n),
+    o.fg = L.take<double>(2 * n);
+    o.conv = L.take<int32_t>((size_t)max_rounds + 1);
+    o.V = L.take<double>(12 * n), o.F = L.take<double>(4 * n), o.Xr = L.take<double>(3 * n),
+    o.Fr = L.take<double>(n), o.ph = L.take<int32_t>(n), o.aux = L.take<int32_t>(n);
+    o.mu = L.take<double>(3 * n), o.mut = L.take<double>(3 * n), o.phi = L.take<double>(n),
+    o.rho = L.take<double>(n), o.u = L.take<double>(4 * n), o.jac = L.take<double>(12 * n),
+    o.nu = L.take<double>(n), o.lph = L.take<int32_t>(n);
+    o.list = L.take<int32_t>(n), o.bsum = L.take<int32_t>((size_t)o.nblk + 1), o.nact = L.take<int32_t>(1),
+    o.rnd = L.take<int32_t>(1), o.cnt = L.take<int32_t>((size_t)nb), o.rank = L.take<int32_t>((size_t)nb + 1),
+    o.o32 = L.take<int32_t>((size_t)nb + 1), o.o64 = L.take<int32_t>((size_t)nb + 1),
+    o.seg = L.take<int64_t>((size_t)nb + 1);
+    o.t32 = L.take<Tile>((size_t)o.max32), o.t64 = L.take<Tile>((size_t)o.max64);
+    o.bytes = L.off;
+    return o;
+}
+
+size_t solver_workspace_bytes(const dbie_ctx* c) {
+    // every budget the API accepts (<= 1e6 trials) and the smallest instantiated tile (most tiles)
+    F32Shape sh[16];
+    const int n = std::min(field32c_shapes(sh, 16), 16);
+    int32_t per = 1 << 30;
+    for (int k = 0; k < n; ++k) per = std::min(per, sh[k].ppl * sh[k].waves * 64);
+    return solver_layout(ctx_n(c), ctx_nb(c), 1000000, per).bytes;
 }
 
 static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs& b) {
@@ -691,61 +736,53 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
     const int32_t nb = ctx_nb(c);
     const F32Shape sh = get_shape(c, lm_mode);
     const int32_t per32 = sh.ppl * sh.waves * 64;
-    b.max32 = pad8((N + per32 - 1) / per32 + nb);
-    b.max64 = pad8((N + 255) / 256 + nb);
-    b.nblk = (int32_t)((N + kCompactBlock - 1) / kCompactBlock);
+    const SolverOffsets o = solver_layout(N, nb, max_rounds, per32);
+    b.max32 = o.max32;
+    b.max64 = o.max64;
+    b.nblk = o.nblk;
     b.max_rounds = max_rounds;
-    Layout L;
-    const size_t n = (size_t)N;
-    const size_t oLam = L.take<double>(3 * n), oBest = L.take<double>(3 * n), oBphi = L.take<double>(n);
-    const size_t oBst = L.take<int32_t>(n), oTr = L.take<int32_t>(n), oSt = L.take<int32_t>(n),
-                 oAct = L.take<int32_t>(n);
-    const size_t oB = L.take<double>(3 * n), odB = L.take<double>(9 * n), oTan = L.take<double>(12 * n),
-                 oFg = L.take<double>(2 * n);
-    const size_t oConv = L.take<int32_t>((size_t)max_rounds + 1);
-    const size_t oV = L.take<double>(12 * n), oF = L.take<double>(4 * n), oXr = L.take<double>(3 * n),
-                 oFr = L.take<double>(n), oPh = L.take<int32_t>(n), oAux = L.take<int32_t>(n);
-    const size_t oMu = L.take<double>(3 * n), oMut = L.take<double>(3 * n), oPhi = L.take<double>(n),
-                 oRho = L.take<double>(n), oU = L.take<double>(4 * n), oJac = L.take<double>(12 * n),
-                 oNu = L.take<double>(n), oLph = L.take<int32_t>(n);
-    const size_t oList = L.take<int32_t>(n), oBsum = L.take<int32_t>((size_t)b.nblk + 1),
-                 oNact = L.take<int32_t>(1), oRnd = L.take<int32_t>(1), oCnt = L.take<int32_t>((size_t)nb),
-                 oRank = L.take<int32_t>((size_t)nb + 1), oO32 = L.take<int32_t>((size_t)nb + 1),
-                 oO64 = L.take<int32_t>((size_t)nb + 1), oSeg = L.take<int64_t>((size_t)nb + 1);
-    const size_t oT32 = L.take<Tile>((size_t)b.max32), oT64 = L.take<Tile>((size_t)b.max64);
-    const size_t need = L.off;
-    if (!S.block || S.bytes < (int64_t)need) {
-        (void)hipFree(S.block);
+    const size_t need = o.bytes;
+    void* ws = ctx_ws_region(c, kWsSolver, need);
+    if (ws == kWsTooSmall)
+        return ctx_fail(c, DBIE_E_WORKSPACE, "the caller's workspace is too small for this solve");
+    if (ws) {
+        if (S.block && S.block_owned) (void)hipFree(S.block);
+        S.block = ws;
+        S.bytes = (int64_t)need;
+        S.block_owned = false;
+    } else if (!S.block || !S.block_owned || S.bytes < (int64_t)need) {
+        if (S.block && S.block_owned) (void)hipFree(S.block);
         S.block = nullptr;
         S.bytes = 0;
         if (hipMalloc(&S.block, need) != hipSuccess)
             return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the solver workspace");
         S.bytes = (int64_t)need;
+        S.block_owned = true;
     }
     if (!S.count_h) {
         if (hipHostMalloc((void**)&S.count_h, sizeof(int32_t)) != hipSuccess)
             return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate pinned host memory");
     }
     char* base = (char*)S.block;
-    auto D = [&](size_t o) { return (void*)(base + o); };
-    b.C = Common{(double*)D(oLam), (double*)D(oBest), (double*)D(oBphi), (int32_t*)D(oBst), (int32_t*)D(oTr),
-                 (int32_t*)D(oSt), (int32_t*)D(oAct), (double*)D(oB), (double*)D(odB), (double*)D(oTan),
-                 (double*)D(oFg), (int32_t*)D(oConv)};
-    b.nm = NMDev{(double*)D(oV), (double*)D(oF), (double*)D(oXr), (double*)D(oFr), (int32_t*)D(oPh),
-                 (int32_t*)D(oAux)};
-    b.lm = LMDev{(double*)D(oMu), (double*)D(oMut), (double*)D(oPhi), (double*)D(oRho), (double*)D(oU),
-                 (double*)D(oJac), (double*)D(oNu), (int32_t*)D(oLph)};
-    b.list = (int32_t*)D(oList);
-    b.bsum = (int32_t*)D(oBsum);
-    b.n_active = (int32_t*)D(oNact);
-    b.round = (int32_t*)D(oRnd);
-    b.cnt_b = (int32_t*)D(oCnt);
-    b.rank = (int32_t*)D(oRank);
-    b.off32 = (int32_t*)D(oO32);
-    b.off64 = (int32_t*)D(oO64);
-    b.segd = (int64_t*)D(oSeg);
-    b.tiles32 = (Tile*)D(oT32);
-    b.tiles64 = (Tile*)D(oT64);
+    auto D = [&](size_t off) { return (void*)(base + off); };
+    b.C = Common{(double*)D(o.lam), (double*)D(o.best), (double*)D(o.bphi), (int32_t*)D(o.bst), (int32_t*)D(o.tr),
+                 (int32_t*)D(o.st), (int32_t*)D(o.act), (double*)D(o.B), (double*)D(o.dB), (double*)D(o.tan),
+                 (double*)D(o.fg), (int32_t*)D(o.conv)};
+    b.nm = NMDev{(double*)D(o.V), (double*)D(o.F), (double*)D(o.Xr), (double*)D(o.Fr), (int32_t*)D(o.ph),
+                 (int32_t*)D(o.aux)};
+    b.lm = LMDev{(double*)D(o.mu), (double*)D(o.mut), (double*)D(o.phi), (double*)D(o.rho), (double*)D(o.u),
+                 (double*)D(o.jac), (double*)D(o.nu), (int32_t*)D(o.lph)};
+    b.list = (int32_t*)D(o.list);
+    b.bsum = (int32_t*)D(o.bsum);
+    b.n_active = (int32_t*)D(o.nact);
+    b.round = (int32_t*)D(o.rnd);
+    b.cnt_b = (int32_t*)D(o.cnt);
+    b.rank = (int32_t*)D(o.rank);
+    b.off32 = (int32_t*)D(o.o32);
+    b.off64 = (int32_t*)D(o.o64);
+    b.segd = (int64_t*)D(o.seg);
+    b.tiles32 = (Tile*)D(o.t32);
+    b.tiles64 = (Tile*)D(o.t64);
     return DBIE_OK;
 }
 

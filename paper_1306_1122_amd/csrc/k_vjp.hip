@@ -318,6 +318,33 @@ __global__ void k_resid_jac(int64_t N, const BoundaryDev* __restrict__ bnd, cons
 
 using namespace dbie;
 
+namespace dbie {
+// Pixel tiles of the two adjoint kernels and the workspace sizes of dbie_grad's gB0 part.
+struct GradPlan {
+    std::vector<PixTile> pt, pt32;
+    size_t szc, szt, szs, szg;
+    size_t bytes() const { return szc + szt + szs + szg; }
+};
+
+static GradPlan grad_plan(const dbie_ctx* c) {
+    GradPlan g;
+    const int32_t nb = ctx_nb(c);
+    for (int32_t b = 0; b < nb; ++b) {
+        const BoundaryDev& bd = ctx_bnd_host(c, b);
+        for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256) g.pt.push_back(PixTile{b, k});
+        for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256 * kVjpPix) g.pt32.push_back(PixTile{b, k});
+    }
+    const QuadGrid grid = ctx_grid(c);
+    g.szc = (size_t)std::max<int64_t>(ctx_n(c), 1) * kVjpCoef * sizeof(double);
+    g.szt = ((g.pt.size() + g.pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
+    g.szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
+    g.szg = grid.G ? (size_t)grid.n_total * 3 * sizeof(double) : 0;
+    return g;
+}
+
+size_t grad_workspace_bytes(const dbie_ctx* c) { return grad_plan(c).bytes(); }
+}  // namespace dbie
+
 extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const double* gdB, double* glam,
                          double* gB0, double* resid_jac, void* stream) {
     if (!c) return DBIE_E_INVAL;
@@ -350,17 +377,11 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
     if (gB0) {
         // pixel tiles of every boundary, and the point segments on the device
         const QuadGrid grid = ctx_grid(c);
-        std::vector<PixTile> pt, pt32;
-        for (int32_t b = 0; b < nb; ++b) {
-            const BoundaryDev& bd = ctx_bnd_host(c, b);
-            for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256) pt.push_back(PixTile{b, k});
-            for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256 * kVjpPix) pt32.push_back(PixTile{b, k});
-        }
-        const size_t szc = (size_t)std::max<int64_t>(N, 1) * kVjpCoef * sizeof(double);
-        const size_t szt = ((pt.size() + pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
-        const size_t szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
-        const size_t szg = grid.G ? (size_t)grid.n_total * 3 * sizeof(double) : 0;
-        char* w = (char*)ctx_scratch(c, 1, szc + szt + szs + szg);
+        const GradPlan gp = grad_plan(c);
+        const std::vector<PixTile>& pt = gp.pt;
+        const std::vector<PixTile>& pt32 = gp.pt32;
+        const size_t szc = gp.szc, szt = gp.szt, szs = gp.szs;
+        char* w = (char*)ctx_scratch(c, 1, gp.bytes());
         if (!w) return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the adjoint workspace");
         double* coef = (double*)w;
         PixTile* ptd = (PixTile*)(w + szc);

@@ -55,6 +55,7 @@ class Context:
         self.shapes = shapes
         self.precision = precision
         self.device = device
+        self._ws = None   # a caller-owned workspace handed to the context (kept alive until close)
 
     @property
     def n_pixels(self) -> int:
@@ -64,6 +65,7 @@ class Context:
         if self.handle:
             _lib().dbie_destroy(self.handle)
             self.handle = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -329,6 +331,24 @@ def dbie_query_split(ctx: Context) -> int:
     v = ctypes.c_int32()
     _check(_lib().dbie_query_split(ctx.handle, ctypes.byref(v)), ctx, "dbie_query_split")
     return int(v.value)
+
+
+def dbie_workspace_bytes(ctx: Context) -> int:
+    return int(_lib().dbie_workspace_bytes(ctx.handle))
+
+
+def dbie_set_workspace(ctx: Context, ws: Optional[torch.Tensor]):
+    """Give the context a caller-owned device workspace (a uint8 tensor of at least
+    dbie_workspace_bytes(ctx) bytes, kept alive by the context object), or None to go back."""
+    if ws is None:
+        _check(_lib().dbie_set_workspace(ctx.handle, None, 0), ctx, "dbie_set_workspace")
+        ctx._ws = None
+        return
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check(_lib().dbie_set_workspace(ctx.handle, ws.data_ptr(), ws.numel() * ws.element_size()), ctx,
+           "dbie_set_workspace")
+    ctx._ws = ws
 
 
 def dbie_destroy(ctx: Context):

@@ -125,6 +125,11 @@ def test_init_argument_checks(lib, case, msg):
     assert not out.value
 
 
+def test_workspace_calls_on_null_context(lib):
+    assert lib.dbie_workspace_bytes(None) == L.DBIE_E_INVAL
+    assert lib.dbie_set_workspace(None, None, 0) == L.DBIE_E_INVAL
+
+
 def test_calls_on_null_context_are_rejected(lib):
     assert lib.dbie_eval_field(None, None, 1, None, None, None, None, None) == L.DBIE_E_INVAL
     assert lib.dbie_timing(None, 1) == L.DBIE_E_INVAL
