@@ -53,7 +53,8 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                                                const BoundaryDev* __restrict__ bnd,
                                                const int64_t* __restrict__ seg, Geo geo, int64_t N,
                                                const double* __restrict__ gpos,
-                                               const double* __restrict__ coef, double* __restrict__ gW) {
+                                               const double* __restrict__ coef, double* __restrict__ gW,
+                                               int64_t slice_stride) {
     __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef][kVjpPts];
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
@@ -63,7 +64,10 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
     const double a = live ? gpos[bd.gpos_off + k % bd.gcols] : 0.0;
     const double bb = live ? gpos[bd.gpos_off + bd.gcols + k / bd.gcols] : 0.0;
     double acc[3] = {0.0, 0.0, 0.0};
-    const int64_t p0 = seg[pt.b], p1 = seg[pt.b + 1];
+    const int64_t s0 = seg[pt.b], s1 = seg[pt.b + 1];
+    const int64_t nch = (s1 - s0 + kVjpPts - 1) / kVjpPts;
+    const int64_t p0 = s0 + (int64_t)blockIdx.y * nch / gridDim.y * kVjpPts;
+    const int64_t p1 = min(s1, s0 + (int64_t)(blockIdx.y + 1) * nch / gridDim.y * kVjpPts);
     for (int64_t i0 = p0; i0 < p1; i0 += kVjpPts) {
         const int n = (int)min<int64_t>(kVjpPts, p1 - i0);
         __syncthreads();
@@ -103,7 +107,8 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
     }
     if (live) {
         const int64_t o = bd.gpl_off + k;
-        for (int p = 0; p < 3; ++p) gW[o + (int64_t)p * ngrid] = acc[p];
+        double* out = gW + (int64_t)blockIdx.y * slice_stride;
+        for (int p = 0; p < 3; ++p) out[o + (int64_t)p * ngrid] = acc[p];
     }
 }
 
@@ -165,7 +170,8 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
                                                 const BoundaryDev* __restrict__ bnd,
                                                 const int64_t* __restrict__ seg, const int32_t* __restrict__ perm,
                                                 const float4* __restrict__ gposf, Geo geo, int64_t N,
-                                                const double* __restrict__ coef, double* __restrict__ gW) {
+                                                const double* __restrict__ coef, double* __restrict__ gW,
+                                                int64_t slice_stride) {
     __shared__ float sp[kVjp32F][kVjp32Pts];
     __shared__ int any_near;
     const PixTile pt = ptiles[blockIdx.x];
@@ -198,7 +204,11 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
 #pragma unroll
     for (int j = 0; j < PPX; ++j)
         for (int p = 0; p < 3; ++p) tot[j][p] = 0.0;
-    const int64_t p0 = seg[pt.b], p1 = seg[pt.b + 1];
+    // point slice blockIdx.y of gridDim.y: an even share of the boundary's 64-point chunks
+    const int64_t s0 = seg[pt.b], s1 = seg[pt.b + 1];
+    const int64_t nch = (s1 - s0 + kVjp32Pts - 1) / kVjp32Pts;
+    const int64_t p0 = s0 + (int64_t)blockIdx.y * nch / gridDim.y * kVjp32Pts;
+    const int64_t p1 = min(s1, s0 + (int64_t)(blockIdx.y + 1) * nch / gridDim.y * kVjp32Pts);
     for (int64_t i0 = p0; i0 < p1; i0 += kVjp32Pts) {
         const int n = (int)min<int64_t>(kVjp32Pts, p1 - i0);
         __syncthreads();
@@ -244,8 +254,18 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
     for (int j = 0; j < PPX; ++j) {
         if (!live[j]) continue;
         const int64_t o = bd.gpl_off + pt.start + (int64_t)threadIdx.x + j * 256;
-        for (int p = 0; p < 3; ++p) gW[o + (int64_t)p * ngrid] = tot[j][p];
+        double* out = gW + (int64_t)blockIdx.y * slice_stride;
+        for (int p = 0; p < 3; ++p) out[o + (int64_t)p * ngrid] = tot[j][p];
     }
+}
+
+// gW[e] = sum over the point slices, in order, of their partial outputs.
+__global__ void k_vjp_reduce(int64_t n, int32_t S, const double* __restrict__ parts, double* __restrict__ gW) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double a = parts[e];
+    for (int32_t y = 1; y < S; ++y) a += parts[(int64_t)y * n + e];
+    gW[e] = a;
 }
 
 // FP64 near pairs of the adjoint: grid point g (global index over all boundaries) gathers the points
@@ -322,8 +342,9 @@ namespace dbie {
 // Pixel tiles of the two adjoint kernels and the workspace sizes of dbie_grad's gB0 part.
 struct GradPlan {
     std::vector<PixTile> pt, pt32;
-    size_t szc, szt, szs, szg;
-    size_t bytes() const { return szc + szt + szs + szg; }
+    int32_t S;                  // point slices of the transpose launch
+    size_t szc, szt, szs, szg, szp;
+    size_t bytes() const { return szc + szt + szs + szg + szp; }
 };
 
 static GradPlan grad_plan(const dbie_ctx* c) {
@@ -335,10 +356,18 @@ static GradPlan grad_plan(const dbie_ctx* c) {
         for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256 * kVjpPix) g.pt32.push_back(PixTile{b, k});
     }
     const QuadGrid grid = ctx_grid(c);
+    // Point slices: the pixel tiles alone are few for small magnetograms (16 workgroups for 128^2 in
+    // FP32C); about four workgroups per compute unit, at least one 64-point chunk per slice.
+    const size_t tiles = ctx_precision(c) == DBIE_FP64 ? g.pt.size() : g.pt32.size();
+    int64_t maxseg = 0;
+    for (int32_t b = 0; b < nb; ++b) maxseg = std::max(maxseg, ctx_seg(c)[b + 1] - ctx_seg(c)[b]);
+    const int64_t want = (1024 + (int64_t)std::max<size_t>(tiles, 1) - 1) / (int64_t)std::max<size_t>(tiles, 1);
+    g.S = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, 64, (maxseg + 63) / 64}));
     g.szc = (size_t)std::max<int64_t>(ctx_n(c), 1) * kVjpCoef * sizeof(double);
     g.szt = ((g.pt.size() + g.pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
     g.szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
     g.szg = grid.G ? (size_t)grid.n_total * 3 * sizeof(double) : 0;
+    g.szp = g.S > 1 ? (size_t)g.S * grid.n_total * 3 * sizeof(double) : 0;
     return g;
 }
 
@@ -387,22 +416,29 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
         PixTile* ptd = (PixTile*)(w + szc);
         int64_t* segd = (int64_t*)(w + szc + szt);
         double* gW = grid.G ? (double*)(w + szc + szt + szs) : gB0;
+        // with point slices the transpose kernels write S partial outputs, reduced into gW in order
+        const int64_t T3 = grid.n_total * 3;
+        double* parts = gp.S > 1 ? (double*)(w + szc + szt + szs + gp.szg) : gW;
         PixTile* ptd32 = ptd + pt.size();
         GRAD_HIP(hipMemcpyAsync(ptd, pt.data(), pt.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
         GRAD_HIP(hipMemcpyAsync(ptd32, pt32.data(), pt32.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
         GRAD_HIP(hipMemcpyAsync(segd, ctx_seg(c), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
         if (N > 0)
             hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
+        const dim3 g64((unsigned)pt.size(), (unsigned)gp.S), g32((unsigned)pt32.size(), (unsigned)gp.S);
         if (ctx_precision(c) == DBIE_FP64) {
-            hipLaunchKernelGGL(k_vjp64, dim3((unsigned)pt.size()), dim3(256), 0, s, ptd, bnd, segd, geo, N,
-                               grid.pos, coef, gW);
+            hipLaunchKernelGGL(k_vjp64, g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos, coef, parts, T3);
         } else {
             if (grid.G)
-                hipLaunchKernelGGL((k_vjp32c<kVjpPix, true>), dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32,
-                                   bnd, segd, ctx_perm(c), grid.posf, geo, N, coef, gW);
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, true>), g32, dim3(256), 0, s, ptd32, bnd, segd, ctx_perm(c),
+                                   grid.posf, geo, N, coef, parts, T3);
             else
-                hipLaunchKernelGGL((k_vjp32c<kVjpPix, false>), dim3((unsigned)pt32.size()), dim3(256), 0, s, ptd32,
-                                   bnd, segd, ctx_perm(c), grid.posf, geo, N, coef, gW);
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, false>), g32, dim3(256), 0, s, ptd32, bnd, segd, ctx_perm(c),
+                                   grid.posf, geo, N, coef, parts, T3);
+        }
+        if (gp.S > 1)
+            hipLaunchKernelGGL(k_vjp_reduce, dim3((unsigned)((T3 + 255) / 256)), dim3(256), 0, s, T3, gp.S, parts, gW);
+        if (ctx_precision(c) != DBIE_FP64) {
             const NearLists nl = ctx_near_lists(c);
             if (nl.n_pairs > 0)
                 hipLaunchKernelGGL(k_vjp_near, dim3((unsigned)((nl.npix_total + 255) / 256)), dim3(256), 0, s,
