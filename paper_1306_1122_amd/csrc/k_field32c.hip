@@ -39,6 +39,17 @@ struct PointState {
     uint32_t msk[PPL];
 };
 
+// Phase in revolutions, reduced to about [0, 1) when FRACT: the rounding error of the product
+// (half an ulp of |lr r|, up to 1.5e-5 revolutions at the 256-revolution bound) is recovered exactly
+// by an FMA and added back after the reduction, leaving r's own rounding as the phase error.
+template <bool FRACT>
+__device__ __forceinline__ float phase_rev(float lr, float r) {
+    const float hi = lr * r;
+    if (!FRACT) return hi;
+    const float lo = fmaf(lr, r, -hi);
+    return __builtin_amdgcn_fractf(hi) + lo;
+}
+
 // One pair given dx, dy (pixels), q = dy^2 + w^2 and the field of the pixel.
 template <bool TAN, bool FRACT>
 __device__ __forceinline__ void pair32(float dx, float dy, float q, const float lt[3], const float lr[3],
@@ -54,7 +65,7 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         // v_sin / v_cos take revolutions and are accurate on [-256, 256]; FRACT reduces first
-        const float tr = FRACT ? __builtin_amdgcn_fractf(lr[p] * r) : lr[p] * r;
+        const float tr = phase_rev<FRACT>(lr[p], r);
         const float sn = __builtin_amdgcn_sinf(tr);
         const float cs = __builtin_amdgcn_cosf(tr);
         const float t = lt[p] * r;
@@ -88,7 +99,7 @@ __device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float
     const float ri3 = ri2 * ri;
     const float dxr = dx * ri2;
     const float dyr = dy * ri2;
-    const float tr = FRACT ? __builtin_amdgcn_fractf(lr * r) : lr * r;
+    const float tr = phase_rev<FRACT>(lr, r);
     const float sn = __builtin_amdgcn_sinf(tr);
     const float cs = __builtin_amdgcn_cosf(tr);
     const float t = lt * r;

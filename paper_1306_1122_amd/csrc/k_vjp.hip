@@ -151,7 +151,9 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
         const float ri5 = ri3 * ri2;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            const float tr = __builtin_amdgcn_fractf(sp[8 + p][e] * r);
+            // phase in revolutions, reduced; the product's rounding recovered by an FMA
+            const float th = sp[8 + p][e] * r;
+            const float tr = __builtin_amdgcn_fractf(th) + fmaf(sp[8 + p][e], r, -th);
             const float sn = __builtin_amdgcn_sinf(tr);
             const float cs = __builtin_amdgcn_cosf(tr);
             const float t = sp[5 + p][e] * r;

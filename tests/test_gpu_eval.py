@@ -225,3 +225,40 @@ def test_scalar_lambda_fast_path(precision):
         B, dB, tan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], lam3, tangents=True)
         for name, ref in (("B", B), ("dB", dB), ("tan", tan)):
             assert rel(out[name][t][:, idx].cpu(), ref) <= TOL[precision], (t, name)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_large_lambda_needs_range_reduction_and_nan_lambda_stays_local(precision):
+    """A 600 x 40 magnetogram with |lambda| h up to 2.9 (near the cap pi/h): lambda r / 2 pi reaches
+    ~277 revolutions, beyond the hardware sin/cos range, so the FP32C kernel takes its range-reduced
+    form (where the FP32 rounding of r, ~ulp(600) = 6e-5 pixel, is the phase error that remains).
+    A NaN lambda at one point gives NaN there only (its wavefront neighbours stay exact)."""
+    rng = np.random.default_rng(8)
+    nx, ny, n = 600, 40, 130
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    xyz = np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0.5, 20, n)])
+    lam = rng.uniform(2.5, 2.9, size=(3, n)) * rng.choice([-1.0, 1.0], size=(3, n))
+
+    class Bd:
+        pass
+
+    bd = Bd()
+    bd.B0, bd.x0, bd.y0, bd.h = B0, 0.0, 0.0, 1.0
+    ctx = ctx_for([bd], xyz, precision)
+    check_against_oracle(ctx, bd, xyz, lam, TOL[precision], fg=False, label=f"large lambda {precision}")
+    bad = lam.copy()
+    bad[1, 17] = np.nan
+    out = D.dbie_eval_field(ctx, T(bad), want_tan=True)
+    ref = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+    torch.cuda.synchronize()
+    keep = np.ones(n, bool)
+    keep[17] = False
+    assert torch.isnan(out["B"][1, 17])
+    for k in ("B", "dB", "tan"):
+        a, b = out[k].cpu().numpy()[:, keep], ref[k].cpu().numpy()[:, keep]
+        assert rel(a, b) <= (0.0 if precision == "fp64" else 1e-6), k
+    # the single-lambda form on the same points
+    sc = D.dbie_eval_field_scalar(ctx, T(lam[:1]), want_tan=True)
+    Bs, dBs, tans = oracle.field(B0, 0.0, 0.0, 1.0, xyz, np.repeat(lam[:1], 3, axis=0), tangents=True)
+    for k, r in (("B", Bs), ("dB", dBs), ("tan", tans)):
+        assert rel(sc[k][0].cpu(), r) <= TOL[precision], k
