@@ -29,9 +29,9 @@ def T(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.fixture(scope="module")
-def case():
-    w = lowlou_table1()
+@pytest.fixture(scope="module", params=["region", "boundary"])
+def case(request):
+    w = lowlou_table1(mapping=request.param)
     bd = w.boundaries[0]
     jj, ii = w.meta["bottom_idx"]
     bottom = bd.B0[:, jj, ii]
@@ -65,7 +65,7 @@ def test_table1_metrics(case):
         rows[name]["converged"] = conv
         fgn = fg.cpu().numpy()
         phis[name] = fgn[0] ** 2 + fgn[1] ** 2
-        print(name, {k: round(v, 3) for k, v in rows[name].items()},
+        print(w.name, name, {k: round(v, 3) for k, v in rows[name].items()},
               "mean Phi %.4f" % float(np.nanmean(phis[name])), flush=True)
     print("paper, present DBIE", {k: paper[k] for k in ("C_vec", "C_cs", "E_n", "E_m", "eps")}, flush=True)
     phi0 = phis[runs[0][0]]

@@ -295,15 +295,17 @@ def config5(seed: int = 1005, n_arcs: int = 4096, per_arc: int = 256) -> Workloa
                     np.array([0, xyz.shape[1]], np.int64), lam, meta=dict(bipoles=bips))
 
 
-def lowlou_table1(seed: int = 1006) -> Workload:
+def lowlou_table1(seed: int = 1006, mapping: str = "region") -> Workload:
     """The Table 1 comparison case: Low & Lou n=3, m=1, l=0.3, Phi=4pi/5 sampled on a 192x192 pixel
-    lower boundary centred on a 64x64x64-pixel test region. Assumed mapping (the case's own grid
-    definition is not reproduced in the paper): the test region spans [-1, 1]^2 x [0, 2], so
-    h = 1/32; boundary nodes at ((k - 95.5) h, (j - 95.5) h); region nodes at x, y = (i - 31.5) h
-    (the central 64 x 64 boundary nodes) and z = k h, k = 0..63. The points are the layers k >= 1
-    (z > 0); the k = 0 layer is the boundary data itself (meta['bottom_idx'] are its pixels)."""
+    lower boundary centred on a 64x64x64-pixel test region. The case's own grid definition is not
+    reproduced in the paper; two mappings are offered: mapping="region", the test region spans
+    [-1, 1]^2 x [0, 2] (h = 1/32, the boundary [-3, 3]^2); mapping="boundary", the boundary spans
+    [-1, 1]^2 (h = 1/96, the region [-1/3, 1/3]^2 x [0, 2/3]). Boundary nodes at ((k - 95.5) h,
+    (j - 95.5) h); region nodes at x, y = (i - 31.5) h (the central 64 x 64 boundary nodes) and
+    z = k h, k = 0..63. The points are the layers k >= 1 (z > 0); the k = 0 layer is the boundary
+    data itself (meta['bottom_idx'] are its pixels)."""
     ll = lowlou_case(n=3, m=1, l=0.3, Phi=4.0 * np.pi / 5.0)
-    h = 1.0 / 32.0
+    h = {"region": 1.0 / 32.0, "boundary": 2.0 / 192.0}[mapping]
     x0 = -95.5 * h
     xs = x0 + h * np.arange(192)
     X, Y = np.meshgrid(xs, xs)
@@ -314,7 +316,7 @@ def lowlou_table1(seed: int = 1006) -> Workload:
     rng = np.random.default_rng(seed)
     lam = rng.uniform(-2.0, 2.0, size=(3, xyz.shape[1]))
     jj, ii = np.meshgrid(np.arange(64) + 64, np.arange(64) + 64, indexing="ij")
-    return Workload("lowlou_n3_192x192_64x64x64", [Boundary(B0, x0, x0, h)], xyz,
+    return Workload("lowlou_n3_192x192_64x64x64_" + mapping, [Boundary(B0, x0, x0, h)], xyz,
                     np.array([0, xyz.shape[1]], np.int64), lam, fp32=False,
                     meta=dict(ll=ll, bottom_idx=(jj.ravel(), ii.ravel()), region_xy=rs))
 
