@@ -188,3 +188,21 @@ def test_captured_solve_survives_a_reallocated_accumulator():
     c = D.dbie_solve_lambda(ctx, T(lam0), method="lm", max_trials=10, fp64_accept=False, use_graph=False)
     for k in ("lam", "status", "trials", "B", "fg"):
         assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k]), k
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32c", 1e-5), ("fp64", 1e-10)])
+def test_largest_grid_workload_sampled(precision, tol):
+    """The 256x256 magnetogram with all 256x256x128 = 8,388,608 points in one launch (the largest
+    single-GPU configuration); the oracle checks a z-stratified sample."""
+    from workloads import config3, z_stratified_subsample
+    w = config3()
+    bd = w.boundaries[0]
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision=precision)
+    out = D.dbie_eval_field(ctx, T(w.lam))
+    torch.cuda.synchronize()
+    idx = z_stratified_subsample(w.xyz, 256, seed=13)
+    B, dB = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], w.lam[:, idx])
+    assert rel(out["B"][:, idx].cpu(), B) <= tol
+    assert rel(out["dB"][:, idx].cpu(), dB) <= tol
+    assert torch.isfinite(out["B"]).all() and torch.isfinite(out["fg"]).all()
+    ctx.close()
