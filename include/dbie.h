@@ -140,7 +140,9 @@ DBIE_API int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_opti
  *   fg     : device double [L][2][N] or NULL    (f_i, g_i; NaN for a DEGENERATE point)
  *   tan    : device double [L][12][N] or NULL   (d/d mu_p, mu = lambda^2, of the rows B_p and
  *                                                dB_p/dx_q: tan[p] and tan[3 + 3p + q])
- * L >= 1. A non-finite lambda gives non-finite outputs for that point only. */
+ * L >= 1. A non-finite lambda gives non-finite outputs for that point only. In an FP32C context the
+ * call with tan != NULL runs the tangent variant of the kernel, whose B and dB agree with the call
+ * without tangents to FP32 rounding (not bit for bit). */
 DBIE_API int dbie_eval_field(dbie_ctx* ctx, const double* lambda, int32_t L, double* B, double* dB,
                              double* fg, double* tan, void* stream);
 

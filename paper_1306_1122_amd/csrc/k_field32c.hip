@@ -58,7 +58,8 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float ri2 = ri * ri;
-    const float ri3 = ri2 * ri;
+    // with tangents B0 / r is needed anyway, so B0 / r^3 is formed from it (one multiply less)
+    const float ri3 = TAN ? 0.0f : ri2 * ri;
     const float dxr = dx * ri2;
     const float dyr = dy * ri2;
     const float b0[3] = {bx, by, bz};
@@ -71,12 +72,13 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
         const float t = lt[p] * r;
         const float n = fmaf(t, sn, cs);
         const float hh = fmaf(t, t * cs, -3.0f * n);
-        const float b3 = ri3 * b0[p];
+        const float rb = TAN ? ri * b0[p] : 0.0f;
+        const float b3 = TAN ? rb * ri2 : ri3 * b0[p];
         const float hb = hh * b3;
         if (TAN) {
             const float nb = n * b3;
             acc[4 * p + 0] += nb;
-            acc[12 + 3 * p + 0] = fmaf(cs, ri * b0[p], acc[12 + 3 * p + 0]);
+            acc[12 + 3 * p + 0] = fmaf(cs, rb, acc[12 + 3 * p + 0]);
             acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
             acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
         } else {
