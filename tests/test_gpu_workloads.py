@@ -206,3 +206,26 @@ def test_largest_grid_workload_sampled(precision, tol):
     assert rel(out["dB"][:, idx].cpu(), dB) <= tol
     assert torch.isfinite(out["B"]).all() and torch.isfinite(out["fg"]).all()
     ctx.close()
+
+
+@pytest.mark.parametrize("which", ["bipoles_128", "active_region_512x256"])
+def test_fp32c_matches_fp64_on_every_point(which):
+    """Every point of the full workload: the FP32C result against the library's FP64 result (itself
+    pinned to the oracle on samples), relative L2 over all points and per magnetogram row."""
+    w = config2() if which == "bipoles_128" else config5()
+    bd = w.boundaries[0]
+    res = {}
+    for prec in ("fp64", "fp32c"):
+        ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision=prec)
+        out = D.dbie_eval_field(ctx, T(w.lam), want_tan=True)
+        torch.cuda.synchronize()
+        res[prec] = {k: out[k].cpu().numpy() for k in ("B", "dB", "tan")}
+        ctx.close()
+    for k in ("B", "dB", "tan"):
+        e = rel(res["fp32c"][k], res["fp64"][k])
+        # the worst single point, relative to that point's own magnitude
+        a, b = res["fp32c"][k], res["fp64"][k]
+        per = np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+        print(which, k, "rel L2 %.2e, worst point %.2e, 99.9%% of points below %.2e" % (
+            e, per.max(), np.quantile(per, 0.999)), flush=True)
+        assert e <= 1e-5, (k, e)
