@@ -24,6 +24,7 @@
 // summed in FP64 by the finalize pass. Blocks that cannot contain such a pair for any point of the
 // wavefront take the unmasked loop; the test is uniform over the wavefront.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 
 #include "dbie_internal.h"
@@ -388,23 +389,28 @@ bool field32c_shape_supported(F32Shape s) {
 
 __global__ void k_clear_work(int32_t* __restrict__ w) { *w = 0; }
 
+constexpr int kMaxDevices = 64;
+
 template <int P, int W, bool T, bool SC, bool GR>
 static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
                              const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L, int32_t S,
                              const int32_t* idx, int32_t* work, double* acc, hipStream_t st) {
     unsigned gx = (unsigned)n_tiles;
     if (work) {
-        // resident workgroups of this kernel on the device
-        static int per_cu = 0, cus = 0;
-        if (per_cu == 0) {
-            int dev = 0, nb = 0;
-            (void)hipGetDevice(&dev);
+        // resident workgroups of this kernel on the current device (queried once per device; a
+        // concurrent first query stores the same value)
+        static std::atomic<int> resident[kMaxDevices];
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int r = (dev >= 0 && dev < kMaxDevices) ? resident[dev].load(std::memory_order_relaxed) : 0;
+        if (r == 0) {
+            int cus = 0, nb = 0;
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field32c<P, W, T, SC, GR>, 64 * W, 0);
-            per_cu = nb > 0 ? nb : 1;
-            if (cus <= 0) cus = 1;
+            r = std::max(nb, 1) * std::max(cus, 1);
+            if (dev >= 0 && dev < kMaxDevices) resident[dev].store(r, std::memory_order_relaxed);
         }
-        gx = (unsigned)std::min<int64_t>(n_tiles, (int64_t)per_cu * cus);
+        gx = (unsigned)std::min<int64_t>(n_tiles, (int64_t)r);
         hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(1), 0, st, work);
     }
     hipLaunchKernelGGL((k_field32c<P, W, T, SC, GR>), dim3(gx, (unsigned)L, (unsigned)S), dim3(64 * W), 0, st,
