@@ -207,6 +207,13 @@ DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixel
  * runs in the persistent form. */
 DBIE_API int dbie_query_tan(const dbie_ctx* ctx, int32_t* ppl, int32_t* waves, int32_t* tile_pixels);
 DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t* with_tangents);
+/* Residual statistics of a reconstruction (the paper quotes the means of f_i and g_i, Eqs. 8-9, over
+ * its volume, Section 4): fg is device double [2][N] as written by dbie_eval_field or
+ * dbie_solve_lambda; out is host double[4] = {<f>, <g>, number of points with finite f and g,
+ * number of points with max(f, g) <= eps (Eq. 12)}, the means over the finite points (NaN if none).
+ * Wavefront shuffles and a fixed-order block sum: deterministic. Synchronises `stream`. */
+DBIE_API int dbie_residual_stats(dbie_ctx* ctx, const double* fg, double eps, double* out, void* stream);
+
 /* Pixel slices per FP32C launch (dbie_options.pixel_split, or the automatic choice); 1 for FP64. */
 DBIE_API int dbie_query_split(const dbie_ctx* ctx, int32_t* slices);
 

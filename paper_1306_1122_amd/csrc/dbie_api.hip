@@ -329,8 +329,8 @@ int32_t ctx_split(const dbie_ctx* c) { return c->split; }
 
 // Regions of a caller-owned workspace, each a multiple of 256 bytes: the sums of one trial (all
 // pixel slices), the solver block (any method, up to 1e6 trials, any tile shape), and scratch slots
-// 0 (dbie_grad's evaluation, dbie_trace_lines), 1 (dbie_grad's gB0 part), 2 (tuning, in dbie_init
-// only: none) and 3 (the expanded lambda of one single-lambda trial).
+// 0 (dbie_grad's evaluation, dbie_trace_lines), 1 (dbie_grad's gB0 part), 2 (dbie_residual_stats;
+// tuning uses it in dbie_init only) and 3 (the expanded lambda of one single-lambda trial).
 void ws_sizes(const dbie_ctx* c, size_t sz[kWsRegions]) {
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t n = (size_t)std::max<int64_t>(c->N, 1);
@@ -338,7 +338,7 @@ void ws_sizes(const dbie_ctx* c, size_t sz[kWsRegions]) {
     sz[kWsSolver] = up(solver_workspace_bytes(c));
     sz[kWsSlot0 + 0] = up(std::max(24 * n * sizeof(double), 27 * n * sizeof(double) + (2 * n + 64) * sizeof(int32_t)));
     sz[kWsSlot0 + 1] = up(grad_workspace_bytes(c));
-    sz[kWsSlot0 + 2] = 0;
+    sz[kWsSlot0 + 2] = up((4 + 4 * 256) * sizeof(double));   // residual statistics (tuning uses it at init)
     sz[kWsSlot0 + 3] = up(3 * n * sizeof(double));
 }
 hipError_t ctx_prep_points(dbie_ctx* c, int32_t* flag, hipStream_t s) {
@@ -819,6 +819,27 @@ int dbie_set_workspace(dbie_ctx* c, void* dev, int64_t bytes) {
         c->ws_size[r] = dev ? sz[r] : 0;
         off += sz[r];
     }
+    return DBIE_OK;
+}
+
+int dbie_residual_stats(dbie_ctx* c, const double* fg, double eps, double* out, void* stream) {
+    if (!c) return DBIE_E_INVAL;
+    if (!out) return fail(c, DBIE_E_INVAL, "out is NULL");
+    if (!(eps >= 0.0)) return fail(c, DBIE_E_INVAL, "eps must be >= 0");
+    if (c->N > 0 && !fg) return fail(c, DBIE_E_INVAL, "fg is NULL");
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c->N > 0) {
+        hipStream_t s = (hipStream_t)stream;
+        double* w = (double*)ctx_scratch(c, 2, (4 + 4 * 256) * sizeof(double));
+        if (!w) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the statistics workspace");
+        DBIE_HIP(c, launch_fg_stats(c->N, fg, eps, w, s));
+        DBIE_HIP(c, hipMemcpyAsync(sums, w, sizeof(sums), hipMemcpyDeviceToHost, s));
+        DBIE_HIP(c, hipStreamSynchronize(s));
+    }
+    out[0] = sums[2] > 0 ? sums[0] / sums[2] : std::nan("");
+    out[1] = sums[2] > 0 ? sums[1] / sums[2] : std::nan("");
+    out[2] = sums[2];
+    out[3] = sums[3];
     return DBIE_OK;
 }
 

@@ -240,4 +240,8 @@ hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const doub
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s);
 
+// Sums of f, g, finite points and points with max(f, g) <= eps into scratch[0..3] (scratch holds
+// 4 + 4 * 256 doubles).
+hipError_t launch_fg_stats(int64_t N, const double* fg, double eps, double* scratch, hipStream_t s);
+
 }  // namespace dbie

@@ -160,3 +160,58 @@ hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const doub
 }
 
 }  // namespace dbie
+
+// ---- residual statistics (dbie_residual_stats) ----------------------------------------------
+// Sums over the points of f, g, the count of finite (f, g) and the count with max(f, g) <= eps:
+// per thread over a grid stride, then across the wavefront with shuffles, then across the block in
+// LDS; one partial per block, added in block order by a single block (fixed order: deterministic).
+namespace dbie {
+
+constexpr int kStatBlocks = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_fg_partial(int64_t N, const double* __restrict__ fg, double eps,
+                                                    double* __restrict__ part) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const double f = fg[i], g = fg[N + i];
+        if (isfinite(f) && isfinite(g)) {
+            s[0] += f;
+            s[1] += g;
+            s[2] += 1.0;
+            if (fmax(f, g) <= eps) s[3] += 1.0;
+        }
+    }
+    __shared__ double red[4][4];   // [wave][quantity]
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int q = 0; q < 4; ++q) {
+        const double v = wave_sum(s[q]);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) v += red[w][threadIdx.x];
+        part[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_fg_final(int32_t nblk, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x >= 4) return;
+    double v = 0.0;
+    for (int32_t b = 0; b < nblk; ++b) v += part[b * 4 + threadIdx.x];
+    out[threadIdx.x] = v;
+}
+
+hipError_t launch_fg_stats(int64_t N, const double* fg, double eps, double* scratch, hipStream_t s) {
+    const int32_t nblk = (int32_t)std::min<int64_t>(kStatBlocks, std::max<int64_t>(1, (N + 255) / 256));
+    hipLaunchKernelGGL(k_fg_partial, dim3(nblk), dim3(256), 0, s, N, fg, eps, scratch + 4);
+    hipLaunchKernelGGL(k_fg_final, dim3(1), dim3(64), 0, s, nblk, scratch + 4, scratch);
+    return hipGetLastError();
+}
+
+}  // namespace dbie

@@ -327,6 +327,16 @@ def dbie_trace_lines(ctx: Context, lam_grid: torch.Tensor, origin, spacing, box,
     return dict(xyz=xyz, count=count)
 
 
+def dbie_residual_stats(ctx: Context, fg: torch.Tensor, eps: float = 1e-4, stream=None) -> Dict[str, float]:
+    """Means of f and g over the points with finite residuals, their number, and the number with
+    max(f, g) <= eps, reduced on the device."""
+    _need(fg, "fg", (2, ctx.n_points))
+    out = (ctypes.c_double * 4)()
+    _check(_lib().dbie_residual_stats(ctx.handle, fg.data_ptr() if ctx.n_points else None, float(eps), out,
+                                      _stream(stream)), ctx, "dbie_residual_stats")
+    return dict(mean_f=out[0], mean_g=out[1], finite=int(out[2]), converged=int(out[3]))
+
+
 def dbie_query_split(ctx: Context) -> int:
     v = ctypes.c_int32()
     _check(_lib().dbie_query_split(ctx.handle, ctypes.byref(v)), ctx, "dbie_query_split")

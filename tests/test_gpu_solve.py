@@ -194,3 +194,25 @@ def test_lowlou_comparison_metrics_are_reported():
         print(name, {k: round(v, 3) for k, v in m.items()}, flush=True)
     for m in rows.values():
         assert m["C_vec"] > 0.5 and m["C_cs"] > 0.0
+
+
+def test_residual_statistics_on_the_device():
+    """dbie_residual_stats against NumPy on the same (f, g): means over finite points, counts; a NaN
+    lambda point is left out; repeated calls agree bitwise."""
+    w, bd, ctx = lowlou_ctx("fp32c")
+    n = w.n_points
+    lam = torch.zeros(3, n, dtype=torch.float64, device="cuda:0")
+    r = D.dbie_solve_lambda(ctx, lam, method="lm", max_trials=10, eps=1e-3)
+    fg = r["fg"]
+    st = D.dbie_residual_stats(ctx, fg, eps=1e-3)
+    a = fg.cpu().numpy()
+    ok = np.isfinite(a[0]) & np.isfinite(a[1])
+    assert st["finite"] == int(ok.sum())
+    assert st["converged"] == int(np.sum(np.maximum(a[0], a[1])[ok] <= 1e-3))
+    assert abs(st["mean_f"] - a[0][ok].mean()) <= 1e-13 * max(1.0, abs(a[0][ok].mean()))
+    assert abs(st["mean_g"] - a[1][ok].mean()) <= 1e-13 * max(1.0, abs(a[1][ok].mean()))
+    assert st == D.dbie_residual_stats(ctx, fg, eps=1e-3)
+    bad = T(np.where(np.arange(n) == 5, np.nan, 0.2) * np.ones((3, 1)))
+    e = D.dbie_eval_field(ctx, bad)
+    s2 = D.dbie_residual_stats(ctx, e["fg"], eps=1e-4)
+    assert s2["finite"] == n - 1
