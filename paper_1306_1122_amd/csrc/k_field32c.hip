@@ -156,8 +156,9 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
         const float bys[kCols] = {Y0.x, Y0.y, Y0.z, Y0.w, Y1.x, Y1.y, Y1.z, Y1.w};
         const float bzs[kCols] = {Z0.x, Z0.y, Z0.z, Z0.w, Z1.x, Z1.y, Z1.z, Z1.w};
         const float brow = b0 + (float)r;
-        float4 rp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (GRID) rp = sR[r];
+        // GRID: the row's split position (the element index is read only by the masked loop)
+        float2 rp = make_float2(0.0f, 0.0f);
+        if (GRID) rp = *reinterpret_cast<const float2*>(&sR[r]);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             const float dy = GRID ? (rp.x + S.yn[j]) + (rp.y - S.yf[j]) : (brow + S.yn[j]) - S.yf[j];
@@ -166,7 +167,7 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
             for (int c = 0; c < kCols; ++c) {
                 float bx = bxs[c], by = bys[c], bz = bzs[c];
                 if (SLOW && GRID) {
-                    const float da = sC[c].z - S.fa[j], db = rp.z - S.fb[j];
+                    const float da = sC[c].z - S.fa[j], db = sR[r].z - S.fb[j];
                     const bool in = fabsf(da) <= (float)kNearWinQ && fabsf(db) <= (float)kNearWinQ;
                     const int bit =
                         in ? (int)(da + (float)kNearWinQ) + kNearSideQ * (int)(db + (float)kNearWinQ) : 0;
@@ -330,7 +331,7 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 // workgroups pulls tile indices from the device counter `work` (cleared by a kernel before the
 // launch) until the schedule is exhausted; every workgroup reaches the exit test after each tile.
 template <int PPL, int WAVES, bool TAN, bool SCALAR, bool GRID>
-__global__ __launch_bounds__(64 * WAVES) void k_field32c(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ? 4 : 1) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
                                                          const BoundaryDev* __restrict__ bnd,
                                                          const float* __restrict__ pixf,
