@@ -579,8 +579,9 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         if (!rc) rc = set_tiles32(c, c->shape_tan, true);
         if (rc) return bail(rc);
     }
-    int32_t* bad = nullptr;
-    DBIE_INIT_HIP(dalloc(&bad, 1));
+    // the validation flag lives in a scratch slot, so that every exit path frees it with the context
+    int32_t* bad = (int32_t*)ctx_scratch(c, 2, sizeof(int32_t));
+    if (!bad) return bail(fail(c, DBIE_E_WORKSPACE, "cannot allocate the validation flag"));
     DBIE_INIT_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
     const double r = (o.precision == DBIE_FP32C) ? o.nearfield_radius_h : 0.0;
     DBIE_INIT_HIP(launch_prep(c->tiles64, c->n_tiles64, c->bnd_d, c->gB, c->xyz, N, c->geo, r * r,
@@ -588,7 +589,6 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     int32_t bad_h = 0;
     DBIE_INIT_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DBIE_INIT_HIP(hipStreamSynchronize(s));
-    (void)hipFree(bad);
     if (bad_h) return bail(fail(c, DBIE_E_INVAL, "a point has z <= 0, a non-finite coordinate, or lies "
                                                  "more than 4e6 pixels away"));
     if (o.precision == DBIE_FP32C && r > 0.0 && N > 0) {
