@@ -134,3 +134,11 @@ def test_calls_on_null_context_are_rejected(lib):
     assert lib.dbie_eval_field(None, None, 1, None, None, None, None, None) == L.DBIE_E_INVAL
     assert lib.dbie_timing(None, 1) == L.DBIE_E_INVAL
     lib.dbie_destroy(None)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """With no built library the binding raises instead of computing anything some other way."""
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIBPATH", str(tmp_path / "libdbie.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        L.load()
