@@ -123,11 +123,11 @@ def adjoint_and_scalar(D, ctx, lam, pairs):
                 scalar_lambda_field_grad_ms=ms_sc, scalar_lambda_pairs_per_s=pairs / (ms_sc * 1e-3))
 
 
-def time_to_solution(D, dev, n_sample=65536):
+def time_to_solution(D, dev, n_sample=65536, eps=1e-4):
     """Plain form (FP64 Nelder-Mead, 200 trials) vs fast form (FP32C Levenberg-Marquardt, 20 trials,
     FP64 acceptance) on a z-stratified sample of the 256x256x128 bipole grid, from lambda = 0; the
     FP32C Nelder-Mead (200 trials, FP64 acceptance) separates the precision from the method.
-    q* = the solved fraction (max(f, g) <= 1e-4 in FP64) the plain form reaches within its budget;
+    q* = the solved fraction (max(f, g) <= eps in FP64) the plain form reaches within its budget;
     TTS(form) = solve time until that form's solved fraction reaches q* (round-end HIP events)."""
     import torch
     from workloads import config3, z_stratified_subsample
@@ -137,7 +137,7 @@ def time_to_solution(D, dev, n_sample=65536):
     xyz = torch.tensor(np.ascontiguousarray(w.xyz[:, idx]), dtype=torch.float64, device=dev)
     B0 = torch.tensor(bd.B0, dtype=torch.float64, device=dev)
     n = xyz.shape[1]
-    res = {"workload": f"{n} z-stratified points of {w.name}", "eps": 1e-4}
+    res = {"workload": f"{n} z-stratified points of {w.name}", "eps": eps}
     forms = (("plain_fp64_nelder_mead", "fp64", "nm", 200),
              ("fp32c_nelder_mead", "fp32c", "nm", 200),
              ("fast_fp32c_levenberg_marquardt", "fp32c", "lm", 20))
@@ -147,7 +147,7 @@ def time_to_solution(D, dev, n_sample=65536):
         D.dbie_solve_trace(ctx, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = D.dbie_solve_lambda(ctx, lam, method=meth, max_trials=budget, eps=1e-4, fp64_accept=True,
+        r = D.dbie_solve_lambda(ctx, lam, method=meth, max_trials=budget, eps=eps, fp64_accept=True,
                                 want_B=False)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -370,6 +370,7 @@ def main():
         for name, fn in (("per_trial_rates", lambda: per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s)),
                          ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs)),
                          ("time_to_solution", lambda: time_to_solution(D, dev)),
+                         ("time_to_solution_eps_0.1", lambda: time_to_solution(D, dev, eps=0.1)),
                          ("batched_64_magnetograms", lambda: batched(D, dev)),
                          ("active_region_512x256_arcs", lambda: active_region(D, dev)),
                          ("quad9_elements_127x127", lambda: quad9_elements(D, dev)),
