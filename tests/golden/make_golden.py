@@ -5,7 +5,9 @@ the kernel sum or the lambda solve, so the stored values are the oracle's; they 
 against unintended changes. Any change to them must name, in its commit message, the passage of the
 paper (or the reading of it) that justifies the change.
 
-Run from the repository root:  python tests/golden/make_golden.py
+Also writes oracle_elements_trace_case.json (9-node elements, a short field line).
+
+Run from the repository root:  python tests/golden/make_golden.py  (or `... elements` for the second file only)
 """
 import json
 import os
@@ -42,5 +44,33 @@ def main():
         json.dump(out, fh, indent=0)
 
 
+def elements_and_trace():
+    """A 7 x 5 magnetogram with 9-node elements (G = 3) and a short field line through the nodal
+    field: written to oracle_elements_trace_case.json."""
+    rng = np.random.default_rng(20130606)
+    nx, ny, h, x0, y0 = 7, 5, 0.5, -1.5, -1.0
+    B0 = rng.normal(size=(3, ny, nx))
+    xyz = np.stack([rng.uniform(-1.6, 1.8, 6), rng.uniform(-1.1, 1.2, 6), rng.uniform(0.1, 2.0, 6)])
+    lam = rng.uniform(-1.5, 1.5, size=(3, 6))
+    B, dB, tan = oracle.field_quad9(B0, x0, y0, h, xyz, lam, G=3, tangents=True)
+    lam_grid = rng.uniform(0.0, 1.0, size=(3, 2, 2, 2))
+    origin, spacing = (-1.5, -1.0, 0.1), (3.0, 2.0, 2.0)
+    d = oracle.dbie_direction(B0, x0, y0, h, lam_grid, origin, spacing)
+    seeds = np.array([[0.1, -0.4], [0.2, 0.3], [0.5, 0.8]])
+    pts, cnt = oracle.rk4_trace(d, seeds, 0.05, 12, (-1.5, -1.0, 0.1), (1.5, 1.0, 2.0))
+    out = dict(nx=nx, ny=ny, h=h, x0=x0, y0=y0, G=3, B0=B0.tolist(), xyz=xyz.tolist(), lam=lam.tolist(),
+               B=B.tolist(), dB=dB.tolist(), tan=tan.tolist(), lam_grid=lam_grid.tolist(),
+               origin=list(origin), spacing=list(spacing), seeds=seeds.tolist(), ds=0.05, n_steps=12,
+               box=[-1.5, -1.0, 0.1, 1.5, 1.0, 2.0], trace=np.nan_to_num(pts, nan=-999.0).tolist(),
+               count=cnt.tolist(), source="oracle/ via tests/golden/make_golden.py")
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_elements_trace_case.json"),
+              "w") as fh:
+        json.dump(out, fh, indent=0)
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "elements":
+        elements_and_trace()
+    else:
+        main()
+        elements_and_trace()
