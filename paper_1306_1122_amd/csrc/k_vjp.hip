@@ -122,7 +122,7 @@ constexpr int kVjp32F = 26;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^
 
 // GRID (9-node elements): output j sits at (a + af, b + bf) (integer part + fraction) and belongs to
 // element (ea, eb); the near mask is per element of the 3x3 window.
-template <int PPX, bool SLOW, bool GRID>
+template <int PPX, bool SLOW, bool GRID, bool FRACT>
 __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e, const float a[PPX],
                                             const float b[PPX], const float af[PPX], const float bf[PPX],
                                             const float ea[PPX], const float eb[PPX], float (&acc)[PPX][3]) {
@@ -151,9 +151,10 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
         const float ri5 = ri3 * ri2;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            // phase in revolutions, reduced; the product's rounding recovered by an FMA
+            // phase in revolutions; FRACT (a chunk beyond the sin/cos range): reduced, with the
+            // product's rounding recovered by an FMA
             const float th = sp[8 + p][e] * r;
-            const float tr = __builtin_amdgcn_fractf(th) + fmaf(sp[8 + p][e], r, -th);
+            const float tr = FRACT ? __builtin_amdgcn_fractf(th) + fmaf(sp[8 + p][e], r, -th) : th;
             const float sn = __builtin_amdgcn_sinf(tr);
             const float cs = __builtin_amdgcn_cosf(tr);
             const float t = sp[5 + p][e] * r;
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
                                                 const double* __restrict__ coef, double* __restrict__ gW,
                                                 int64_t slice_stride) {
     __shared__ float sp[kVjp32F][kVjp32Pts];
-    __shared__ int any_near;
+    __shared__ int any_near, any_far;
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
     const int32_t ngrid = bd.gcols * bd.grows;
@@ -214,7 +215,10 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
     for (int64_t i0 = p0; i0 < p1; i0 += kVjp32Pts) {
         const int n = (int)min<int64_t>(kVjp32Pts, p1 - i0);
         __syncthreads();
-        if (threadIdx.x == 0) any_near = 0;
+        if (threadIdx.x == 0) {
+            any_near = 0;
+            any_far = 0;
+        }
         __syncthreads();
         for (int e = threadIdx.x; e < n; e += blockDim.x) {
             const int64_t i = perm ? (int64_t)perm[i0 + e] : i0 + e;
@@ -238,15 +242,31 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
             const uint32_t m = geo.near_mask[i];
             sp[25][e] = __uint_as_float(m);
             if (m) any_near = 1;
+            {
+                // the largest |Lambda| r / 2pi of this point over the magnetogram's grid (positions in
+                // [0, nx-1] x [0, ny-1]); beyond the hardware sin/cos range the chunk reduces first
+                const float uf = sp[0][e] + sp[1][e], vf = sp[2][e] + sp[3][e];
+                const float dxm = fmaxf(fabsf(uf), fabsf((float)(bd.nx - 1) - uf)) + 1.0f;
+                const float dym = fmaxf(fabsf(vf), fabsf((float)(bd.ny - 1) - vf)) + 1.0f;
+                const float rmax = sqrtf(dxm * dxm + dym * dym + sp[4][e]);
+                const float lmax = fmaxf(fabsf(sp[8][e]), fmaxf(fabsf(sp[9][e]), fabsf(sp[10][e])));
+                if (!(lmax * rmax < 255.0f)) any_far = 1;   // NaN lambda included
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < PPX; ++j)
             for (int p = 0; p < 3; ++p) part[j][p] = 0.0f;
-        if (any_near) {
-            for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID>(sp, e, a, b, af, bf, ea, eb, part);
+        if (any_far) {
+            if (any_near)
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID, true>(sp, e, a, b, af, bf, ea, eb, part);
+            else
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID, true>(sp, e, a, b, af, bf, ea, eb, part);
         } else {
-            for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID>(sp, e, a, b, af, bf, ea, eb, part);
+            if (any_near)
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID, false>(sp, e, a, b, af, bf, ea, eb, part);
+            else
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID, false>(sp, e, a, b, af, bf, ea, eb, part);
         }
 #pragma unroll
         for (int j = 0; j < PPX; ++j)
