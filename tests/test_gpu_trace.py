@@ -71,3 +71,36 @@ def test_seed_outside_the_box_and_zero_steps(case):
         D.dbie_trace_lines(ctx, T(lam_grid), origin, spacing, (-1, -1, 0.0, 1, 1, 1), 0.05, 3)
     with pytest.raises(D.DbieError, match="sense"):
         D.dbie_trace_lines(ctx, T(lam_grid), origin, spacing, box, 0.05, 3, sense=0.5)
+
+
+def test_lines_through_the_element_field_and_several_magnetograms():
+    """Tracing in a context with 9-node elements (Eq. 15, G = 3) and two magnetograms: each line
+    follows the oracle's element field of its own magnetogram."""
+    rng = np.random.default_rng(78)
+    mags = [(rng.normal(size=(3, 15, 17)), -1.0, -1.0, 0.125), (rng.normal(size=(3, 11, 13)), 0.5, 0.0, 0.1)]
+    seeds, seg = [], [0]
+    for B0, x0, y0, h in mags:
+        ny, nx = B0.shape[1:]
+        s = np.stack([rng.uniform(x0 + 0.3, x0 + (nx - 1) * h - 0.3, 4), rng.uniform(y0 + 0.3, y0 + (ny - 1) * h - 0.3, 4),
+                      rng.uniform(0.2, 0.6, 4)])
+        seeds.append(s)
+        seg.append(seg[-1] + 4)
+    seeds = np.concatenate(seeds, axis=1)
+    lam_grid = np.full((3, 1, 1, 1), 0.4)
+    box = (-2.0, -2.0, 0.05, 3.0, 3.0, 2.0)
+    ctx = D.dbie_init([dict(B0=T(B0), x0=x0, y0=y0, h=h) for B0, x0, y0, h in mags], T(seeds), seg=seg,
+                      precision="fp64", quad_points=3)
+    out = D.dbie_trace_lines(ctx, T(lam_grid), (0, 0, 0), (1, 1, 1), box, 0.03, 15)
+    torch.cuda.synchronize()
+    xyz, cnt = out["xyz"].cpu().numpy(), out["count"].cpu().numpy()
+    for b, (B0, x0, y0, h) in enumerate(mags):
+        def direction(p, B0=B0, x0=x0, y0=y0, h=h):
+            lam = np.full(p.shape, 0.4)
+            B, _ = oracle.field_quad9(B0, x0, y0, h, p, lam, G=3)
+            return B / np.sqrt(np.sum(B * B, axis=0))
+        s0, s1 = seg[b], seg[b + 1]
+        ref, rc = oracle.rk4_trace(direction, seeds[:, s0:s1], 0.03, 15, box[:3], box[3:])
+        assert np.array_equal(cnt[s0:s1], rc), (b, cnt[s0:s1], rc)
+        for j in range(s1 - s0):
+            k = rc[j]
+            assert np.max(np.abs(xyz[:k, :, s0 + j] - ref[:k, :, j])) <= 1e-9, (b, j)
