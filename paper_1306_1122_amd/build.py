@@ -2,10 +2,12 @@
 
     python -m paper_1306_1122_amd.build
 """
+import concurrent.futures
 import glob
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -23,10 +25,7 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build_library(verbose: bool = False, out: str = LIB) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = out + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] + sources() + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -35,7 +34,22 @@ def build_library(verbose: bool = False, out: str = LIB) -> str:
         raise RuntimeError("hipcc failed:\n" + msg)
     if verbose and msg.strip():
         print(msg)
-    os.replace(tmp, out)
+
+
+def build_library(verbose: bool = False, out: str = LIB) -> str:
+    """Compile every source to an object (in parallel, at most 8 at a time), then link."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(ROOT, "include")]
+    cflags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="dbie_build_") as td:
+        objs = [os.path.join(td, os.path.basename(src) + ".o") for src in sources()]
+        jobs = [[hipcc] + cflags + inc + ["-c", src, "-o", obj] for src, obj in zip(sources(), objs)]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+            for f in [ex.submit(_run, j, verbose) for j in jobs]:
+                f.result()
+        tmp = out + ".tmp"
+        _run([hipcc] + HIPCC_FLAGS + objs + ["-o", tmp], verbose)
+        os.replace(tmp, out)
     return out
 
 
