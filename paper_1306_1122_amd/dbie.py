@@ -195,6 +195,9 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
                       eps: float = 1e-4, init_step: float = 0.0, lambda_cap: float = 0.0,
                       fp64_accept: bool = True, B=None, fg=None, status=None, trials=None,
                       want_B: bool = True, want_fg: bool = True, use_graph: bool = True, stream=None):
+    """Per-point lambda search (method "nm": Nelder-Mead, "lm": Levenberg-Marquardt in mu = lambda^2)
+    from the start values in lambda_inout [3, N], which receives |lambda*|. Returns dict(lam, B, fg,
+    status, trials): status per point (_lib.DBIE_ST_*), trials = evaluations used."""
     N = ctx.n_points
     _need(lambda_inout, "lambda_inout", (3, N))
     dev = lambda_inout.device
@@ -221,6 +224,9 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
 def dbie_grad(ctx: Context, lam: torch.Tensor, gB=None, gdB=None, want_glambda: bool = True,
               want_gB0: bool = True, want_resid_jac: bool = False, glambda=None, gB0=None,
               resid_jac=None, stream=None):
+    """Adjoint of the evaluation at lam [3, N] for the upstream gradients gB [3, N] and gdB [9, N]:
+    glambda [3, N], gB0 (concatenated [3, ny, nx] per boundary; see split_gB0) and, on request, the
+    residual Jacobian d(u, s)/d mu [4, 3, N]."""
     N = ctx.n_points
     _need(lam, "lambda", (3, N))
     dev = lam.device
