@@ -27,9 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# algorithmic FP32 flops per kernel pair (FMA = 2, add/mul = 1, sin/cos/rsqrt = 1), see the design doc
-FLOPS_FIELD_GRAD = 69
-FLOPS_FIELD_GRAD_TAN = 90
+# algorithmic FP32 flops per kernel pair (point, pixel, trial; all three components): the formulas
+# of the field, its frozen-lambda gradient and the mu-tangents counted with FMA = 2, add/mul = 1 and
+# each sin, cos, rsqrt = 1
+FLOPS_FIELD_GRAD = 68
+FLOPS_FIELD_GRAD_TAN = 89
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 TRIALS_PER_STEP = 3
 

@@ -23,7 +23,7 @@ Everything is float64 NumPy, written to be checked against the paper by eye:
 Sums over pixels use numpy's pairwise summation along a contiguous axis (error ~log2(N_pix) ulp
 of the sum of absolute terms).
 
-Readings where the paper is silent (all stated in the design doc of the repository):
+Readings where the paper is silent:
   * nodes are pixel centres with weight h^2; the field outside the magnetogram is zero (Eq. 3 text);
   * one lambda per field component and point;
   * derivatives are the exact delta -> 0 limit at frozen lambda;

@@ -86,7 +86,9 @@ struct dbie_ctx {
     int64_t n_tiles32 = 0;
     Tile* tiles32t = nullptr;    // static schedule of the FP32C pass with mu-tangents
     int64_t n_tiles32t = 0;
-    F32Shape shape{1, 8, kRows * kCols, 0};
+    // untuned shapes: four-wave workgroups (at three resident waves per SIMD, the register count
+    // of both nodal FP32C forms, eight-wave workgroups leave a third of the slots empty)
+    F32Shape shape{1, 4, kRows * kCols, 0};
     F32Shape shape_tan{1, 4, kRows * kCols, 0};
     int32_t* work = nullptr;    // tile counter of the persistent FP32C form
     int32_t split = 1;          // FP32C pixel slices per launch (grid z); acc holds split x L slices

@@ -14,10 +14,12 @@
 // are kept in registers; for each row dy = (b0 + r - floor(v)) - frac(v) and q = dy^2 + w^2; then
 //   rho^2 = dx_c^2 + q, rho^-1 = rsq(rho^2), and per component t = Lambda rho, sin/cos in
 //   revolutions (range-reduced by fract only when a wavefront's |Lambda| rho / 2pi can exceed the
-//   hardware's accurate range of 256 revolutions), N = t sin t + cos t, H = t (t cos t) - 3 N,
-//   A0 += N rho^-3 B0,  A1 += H rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += H rho^-3 B0 rho^-2
-//   (and with tangents T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy).
-// SCALAR: the three components share one lambda, so t, sin, cos, N and H are computed once per pair.
+//   hardware's accurate range of 256 revolutions), N = t sin t + cos t and, in place of
+//   H = t^2 cos t - 3 N, the two-operation form Q = -H / 3 = N - (Lambda^2 / 3) rho^2 cos t;
+//   A0 += N rho^-3 B0,  A1 += Q rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += Q rho^-3 B0 rho^-2
+//   (the totals of A1..A3 are multiplied by -3 when written), and with tangents
+//   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy.
+// SCALAR: the three components share one lambda, so t, sin, cos, N and Q are computed once per pair.
 // Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
 // FP64 totals, so the error does not grow with the magnetogram size.
 // Near field: pairs whose (FP64-classified) distance is below the near radius are skipped here and
@@ -34,18 +36,20 @@ namespace dbie {
 template <int PPL, bool TAN>
 struct PointState {
     float xn[PPL], xf[PPL], yn[PPL], yf[PPL], w2[PPL];
-    float lt[PPL][3];   // Lambda (radians per pixel)
+    float l3[PPL][3];   // -Lambda^2 / 3 (per pixel^2)
     float lr[PPL][3];   // Lambda / 2pi (revolutions per pixel)
     float fa[PPL], fb[PPL];   // near-window centre as floats
     uint32_t msk[PPL];
 };
 
-// Phase in revolutions, reduced to about [0, 1) when FRACT: the rounding error of the product
-// (half an ulp of |lr r|, up to 1.5e-5 revolutions at the 256-revolution bound) is recovered exactly
-// by an FMA and added back after the reduction, leaving r's own rounding as the phase error.
+constexpr float kTwoPiF = 6.28318530717958647692f;
+
+// Phase in revolutions (hi = lr r as rounded), reduced to about [0, 1) when FRACT: the rounding
+// error of the product (half an ulp of |lr r|, up to 1.5e-5 revolutions at the 256-revolution
+// bound) is recovered exactly by an FMA and added back after the reduction, leaving r's own
+// rounding as the phase error.
 template <bool FRACT>
-__device__ __forceinline__ float phase_rev(float lr, float r) {
-    const float hi = lr * r;
+__device__ __forceinline__ float phase_rev(float lr, float r, float hi) {
     if (!FRACT) return hi;
     const float lo = fmaf(lr, r, -hi);
     return __builtin_amdgcn_fractf(hi) + lo;
@@ -53,7 +57,7 @@ __device__ __forceinline__ float phase_rev(float lr, float r) {
 
 // One pair given dx, dy (pixels), q = dy^2 + w^2 and the field of the pixel.
 template <bool TAN, bool FRACT>
-__device__ __forceinline__ void pair32(float dx, float dy, float q, const float lt[3], const float lr[3],
+__device__ __forceinline__ void pair32(float dx, float dy, float q, const float nl3[3], const float lr[3],
                                        float bx, float by, float bz, float* acc) {
     const float r2 = fmaf(dx, dx, q);
     const float ri = __builtin_amdgcn_rsqf(r2);
@@ -67,12 +71,13 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         // v_sin / v_cos take revolutions and are accurate on [-256, 256]; FRACT reduces first
-        const float tr = phase_rev<FRACT>(lr[p], r);
+        const float hi = lr[p] * r;
+        const float tr = phase_rev<FRACT>(lr[p], r, hi);
         const float sn = __builtin_amdgcn_sinf(tr);
         const float cs = __builtin_amdgcn_cosf(tr);
-        const float t = lt[p] * r;
+        const float t = hi * kTwoPiF;
         const float n = fmaf(t, sn, cs);
-        const float hh = fmaf(t, t * cs, -3.0f * n);
+        const float hh = fmaf(nl3[p] * r2, cs, n);   // -H / 3
         const float rb = TAN ? ri * b0[p] : 0.0f;
         const float b3 = TAN ? rb * ri2 : ri3 * b0[p];
         const float hb = hh * b3;
@@ -93,7 +98,7 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
 
 // One pair when the three components share one lambda: the sin/cos, N and H are computed once.
 template <bool TAN, bool FRACT>
-__device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float lt, float lr, float bx, float by,
+__device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float nl3, float lr, float bx, float by,
                                               float bz, float* acc) {
     const float r2 = fmaf(dx, dx, q);
     const float ri = __builtin_amdgcn_rsqf(r2);
@@ -102,12 +107,13 @@ __device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float
     const float ri3 = ri2 * ri;
     const float dxr = dx * ri2;
     const float dyr = dy * ri2;
-    const float tr = phase_rev<FRACT>(lr, r);
+    const float hi = lr * r;
+    const float tr = phase_rev<FRACT>(lr, r, hi);
     const float sn = __builtin_amdgcn_sinf(tr);
     const float cs = __builtin_amdgcn_cosf(tr);
-    const float t = lt * r;
+    const float t = hi * kTwoPiF;
     const float n = fmaf(t, sn, cs);
-    const float hh = fmaf(t, t * cs, -3.0f * n);
+    const float hh = fmaf(nl3 * r2, cs, n);   // -H / 3
     const float nr3 = n * ri3, hr3 = hh * ri3;
     const float cri = cs * ri;
     const float b0[3] = {bx, by, bz};
@@ -180,9 +186,9 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
                     if (in && ((S.msk[j] >> bit) & 1u)) bx = by = bz = 0.0f;
                 }
                 if (SCALAR)
-                    pair32_scalar<TAN, FRACT>(dxc[j][c], dy, q, S.lt[j][0], S.lr[j][0], bx, by, bz, part[j]);
+                    pair32_scalar<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j][0], S.lr[j][0], bx, by, bz, part[j]);
                 else
-                    pair32<TAN, FRACT>(dxc[j][c], dy, q, S.lt[j], S.lr[j], bx, by, bz, part[j]);
+                    pair32<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j], S.lr[j], bx, by, bz, part[j]);
             }
         }
     }
@@ -226,7 +232,7 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             const double L = lam[(trial * 3 + p) * N + i] * bd.h;
-            S.lt[j][p] = (float)L;
+            S.l3[j][p] = (float)(L * L * (-1.0 / 3.0));
             S.lr[j][p] = (float)(L * 0.15915494309189533577);
         }
         const int32_t wa = geo.win_a[i], wb = geo.win_b[i];
@@ -323,7 +329,11 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
     for (int j = 0; j < PPL; ++j) {
         if (!live[j]) continue;
 #pragma unroll
-        for (int r = 0; r < NA; ++r) acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + pid[j]] = tot[j][r];
+        for (int r = 0; r < NA; ++r) {
+            // rows A1..A3 were summed as -1/3 of their terms
+            const double sc = (r < kAccField && (r & 3) != 0) ? -3.0 : 1.0;
+            acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + pid[j]] = sc * tot[j][r];
+        }
     }
 }
 

@@ -117,8 +117,10 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
 // FP32 partials per point tile cascaded into FP64. Pairs classified near in dbie_init are skipped
 // here (point tiles holding such points take a masked loop) and added in FP64 by k_vjp_near.
 constexpr int kVjp32Pts = 64;
-constexpr int kVjp32F = 26;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^2, Lambda[3], Lambda/2pi[3],
-                              // alpha[3], beta[3], gx[3], gy[3], window a, window b, mask (as bits)
+constexpr int kVjp32F = 26;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^2, -Lambda^2/3 [3],
+                              // Lambda/2pi [3], alpha[3], -3 beta[3], -3 gx[3], -3 gy[3], window a,
+                              // window b, mask (as bits)
+constexpr float kTwoPiF = 6.28318530717958647692f;
 
 // GRID (9-node elements): output j sits at (a + af, b + bf) (integer part + fraction) and belongs to
 // element (ea, eb); the near mask is per element of the 3x3 window.
@@ -157,9 +159,10 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
             const float tr = FRACT ? __builtin_amdgcn_fractf(th) + fmaf(sp[8 + p][e], r, -th) : th;
             const float sn = __builtin_amdgcn_sinf(tr);
             const float cs = __builtin_amdgcn_cosf(tr);
-            const float t = sp[5 + p][e] * r;
+            const float t = th * kTwoPiF;
             const float n = fmaf(t, sn, cs);
-            const float hh = fmaf(t, t * cs, -3.0f * n);
+            // -H / 3 = N - (Lambda^2 / 3) r^2 cos t; the -3 sits in the staged coefficients of lin
+            const float hh = fmaf(sp[5 + p][e] * r2, cs, n);
             const float lin = fmaf(sp[17 + p][e], dx, fmaf(sp[20 + p][e], dy, sp[14 + p][e]));
             acc[j][p] = fmaf(n * ri3, sp[11 + p][e], fmaf(hh * ri5, lin, acc[j][p]));
         }
@@ -230,12 +233,12 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
             sp[4][e] = wf * wf;
             for (int p = 0; p < 3; ++p) {
                 const double L = coef[(0 + p) * N + i];
-                sp[5 + p][e] = (float)L;
+                sp[5 + p][e] = (float)(L * L * (-1.0 / 3.0));
                 sp[8 + p][e] = (float)(L * 0.15915494309189533577);
                 sp[11 + p][e] = (float)coef[(3 + p) * N + i];
-                sp[14 + p][e] = (float)coef[(6 + p) * N + i];
-                sp[17 + p][e] = (float)coef[(9 + p) * N + i];
-                sp[20 + p][e] = (float)coef[(12 + p) * N + i];
+                sp[14 + p][e] = (float)(-3.0 * coef[(6 + p) * N + i]);
+                sp[17 + p][e] = (float)(-3.0 * coef[(9 + p) * N + i]);
+                sp[20 + p][e] = (float)(-3.0 * coef[(12 + p) * N + i]);
             }
             sp[23][e] = (float)geo.win_a[i];
             sp[24][e] = (float)geo.win_b[i];
