@@ -24,6 +24,8 @@
  *     Argument checks run on the host before anything is enqueued. No call aborts or throws.
  *     Per-point outcomes go into per-point status arrays, never into the return code.
  *   - One context must not be used from two host threads at once.
+ *   - A context lives on the HIP device that was current at dbie_init; every call that enqueues
+ *     work needs that device current and returns DBIE_E_INVAL otherwise.
  */
 #ifndef DBIE_H
 #define DBIE_H

@@ -325,6 +325,12 @@ int ctx_precision(const dbie_ctx* c) { return c->opt.precision; }
 double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
 SolverState& ctx_solver(dbie_ctx* c) { return c->solver; }
 int ctx_fail(dbie_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+int ctx_check_device(dbie_ctx* c) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess || d != c->device)
+        return fail(c, DBIE_E_INVAL, "the current HIP device is not the one the context was created on");
+    return DBIE_OK;
+}
 double* ctx_xyz(dbie_ctx* c) { return c->xyz; }
 const void* ctx_acc(const dbie_ctx* c) { return c->acc; }
 int32_t ctx_split(const dbie_ctx* c) { return c->split; }
@@ -621,7 +627,8 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         // the near pairs by grid point (pixel, or Gauss point of a 9-node element) for the adjoint
         // (counting sort by grid point; points ascending)
         const int64_t P = c->ngrid_total;
-        std::vector<int32_t> ptr(P + 1, 0), pixb(P);
+        std::vector<int64_t> ptr(P + 1, 0);
+        std::vector<int32_t> pixb(P);
         for (int32_t b = 0; b < nb; ++b)
             for (int64_t k = 0; k < (int64_t)c->bnd_h[b].gcols * c->bnd_h[b].grows; ++k)
                 pixb[c->bnd_h[b].gpl_off / 3 + k] = b;
@@ -645,15 +652,18 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
             for (uint32_t m = mask[i]; m; m &= m - 1u) for_pair(i, __builtin_ctz(m), [&](int64_t g) { ++ptr[g + 1]; });
         for (int64_t g = 0; g < P; ++g) ptr[g + 1] += ptr[g];
         c->near_pairs = ptr[P];
+        if (c->near_pairs > ((int64_t)1 << 31) - 1)
+            return bail(fail(c, DBIE_E_UNSUPPORTED, "more than 2^31 - 1 near-field pairs"));
         if (c->near_pairs > 0) {
-            std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1), pts(c->near_pairs);
+            std::vector<int32_t> ptr32(ptr.begin(), ptr.end());
+            std::vector<int32_t> fill(ptr32.begin(), ptr32.end() - 1), pts(c->near_pairs);
             for (int64_t i = 0; i < N; ++i)
                 for (uint32_t m = mask[i]; m; m &= m - 1u)
                     for_pair(i, __builtin_ctz(m), [&](int64_t g) { pts[fill[g]++] = (int32_t)i; });
             DBIE_INIT_HIP(dalloc(&c->near_ptr, (size_t)P + 1));
             DBIE_INIT_HIP(dalloc(&c->near_pts, (size_t)c->near_pairs));
             DBIE_INIT_HIP(dalloc(&c->pix_bnd, (size_t)P));
-            DBIE_INIT_HIP(hipMemcpy(c->near_ptr, ptr.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+            DBIE_INIT_HIP(hipMemcpy(c->near_ptr, ptr32.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
             DBIE_INIT_HIP(hipMemcpy(c->near_pts, pts.data(), c->near_pairs * sizeof(int32_t), hipMemcpyHostToDevice));
             DBIE_INIT_HIP(hipMemcpy(c->pix_bnd, pixb.data(), P * sizeof(int32_t), hipMemcpyHostToDevice));
         }
@@ -661,6 +671,13 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     if (o.precision == DBIE_FP32C && o.tune) {
         rc = tune_shapes(c, opt ? opt->tune_cache : nullptr, s);
         if (rc) return bail(rc);
+        // the tuning buffers (27 doubles per point) are not kept: later calls size these slots
+        DBIE_INIT_HIP(hipStreamSynchronize(s));
+        for (int k = 2; k < 4; ++k) {
+            DBIE_INIT_HIP(hipFree(c->scratch[k]));
+            c->scratch[k] = nullptr;
+            c->scratch_bytes[k] = 0;
+        }
     }
     *out = c;
     return DBIE_OK;
@@ -674,6 +691,7 @@ int dbie_eval_field(dbie_ctx* c, const double* lambda, int32_t L, double* B, dou
     if (c->N > 0 && (!lambda || !B)) return fail(c, DBIE_E_INVAL, "lambda and B are required");
     if ((int64_t)L * c->N > ((int64_t)1 << 31) - 1)
         return fail(c, DBIE_E_INVAL, "L * n_points exceeds 2^31 - 1");
+    if (int rc = ctx_check_device(c)) return rc;
     if (c->N == 0) return DBIE_OK;
     return eval_core(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, B, dB, fg, tan,
                      (hipStream_t)stream);
@@ -686,6 +704,7 @@ int dbie_eval_field_scalar(dbie_ctx* c, const double* lambda, int32_t L, double*
     if (c->N > 0 && (!lambda || !B)) return fail(c, DBIE_E_INVAL, "lambda and B are required");
     if ((int64_t)L * c->N > ((int64_t)1 << 31) - 1)
         return fail(c, DBIE_E_INVAL, "L * n_points exceeds 2^31 - 1");
+    if (int rc = ctx_check_device(c)) return rc;
     if (c->N == 0) return DBIE_OK;
     hipStream_t s = (hipStream_t)stream;
     double* lam3 = (double*)ctx_scratch(c, 3, (size_t)L * 3 * c->N * sizeof(double));
@@ -732,6 +751,7 @@ int dbie_query(const dbie_ctx* c, int64_t* n_points, int64_t* n_pixels, int32_t*
 int dbie_set_tile_shape(dbie_ctx* c, int32_t ppl, int32_t waves, int32_t tile_pixels, int32_t persistent) {
     if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
     if (c->opt.precision != DBIE_FP32C) return fail(c, DBIE_E_UNSUPPORTED, "tile shapes apply to FP32C contexts");
+    if (int rc = ctx_check_device(c)) return rc;
     const F32Shape sh{ppl, waves, tile_pixels, persistent};
     int rc = dbie::set_shape(c, sh, false);
     if (!rc) rc = dbie::set_shape(c, sh, true);
@@ -795,6 +815,7 @@ int dbie_set_workspace(dbie_ctx* c, void* dev, int64_t bytes) {
     size_t total = 0;
     for (int r = 0; r < kWsRegions; ++r) total += sz[r];
     if (dev && bytes < (int64_t)total) return fail(c, DBIE_E_WORKSPACE, "workspace smaller than dbie_workspace_bytes");
+    if (int rc = ctx_check_device(c)) return rc;
     // nothing may still use the buffers being given up
     DBIE_HIP(c, hipDeviceSynchronize());
     if (c->acc_owned) (void)hipFree(c->acc);
@@ -829,6 +850,7 @@ int dbie_residual_stats(dbie_ctx* c, const double* fg, double eps, double* out, 
     if (!out) return fail(c, DBIE_E_INVAL, "out is NULL");
     if (!(eps >= 0.0)) return fail(c, DBIE_E_INVAL, "eps must be >= 0");
     if (c->N > 0 && !fg) return fail(c, DBIE_E_INVAL, "fg is NULL");
+    if (int rc = ctx_check_device(c)) return rc;
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     if (c->N > 0) {
         hipStream_t s = (hipStream_t)stream;
@@ -898,32 +920,36 @@ int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s) {
         const int nc = std::min(field32c_shapes(cand, 16), 16);
         float best = 1e30f;
         F32Shape bs = tan ? c->shape_tan : c->shape;
-        hipEvent_t e0, e1;
-        DBIE_HIP(c, hipEventCreate(&e0));
-        DBIE_HIP(c, hipEventCreate(&e1));
+        struct Events {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            ~Events() {
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+            }
+        } ev;
+        DBIE_HIP(c, hipEventCreate(&ev.e0));
+        DBIE_HIP(c, hipEventCreate(&ev.e1));
         for (int k = 0; k < nc; ++k) {
             int rc = set_tiles32(c, cand[k], tan != 0);
             if (rc) return rc;
             rc = eval_core(c, lam, 1, false, tan != 0, nullptr, out, out + 3 * c->N, nullptr,
                            tan ? out + 12 * c->N : nullptr, s);
             if (rc) return rc;
-            DBIE_HIP(c, hipEventRecord(e0, s));
+            DBIE_HIP(c, hipEventRecord(ev.e0, s));
             for (int r = 0; r < 2; ++r) {
                 rc = eval_core(c, lam, 1, false, tan != 0, nullptr, out, out + 3 * c->N, nullptr,
                                tan ? out + 12 * c->N : nullptr, s);
                 if (rc) return rc;
             }
-            DBIE_HIP(c, hipEventRecord(e1, s));
-            DBIE_HIP(c, hipEventSynchronize(e1));
+            DBIE_HIP(c, hipEventRecord(ev.e1, s));
+            DBIE_HIP(c, hipEventSynchronize(ev.e1));
             float ms = 0.0f;
-            DBIE_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+            DBIE_HIP(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
             if (ms < best) {
                 best = ms;
                 bs = cand[k];
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         int rc = set_tiles32(c, bs, tan != 0);
         if (rc) return rc;
         if (cache_path) {

@@ -79,6 +79,8 @@ int ctx_precision(const dbie_ctx* c);
 double ctx_dvds(const dbie_ctx* c);
 SolverState& ctx_solver(dbie_ctx* c);
 int ctx_fail(dbie_ctx* c, int code, const char* msg);
+// DBIE_OK when the current HIP device is the context's, else DBIE_E_INVAL with a message.
+int ctx_check_device(dbie_ctx* c);
 const void* ctx_acc(const dbie_ctx* c);
 int32_t ctx_split(const dbie_ctx* c);
 double* ctx_xyz(dbie_ctx* c);   // the context's own copy of the points (device [3][N])

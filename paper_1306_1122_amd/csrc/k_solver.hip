@@ -818,6 +818,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     if (!std::isfinite(opt->init_step) || !std::isfinite(opt->lambda_cap))
         return ctx_fail(c, DBIE_E_INVAL, "init_step and lambda_cap must be finite");
     const int64_t N = ctx_n(c);
+    if (int rc = ctx_check_device(c)) return rc;
     if (N > 0 && (!lam || !status || !trials))
         return ctx_fail(c, DBIE_E_INVAL, "lambda_inout, status and trials are required");
     if (N == 0) return DBIE_OK;

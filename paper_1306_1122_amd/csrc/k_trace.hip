@@ -158,6 +158,7 @@ extern "C" int dbie_trace_lines(dbie_ctx* c, const dbie_lambda_grid* lg, const d
     if (!(box[2] > 0.0)) return ctx_fail(c, DBIE_E_INVAL, "box z_lo must be > 0 (the field needs z > 0)");
     if (lg->nx < 1 || lg->ny < 1 || lg->nz < 1 || !lg->lambda)
         return ctx_fail(c, DBIE_E_INVAL, "lambda grid needs nx, ny, nz >= 1 and a lambda pointer");
+    if (int rc = ctx_check_device(c)) return rc;
     if (!(lg->dx > 0.0 && lg->dy > 0.0 && lg->dz > 0.0))
         return ctx_fail(c, DBIE_E_INVAL, "lambda grid spacing must be positive");
     const int64_t N = ctx_n(c);

@@ -404,6 +404,7 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
     if (!c) return DBIE_E_INVAL;
     const int64_t N = ctx_n(c);
     if (N > 0 && !lam) return ctx_fail(c, DBIE_E_INVAL, "lambda is required");
+    if (int rc = ctx_check_device(c)) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int32_t nb = ctx_nb(c);
     const Geo& geo = ctx_geo(c);

@@ -32,17 +32,24 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _need(t: torch.Tensor, name: str, shape: Sequence[int], dtype=torch.float64):
+def _need(t: torch.Tensor, name: str, shape: Sequence[int], dtype=torch.float64, device=None):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be on the GPU")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the context on {device}")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _on(device: torch.device):
+    """Make the context's device current for a call (the library requires it)."""
+    return torch.cuda.device(device)
 
 
 class Context:
@@ -63,7 +70,8 @@ class Context:
 
     def close(self):
         if self.handle:
-            _lib().dbie_destroy(self.handle)
+            with _on(self.device):
+                _lib().dbie_destroy(self.handle)
             self.handle = None
         self._ws = None
 
@@ -116,6 +124,9 @@ def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[
     if xyz.dim() != 2 or xyz.shape[0] != 3:
         raise ValueError("xyz must have shape [3, N]")
     _need(xyz, "xyz", tuple(xyz.shape))
+    for bd in boundaries:
+        if bd["B0"].device != xyz.device:
+            raise ValueError("every B0 must be on the device of xyz")
     N = int(xyz.shape[1])
     prob = L.dbie_problem()
     prob.n_boundaries = nb
@@ -124,6 +135,8 @@ def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[
     prob.xyz = xyz.data_ptr()
     segarr = None
     if seg is not None:
+        if len(seg) != nb + 1:
+            raise ValueError(f"seg must hold n_boundaries + 1 = {nb + 1} offsets")
         segarr = (ctypes.c_int64 * len(seg))(*[int(s) for s in seg])
         prob.seg = segarr
     opt = dbie_default_options()
@@ -135,7 +148,8 @@ def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[
     opt.quad_points = int(quad_points)
     opt.pixel_split = int(pixel_split)
     h = ctypes.c_void_p()
-    rc = lib.dbie_init(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), _stream(stream))
+    with _on(xyz.device):
+        rc = lib.dbie_init(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), _stream(stream))
     if rc != L.DBIE_OK:
         msg = lib.dbie_last_error(None)
         raise DbieError(f"dbie_init failed ({rc}): {msg.decode() if msg else ''}")
@@ -149,7 +163,7 @@ def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, t
     squeeze = lam.dim() == 2
     lam3 = lam.unsqueeze(0) if squeeze else lam
     Lt = int(lam3.shape[0])
-    _need(lam3, "lambda", (Lt, 3, N))
+    _need(lam3, "lambda", (Lt, 3, N), device=ctx.device)
     dev = lam.device
     z = lambda *s: torch.empty(*s, dtype=torch.float64, device=dev)  # noqa: E731
     B = z(Lt, 3, N) if B is None else B
@@ -158,9 +172,11 @@ def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, t
     tan = (z(Lt, 12, N) if want_tan else None) if tan is None else tan
     for t, nm, rows in ((B, "B", 3), (dB, "dB", 9), (fg, "fg", 2), (tan, "tan", 12)):
         if t is not None:
-            _need(t, nm, (Lt, rows, N) if t.dim() == 3 else (rows, N))
-    rc = _lib().dbie_eval_field(ctx.handle, _ptr(lam3), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
-                                _stream(stream))
+            # a 2-D output is accepted for one trial only
+            _need(t, nm, (Lt, rows, N) if (t.dim() == 3 or Lt > 1) else (rows, N), device=ctx.device)
+    with _on(ctx.device):
+        rc = _lib().dbie_eval_field(ctx.handle, _ptr(lam3), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
+                                    _stream(stream))
     _check(rc, ctx, "dbie_eval_field")
     out = dict(B=B, dB=dB, fg=fg, tan=tan)
     if squeeze:
@@ -175,15 +191,16 @@ def dbie_eval_field_scalar(ctx: Context, lam: torch.Tensor, want_dB: bool = True
     squeeze = lam.dim() == 1
     lam2 = lam.unsqueeze(0) if squeeze else lam
     Lt = int(lam2.shape[0])
-    _need(lam2, "lambda", (Lt, N))
+    _need(lam2, "lambda", (Lt, N), device=ctx.device)
     dev = lam.device
     z = lambda *s: torch.empty(*s, dtype=torch.float64, device=dev)  # noqa: E731
     B = z(Lt, 3, N)
     dB = z(Lt, 9, N) if want_dB else None
     fg = z(Lt, 2, N) if want_fg else None
     tan = z(Lt, 12, N) if want_tan else None
-    rc = _lib().dbie_eval_field_scalar(ctx.handle, _ptr(lam2), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
-                                       _stream(stream))
+    with _on(ctx.device):
+        rc = _lib().dbie_eval_field_scalar(ctx.handle, _ptr(lam2), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
+                                           _stream(stream))
     _check(rc, ctx, "dbie_eval_field_scalar")
     out = dict(B=B, dB=dB, fg=fg, tan=tan)
     if squeeze:
@@ -199,14 +216,18 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
     from the start values in lambda_inout [3, N], which receives |lambda*|. Returns dict(lam, B, fg,
     status, trials): status per point (_lib.DBIE_ST_*), trials = evaluations used."""
     N = ctx.n_points
-    _need(lambda_inout, "lambda_inout", (3, N))
+    _need(lambda_inout, "lambda_inout", (3, N), device=ctx.device)
     dev = lambda_inout.device
     B = (torch.empty(3, N, dtype=torch.float64, device=dev) if want_B else None) if B is None else B
     fg = (torch.empty(2, N, dtype=torch.float64, device=dev) if want_fg else None) if fg is None else fg
     status = torch.empty(N, dtype=torch.int32, device=dev) if status is None else status
     trials = torch.empty(N, dtype=torch.int32, device=dev) if trials is None else trials
-    _need(status, "status", (N,), torch.int32)
-    _need(trials, "trials", (N,), torch.int32)
+    _need(status, "status", (N,), torch.int32, device=ctx.device)
+    _need(trials, "trials", (N,), torch.int32, device=ctx.device)
+    if B is not None:
+        _need(B, "B", (3, N), device=ctx.device)
+    if fg is not None:
+        _need(fg, "fg", (2, N), device=ctx.device)
     o = dbie_default_solve_opts()
     o.method = {"nm": L.DBIE_NELDER_MEAD, "lm": L.DBIE_LEVENBERG_MARQUARDT}[method]
     o.max_trials = int(max_trials)
@@ -215,8 +236,9 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
     o.lambda_cap = float(lambda_cap)
     o.fp64_accept = int(bool(fp64_accept))
     o.use_graph = int(bool(use_graph))
-    rc = _lib().dbie_solve_lambda(ctx.handle, _ptr(lambda_inout), ctypes.byref(o), _ptr(B), _ptr(fg),
-                                  _ptr(status), _ptr(trials), _stream(stream))
+    with _on(ctx.device):
+        rc = _lib().dbie_solve_lambda(ctx.handle, _ptr(lambda_inout), ctypes.byref(o), _ptr(B), _ptr(fg),
+                                      _ptr(status), _ptr(trials), _stream(stream))
     _check(rc, ctx, "dbie_solve_lambda")
     return dict(lam=lambda_inout, B=B, fg=fg, status=status, trials=trials)
 
@@ -228,20 +250,25 @@ def dbie_grad(ctx: Context, lam: torch.Tensor, gB=None, gdB=None, want_glambda: 
     glambda [3, N], gB0 (concatenated [3, ny, nx] per boundary; see split_gB0) and, on request, the
     residual Jacobian d(u, s)/d mu [4, 3, N]."""
     N = ctx.n_points
-    _need(lam, "lambda", (3, N))
+    _need(lam, "lambda", (3, N), device=ctx.device)
     dev = lam.device
     if gB is not None:
-        _need(gB, "gB", (3, N))
+        _need(gB, "gB", (3, N), device=ctx.device)
     if gdB is not None:
-        _need(gdB, "gdB", (9, N))
+        _need(gdB, "gdB", (9, N), device=ctx.device)
     glambda = (torch.empty(3, N, dtype=torch.float64, device=dev) if want_glambda else None) \
         if glambda is None else glambda
     gB0 = (torch.empty(3 * ctx.n_pixels, dtype=torch.float64, device=dev) if want_gB0 else None) \
         if gB0 is None else gB0
     resid_jac = (torch.empty(4, 3, N, dtype=torch.float64, device=dev) if want_resid_jac else None) \
         if resid_jac is None else resid_jac
-    rc = _lib().dbie_grad(ctx.handle, _ptr(lam), _ptr(gB), _ptr(gdB), _ptr(glambda), _ptr(gB0),
-                          _ptr(resid_jac), _stream(stream))
+    for t, nm, shape in ((glambda, "glambda", (3, N)), (gB0, "gB0", (3 * ctx.n_pixels,)),
+                         (resid_jac, "resid_jac", (4, 3, N))):
+        if t is not None:
+            _need(t, nm, shape, device=ctx.device)
+    with _on(ctx.device):
+        rc = _lib().dbie_grad(ctx.handle, _ptr(lam), _ptr(gB), _ptr(gdB), _ptr(glambda), _ptr(gB0),
+                              _ptr(resid_jac), _stream(stream))
     _check(rc, ctx, "dbie_grad")
     return dict(glambda=glambda, gB0=gB0, resid_jac=resid_jac)
 
@@ -282,8 +309,9 @@ def dbie_query_tan(ctx: Context) -> Dict[str, int]:
 
 
 def dbie_set_tile_shape(ctx: Context, ppl: int, waves: int, tile_pixels: int, persistent: bool = False):
-    _check(_lib().dbie_set_tile_shape(ctx.handle, int(ppl), int(waves), int(tile_pixels), int(bool(persistent))),
-           ctx, "dbie_set_tile_shape")
+    with _on(ctx.device):
+        rc = _lib().dbie_set_tile_shape(ctx.handle, int(ppl), int(waves), int(tile_pixels), int(bool(persistent)))
+    _check(rc, ctx, "dbie_set_tile_shape")
 
 
 def dbie_query_persistent(ctx: Context) -> Dict[str, bool]:
@@ -316,7 +344,7 @@ def dbie_trace_lines(ctx: Context, lam_grid: torch.Tensor, origin, spacing, box,
     box = (x_lo, y_lo, z_lo, x_hi, y_hi, z_hi). Returns dict(xyz=[n_steps + 1, 3, N], count=[N])."""
     if lam_grid.dim() != 4 or lam_grid.shape[0] != 3:
         raise ValueError("lam_grid must have shape [3, nz, ny, nx]")
-    _need(lam_grid, "lam_grid", tuple(lam_grid.shape))
+    _need(lam_grid, "lam_grid", tuple(lam_grid.shape), device=ctx.device)
     N = ctx.n_points
     g = L.dbie_lambda_grid()
     g.nz, g.ny, g.nx = (int(v) for v in lam_grid.shape[1:])
@@ -327,19 +355,23 @@ def dbie_trace_lines(ctx: Context, lam_grid: torch.Tensor, origin, spacing, box,
     xyz = torch.empty(int(n_steps) + 1, 3, N, dtype=torch.float64, device=lam_grid.device)
     count = torch.empty(N, dtype=torch.int32, device=lam_grid.device)
     m = {"field": L.DBIE_TRACE_FIELD, "current": L.DBIE_TRACE_CURRENT}[mode]
-    _check(_lib().dbie_trace_lines(ctx.handle, ctypes.byref(g), bx, float(ds), int(n_steps), m, float(sense),
-                                   xyz.data_ptr() if N else None, count.data_ptr() if N else None,
-                                   _stream(stream)), ctx, "dbie_trace_lines")
+    with _on(ctx.device):
+        rc = _lib().dbie_trace_lines(ctx.handle, ctypes.byref(g), bx, float(ds), int(n_steps), m, float(sense),
+                                     xyz.data_ptr() if N else None, count.data_ptr() if N else None,
+                                     _stream(stream))
+    _check(rc, ctx, "dbie_trace_lines")
     return dict(xyz=xyz, count=count)
 
 
 def dbie_residual_stats(ctx: Context, fg: torch.Tensor, eps: float = 1e-4, stream=None) -> Dict[str, float]:
     """Means of f and g over the points with finite residuals, their number, and the number with
     max(f, g) <= eps, reduced on the device."""
-    _need(fg, "fg", (2, ctx.n_points))
+    _need(fg, "fg", (2, ctx.n_points), device=ctx.device)
     out = (ctypes.c_double * 4)()
-    _check(_lib().dbie_residual_stats(ctx.handle, fg.data_ptr() if ctx.n_points else None, float(eps), out,
-                                      _stream(stream)), ctx, "dbie_residual_stats")
+    with _on(ctx.device):
+        rc = _lib().dbie_residual_stats(ctx.handle, fg.data_ptr() if ctx.n_points else None, float(eps), out,
+                                        _stream(stream))
+    _check(rc, ctx, "dbie_residual_stats")
     return dict(mean_f=out[0], mean_g=out[1], finite=int(out[2]), converged=int(out[3]))
 
 
@@ -357,13 +389,18 @@ def dbie_set_workspace(ctx: Context, ws: Optional[torch.Tensor]):
     """Give the context a caller-owned device workspace (a uint8 tensor of at least
     dbie_workspace_bytes(ctx) bytes, kept alive by the context object), or None to go back."""
     if ws is None:
-        _check(_lib().dbie_set_workspace(ctx.handle, None, 0), ctx, "dbie_set_workspace")
+        with _on(ctx.device):
+            rc = _lib().dbie_set_workspace(ctx.handle, None, 0)
+        _check(rc, ctx, "dbie_set_workspace")
         ctx._ws = None
         return
     if not ws.is_cuda or not ws.is_contiguous():
         raise ValueError("workspace must be a contiguous device tensor")
-    _check(_lib().dbie_set_workspace(ctx.handle, ws.data_ptr(), ws.numel() * ws.element_size()), ctx,
-           "dbie_set_workspace")
+    if ws.device != ctx.device:
+        raise ValueError(f"workspace is on {ws.device}, the context on {ctx.device}")
+    with _on(ctx.device):
+        rc = _lib().dbie_set_workspace(ctx.handle, ws.data_ptr(), ws.numel() * ws.element_size())
+    _check(rc, ctx, "dbie_set_workspace")
     ctx._ws = ws
 
 

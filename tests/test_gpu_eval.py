@@ -200,6 +200,18 @@ def test_zero_points_and_invalid_points():
     nanp = T(np.array([[np.nan], [0.0], [1.0]]))
     with pytest.raises(D.DbieError, match="non-finite"):
         D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], nanp)
+    # the binding rejects what the library could not check: a short offset list, and a caller's
+    # output buffer too small for the trials
+    pts = T(np.array([[0.5, 1.5], [0.5, 1.5], [1.0, 2.0]]))
+    with pytest.raises(ValueError, match="seg must hold"):
+        D.dbie_init([dict(B0=B0), dict(B0=B0)], pts, seg=[0, 2])
+    ctx2 = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], pts)
+    lam2 = torch.zeros(2, 3, 2, dtype=torch.float64, device=dev())
+    with pytest.raises(ValueError, match="shape"):
+        D.dbie_eval_field(ctx2, lam2, B=torch.empty(3, 2, dtype=torch.float64, device=dev()))
+    with pytest.raises(ValueError, match="shape"):
+        D.dbie_grad(ctx2, lam2[0], gB=torch.ones(3, 2, dtype=torch.float64, device=dev()),
+                    gB0=torch.empty(3, dtype=torch.float64, device=dev()))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
