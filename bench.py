@@ -60,7 +60,13 @@ def cpu_baseline(w, n_sample, seed=7):
         n = sum(pool.map(_oracle_chunk, jobs))
         dt = time.perf_counter() - t0
     pairs = n * bd.nx * bd.ny
-    return dict(value=pairs / dt, unit="pairs/s", cores=cores, kind="oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=pairs / dt, unit="pairs/s", cores=cores, kind="oracle", cpu=model,
                 sample=f"{n} z-stratified points of the {w.name} workload x all {bd.nx * bd.ny} pixels "
                        f"(FP64 field + grad + mu-tangents + residuals), {dt:.2f} s wall")
 

@@ -78,6 +78,8 @@ struct dbie_ctx {
     int32_t* near_pts = nullptr;
     int32_t* pix_bnd = nullptr;
     int64_t near_pairs = 0;
+    void* vjp_dev = nullptr;    // the adjoint's tile lists and point segments (VjpTables)
+    VjpTables vjp{};
     int32_t* perm = nullptr;    // FP32C point order (NULL = identity): per magnetogram, the points
                                 // with near-field pairs first, sorted by their window, then the rest
     Tile* tiles64 = nullptr;
@@ -178,6 +180,7 @@ void free_ctx(dbie_ctx* c) {
     (void)hipFree(c->near_ptr);
     (void)hipFree(c->near_pts);
     (void)hipFree(c->pix_bnd);
+    (void)hipFree(c->vjp_dev);
     (void)hipFree(c->tiles64);
     (void)hipFree(c->tiles32);
     (void)hipFree(c->tiles32t);
@@ -320,6 +323,7 @@ bool ctx_timing(const dbie_ctx* c) { return c->timing; }
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
+VjpTables ctx_vjp_tables(const dbie_ctx* c) { return c->vjp; }
 QuadGrid ctx_grid(const dbie_ctx* c) { return QuadGrid{c->gpos, c->gB, c->qlw, c->G, c->ngrid_total, c->gposf}; }
 int ctx_precision(const dbie_ctx* c) { return c->opt.precision; }
 double ctx_dvds(const dbie_ctx* c) { return c->opt.dv_over_dsigma_h; }
@@ -582,6 +586,7 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         DBIE_INIT_HIP(hipMemcpy(c->tiles64, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
         c->n_tiles64 = (int64_t)t.size();
     }
+    DBIE_INIT_HIP(vjp_tables_init(c, &c->vjp_dev, &c->vjp));
     if (o.precision == DBIE_FP32C) {
         rc = set_tiles32(c, c->shape, false);
         if (!rc) rc = set_tiles32(c, c->shape_tan, true);

@@ -96,6 +96,15 @@ extern void* const kWsTooSmall;
 void* ctx_ws_region(dbie_ctx* c, int region, size_t bytes);
 size_t solver_workspace_bytes(const dbie_ctx* c);
 size_t grad_workspace_bytes(const dbie_ctx* c);   // dbie_grad's gB0 part (scratch slot 1)
+// The transpose kernels' pixel-tile lists and the point segments, on the device (built in dbie_init):
+// n64 tiles of the FP64 kernel, then n32 of the FP32C kernel, then nb + 1 int64 offsets at seg_off.
+struct VjpTables {
+    const void* base;
+    int64_t n64, n32;
+    size_t seg_off;
+};
+hipError_t vjp_tables_init(const dbie_ctx* c, void** dev, VjpTables* t);
+VjpTables ctx_vjp_tables(const dbie_ctx* c);
 void ws_sizes(const dbie_ctx* c, size_t sz[kWsRegions]);
 // Near-field pairs grouped by pixel (global pixel index over all magnetograms), for the adjoint.
 struct NearLists {

@@ -365,32 +365,50 @@ using namespace dbie;
 
 namespace dbie {
 // Pixel tiles of the two adjoint kernels and the workspace sizes of dbie_grad's gB0 part.
+// Pixel tiles of every boundary's grid: 256 grid points each (FP64 kernel) and 256 * kVjpPix
+// (FP32C kernel), uploaded once with the point segments.
+hipError_t vjp_tables_init(const dbie_ctx* c, void** dev, VjpTables* t) {
+    std::vector<PixTile> pt;
+    const int32_t nb = ctx_nb(c);
+    for (int per : {256, 256 * kVjpPix}) {
+        for (int32_t b = 0; b < nb; ++b) {
+            const BoundaryDev& bd = ctx_bnd_host(c, b);
+            for (int32_t k = 0; k < bd.gcols * bd.grows; k += per) pt.push_back(PixTile{b, k});
+        }
+        if (per == 256) t->n64 = (int64_t)pt.size();
+    }
+    t->n32 = (int64_t)pt.size() - t->n64;
+    t->seg_off = (pt.size() * sizeof(PixTile) + 255) / 256 * 256;
+    const size_t bytes = t->seg_off + (size_t)(nb + 1) * sizeof(int64_t);
+    *dev = nullptr;
+    hipError_t e = hipMalloc(dev, bytes);
+    if (e == hipSuccess) e = hipMemcpy(*dev, pt.data(), pt.size() * sizeof(PixTile), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)*dev + t->seg_off, ctx_seg(c), (size_t)(nb + 1) * sizeof(int64_t),
+                      hipMemcpyHostToDevice);
+    t->base = *dev;
+    return e;
+}
+
 struct GradPlan {
-    std::vector<PixTile> pt, pt32;
     int32_t S;                  // point slices of the transpose launch
-    size_t szc, szt, szs, szg, szp;
-    size_t bytes() const { return szc + szt + szs + szg + szp; }
+    size_t szc, szg, szp;
+    size_t bytes() const { return szc + szg + szp; }
 };
 
 static GradPlan grad_plan(const dbie_ctx* c) {
     GradPlan g;
     const int32_t nb = ctx_nb(c);
-    for (int32_t b = 0; b < nb; ++b) {
-        const BoundaryDev& bd = ctx_bnd_host(c, b);
-        for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256) g.pt.push_back(PixTile{b, k});
-        for (int32_t k = 0; k < bd.gcols * bd.grows; k += 256 * kVjpPix) g.pt32.push_back(PixTile{b, k});
-    }
+    const VjpTables vt = ctx_vjp_tables(c);
     const QuadGrid grid = ctx_grid(c);
     // Point slices: the pixel tiles alone are few for small magnetograms (16 workgroups for 128^2 in
     // FP32C); about four workgroups per compute unit, at least one 64-point chunk per slice.
-    const size_t tiles = ctx_precision(c) == DBIE_FP64 ? g.pt.size() : g.pt32.size();
+    const size_t tiles = (size_t)(ctx_precision(c) == DBIE_FP64 ? vt.n64 : vt.n32);
     int64_t maxseg = 0;
     for (int32_t b = 0; b < nb; ++b) maxseg = std::max(maxseg, ctx_seg(c)[b + 1] - ctx_seg(c)[b]);
     const int64_t want = (1024 + (int64_t)std::max<size_t>(tiles, 1) - 1) / (int64_t)std::max<size_t>(tiles, 1);
     g.S = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, 64, (maxseg + 63) / 64}));
-    g.szc = (size_t)std::max<int64_t>(ctx_n(c), 1) * kVjpCoef * sizeof(double);
-    g.szt = ((g.pt.size() + g.pt32.size()) * sizeof(PixTile) + 255) / 256 * 256;
-    g.szs = ((size_t)(nb + 1) * sizeof(int64_t) + 255) / 256 * 256;
+    g.szc = ((size_t)std::max<int64_t>(ctx_n(c), 1) * kVjpCoef * sizeof(double) + 255) / 256 * 256;
     g.szg = grid.G ? (size_t)grid.n_total * 3 * sizeof(double) : 0;
     g.szp = g.S > 1 ? (size_t)g.S * grid.n_total * 3 * sizeof(double) : 0;
     return g;
@@ -433,25 +451,20 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
         // pixel tiles of every boundary, and the point segments on the device
         const QuadGrid grid = ctx_grid(c);
         const GradPlan gp = grad_plan(c);
-        const std::vector<PixTile>& pt = gp.pt;
-        const std::vector<PixTile>& pt32 = gp.pt32;
-        const size_t szc = gp.szc, szt = gp.szt, szs = gp.szs;
+        const VjpTables vt = ctx_vjp_tables(c);
         char* w = (char*)ctx_scratch(c, 1, gp.bytes());
         if (!w) return ctx_fail(c, DBIE_E_WORKSPACE, "cannot allocate the adjoint workspace");
         double* coef = (double*)w;
-        PixTile* ptd = (PixTile*)(w + szc);
-        int64_t* segd = (int64_t*)(w + szc + szt);
-        double* gW = grid.G ? (double*)(w + szc + szt + szs) : gB0;
+        double* gW = grid.G ? (double*)(w + gp.szc) : gB0;
         // with point slices the transpose kernels write S partial outputs, reduced into gW in order
         const int64_t T3 = grid.n_total * 3;
-        double* parts = gp.S > 1 ? (double*)(w + szc + szt + szs + gp.szg) : gW;
-        PixTile* ptd32 = ptd + pt.size();
-        GRAD_HIP(hipMemcpyAsync(ptd, pt.data(), pt.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
-        GRAD_HIP(hipMemcpyAsync(ptd32, pt32.data(), pt32.size() * sizeof(PixTile), hipMemcpyHostToDevice, s));
-        GRAD_HIP(hipMemcpyAsync(segd, ctx_seg(c), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        double* parts = gp.S > 1 ? (double*)(w + gp.szc + gp.szg) : gW;
+        const PixTile* ptd = (const PixTile*)vt.base;
+        const PixTile* ptd32 = ptd + vt.n64;
+        const int64_t* segd = (const int64_t*)((const char*)vt.base + vt.seg_off);
         if (N > 0)
             hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
-        const dim3 g64((unsigned)pt.size(), (unsigned)gp.S), g32((unsigned)pt32.size(), (unsigned)gp.S);
+        const dim3 g64((unsigned)vt.n64, (unsigned)gp.S), g32((unsigned)vt.n32, (unsigned)gp.S);
         if (ctx_precision(c) == DBIE_FP64) {
             hipLaunchKernelGGL(k_vjp64, g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos, coef, parts, T3);
         } else {
@@ -474,8 +487,6 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
             for (int32_t b = 0; b < nb; ++b)
                 GRAD_HIP(launch_quad_transpose(ctx_bnd_host(c, b), gW, grid.lw, grid.G, gB0, s));
         GRAD_HIP(hipGetLastError());
-        // the host arrays above must stay alive until the copies have been consumed
-        GRAD_HIP(hipStreamSynchronize(s));
     }
     return DBIE_OK;
 #undef GRAD_HIP
