@@ -232,9 +232,12 @@ def residual_jacobian(B, dB, tan, h, dv_over_dsigma_h: float = 1.0 / 6.0):
 # ------------------------------------------------------------------------------------------------
 # VJP: transpose of Eq. (16) with its frozen-lambda derivative rows
 # ------------------------------------------------------------------------------------------------
-def vjp(B0, x0, y0, h, xyz, lam, gB=None, gdB=None, chunk: int = 64):
+def vjp(B0, x0, y0, h, xyz, lam, gB=None, gdB=None, chunk: int = 64, pixels=None):
     """g_B0[p, k] = sum_i h^2 [K_p gB_p + dK_p/dx_i gdB_{p,x} + dK_p/dy_i gdB_{p,y} + dK_p/dz_i gdB_{p,z}]
-    and g_lambda from the tangents: g_mu_p = gB_p . tan_p + sum_q gdB_pq . tan_pq, g_lambda = 2 lambda g_mu."""
+    and g_lambda from the tangents: g_mu_p = gB_p . tan_p + sum_q gdB_pq . tan_pq, g_lambda = 2 lambda g_mu.
+
+    pixels (flat indices b * nx + a): only those outputs, as g_B0 [3, len(pixels)], with g_lambda
+    and g_mu returned as None (the same sum over every point, for a few pixels of a large problem)."""
     B0 = np.asarray(B0, np.float64)
     ny, nx = B0.shape[1:]
     npts = xyz.shape[1]
@@ -243,7 +246,11 @@ def vjp(B0, x0, y0, h, xyz, lam, gB=None, gdB=None, chunk: int = 64):
     if gdB is None:
         gdB = np.zeros((9, npts))
     X, Y = pixel_centres(nx, ny, x0, y0, h)
-    gB0 = np.zeros((3, nx * ny))
+    if pixels is not None:
+        pixels = np.asarray(pixels, np.int64)
+        X, Y = X[pixels], Y[pixels]
+        chunk = max(chunk, (1 << 18) // max(len(pixels), 1))
+    gB0 = np.zeros((3, X.size))
     w = h * h / TWO_PI
     for s in range(0, npts, chunk):
         e = min(npts, s + chunk)
@@ -263,6 +270,8 @@ def vjp(B0, x0, y0, h, xyz, lam, gB=None, gdB=None, chunk: int = 64):
                     - zi * G * dy * gdB[3 * p + 1, s:e, None]
                     + (F + zi * zi * G) * gdB[3 * p + 2, s:e, None])
             gB0[p] += w * np.sum(np.ascontiguousarray(coef.T), axis=1)
+    if pixels is not None:
+        return gB0, None, None
     _, _, tan = field(B0, x0, y0, h, xyz, lam, tangents=True)
     gmu = np.zeros((3, npts))
     for p in range(3):

@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import paper_1306_1122_amd as D
-from workloads import config3
+from workloads import config2, config3
 
 pytestmark = pytest.mark.gpu
 
@@ -143,3 +143,25 @@ def test_grad_at_large_lambda_matches_oracle(precision, tol):
     e = rel(r["gB0"].cpu().numpy().reshape(3, ny, nx), gB0_ref)
     print("large-lambda adjoint", precision, "%.2e" % e, flush=True)
     assert e <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_full_size_adjoint_sampled(precision):
+    """The benchmark's adjoint: the 128x128 bipole magnetogram and all 2^20 points of its grid, one
+    trial, seeded upstream gradients; eight pixels (the four corners, edges, the interior) against
+    the oracle's sum over every point."""
+    w = config2()
+    bd = w.boundaries[0]
+    rng = np.random.default_rng(36)
+    gB = rng.normal(size=(3, w.n_points))
+    gdB = rng.normal(size=(9, w.n_points))
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision=precision)
+    r = D.dbie_grad(ctx, T(w.lam), gB=T(gB), gdB=T(gdB), want_glambda=False)
+    torch.cuda.synchronize()
+    nx = ny = 128
+    pix = np.array([0, nx - 1, (ny - 1) * nx, nx * ny - 1, 5, 3 * nx, 64 * nx + 64, int(rng.integers(nx * ny))])
+    ref, _, _ = oracle.vjp(bd.B0, bd.x0, bd.y0, bd.h, w.xyz, w.lam, gB, gdB, pixels=pix)
+    got = r["gB0"].view(3, -1)[:, pix].cpu().numpy()
+    err = rel(got, ref)
+    print("full-size adjoint", precision, f"{err:.1e}", flush=True)
+    assert err <= (1e-10 if precision == "fp64" else 1e-5)

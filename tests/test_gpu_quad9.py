@@ -201,3 +201,27 @@ def test_lm_search_follows_the_oracle():
             same += 1
     print("quad9 LM identical trajectories", same, "of", n, flush=True)
     assert same >= int(0.9 * n)
+
+
+@pytest.mark.parametrize("G", [2, 4])
+def test_full_size_elements_sampled(G):
+    """The benchmark's element run: the 128x128 bipole magnetogram cropped to 127x127, all 2^20
+    points of the 128x128x64 grid, FP32C in its default launch shape; z-stratified points (48 for
+    G = 2, 24 for G = 4) against the oracle's element sum, and their (f, g) against the oracle's
+    residuals."""
+    from workloads import config2, z_stratified_subsample
+    w = config2()
+    B0 = np.ascontiguousarray(w.boundaries[0].B0[:, :127, :127])
+    ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(w.xyz), precision="fp32c", quad_points=G)
+    out = D.dbie_eval_field(ctx, T(w.lam), want_tan=True)
+    torch.cuda.synchronize()
+    idx = z_stratified_subsample(w.xyz, 48 if G == 2 else 24, seed=31 + G)
+    B, dB, tan = oracle.field_quad9(B0, 0.0, 0.0, 1.0, w.xyz[:, idx], w.lam[:, idx], G=G, tangents=True)
+    errs = dict(B=rel(out["B"][:, idx].cpu(), B), dB=rel(out["dB"][:, idx].cpu(), dB),
+                tan=rel(out["tan"][:, idx].cpu(), tan))
+    print("quad9 full size", G, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= TOLS["fp32c"], (k, v)
+    res = oracle.residuals(B, dB, 1.0)
+    fg = out["fg"][:, idx].cpu().numpy()
+    assert rel(fg[0], res["f"]) <= 1e-4 and rel(fg[1], res["g"]) <= 1e-4

@@ -382,6 +382,27 @@ def test_vjp_dot_product():
     assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + np.abs(gB0).max())
 
 
+def test_vjp_selected_pixels_are_forward_maps_of_unit_fields():
+    """gB0 at a chosen pixel k and component p equals <g, A(lambda) e_pk>: the forward map applied to
+    a magnetogram that is 1 at that pixel and component and 0 elsewhere (the restricted output path,
+    with its own point chunking, pinned to the forward sum)."""
+    rng = np.random.default_rng(18)
+    B0, x0, y0, h, xyz, lam = random_case(rng, npts=300)
+    gB = rng.normal(size=(3, 300))
+    gdB = rng.normal(size=(9, 300))
+    ny, nx = B0.shape[1:]
+    pix = np.array([0, nx * ny - 1, nx + 2, rng.integers(nx * ny)])
+    sel, none1, none2 = oracle.vjp(B0, x0, y0, h, xyz, lam, gB, gdB, pixels=pix)
+    assert sel.shape == (3, pix.size) and none1 is None and none2 is None
+    for j, k in enumerate(pix):
+        for p in range(3):
+            e = np.zeros_like(B0)
+            e[p].flat[k] = 1.0
+            B, dB = oracle.field(e, x0, y0, h, xyz, lam)
+            ref = np.sum(gB * B) + np.sum(gdB * dB)
+            assert abs(sel[p, j] - ref) <= 1e-12 * max(abs(ref), 1.0), (k, p)
+
+
 def test_vjp_lambda_gradient_matches_differences():
     rng = np.random.default_rng(17)
     B0, x0, y0, h, xyz, lam = random_case(rng, npts=5)
