@@ -76,10 +76,41 @@ struct Geo {
     int32_t* bidx;
 };
 
+// sin and cos of t for |t| < kSincosBound, to about one ulp, without branches: t = k pi/2 + r with
+// k = rint(2t/pi) and r from a two-constant Cody-Waite reduction (with FMA the first step is exact
+// for |k| < 2^20, the second leaves ~1e-27), polynomials on [-pi/4, pi/4] fitted by least squares on
+// Chebyshev nodes in 50-digit arithmetic (sin r = r + r^3 P(r^2), cos r = 1 - r^2/2 + r^4 Q(r^2),
+// both of degree 5; fit errors below 2e-17 with the coefficients rounded to double), and the
+// quadrant k mod 4 applied by selects. Larger arguments take the device library's sincos.
+constexpr double kSincosBound = 524288.0;   // 2^19
+__device__ __forceinline__ void sincos_reduced(double t, double* s, double* c) {
+    const double k = __builtin_rint(t * 0.6366197723675814);
+    double r = __builtin_fma(-k, 1.5707963267948966, t);
+    r = __builtin_fma(-k, 6.123233995736766e-17, r);
+    const double z = r * r;
+    double p = __builtin_fma(z, 1.5896542207786722e-10, -2.5050753161004457e-08);
+    p = __builtin_fma(z, p, 2.7557313655329285e-06);
+    p = __builtin_fma(z, p, -0.00019841269829682216);
+    p = __builtin_fma(z, p, 0.008333333333322219);
+    p = __builtin_fma(z, p, -0.1666666666666663);
+    const double sr = __builtin_fma(r * z, p, r);
+    double q = __builtin_fma(z, -1.135923037716418e-11, 2.0875714493184434e-09);
+    q = __builtin_fma(z, q, -2.7557314281167143e-07);
+    q = __builtin_fma(z, q, 2.4801587289206567e-05);
+    q = __builtin_fma(z, q, -0.001388888888887362);
+    q = __builtin_fma(z, q, 0.041666666666666595);
+    const double cr = __builtin_fma(z * z, q, __builtin_fma(z, -0.5, 1.0));
+    const int qd = (int)k;
+    const double a = (qd & 1) ? cr : sr, b = (qd & 1) ? sr : cr;
+    *s = (qd & 2) ? -a : a;
+    *c = ((qd + 1) & 2) ? -b : b;
+}
+
 // One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
 // dx = a_k - u, dy = b_k - v, w2 = w^2, all in pixels. Shared by the FP64 bulk kernel and the
-// FP64 near-field pass of the FP32C path so that both use identical arithmetic.
-template <bool TAN>
+// FP64 near-field pass of the FP32C path. WIDE: the device library's sincos (any argument);
+// otherwise every |lambda r| must stay below kSincosBound.
+template <bool TAN, bool WIDE>
 __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const double lam[3],
                                           double b0x, double b0y, double b0z, double* acc) {
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
@@ -93,7 +124,8 @@ __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const
     for (int p = 0; p < 3; ++p) {
         const double t = lam[p] * r;
         double s, c;
-        sincos(t, &s, &c);
+        if (WIDE) sincos(t, &s, &c);
+        else sincos_reduced(t, &s, &c);
         const double n = __builtin_fma(t, s, c);
         const double hh = __builtin_fma(t, t * c, -3.0 * n);
         const double nb = n * (ri3 * b0[p]);

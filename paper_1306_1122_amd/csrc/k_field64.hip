@@ -5,7 +5,9 @@
 // Grid: one workgroup per schedule tile (a run of <= tile points of one magnetogram) and one
 // grid row per lambda trial. Each lane owns one point; the magnetogram streams through LDS in
 // tiles of kTP64 pixels that all lanes read at the same address (LDS broadcast). Sums are cascaded:
-// a per-tile partial in FP64, then added to the running FP64 total.
+// a per-tile partial in FP64, then added to the running FP64 total. sin and cos come from the
+// branch-free reduced form unless some pair of the workgroup's points can exceed its argument
+// bound (then, and for NaN lambda, from the device library).
 #include "dbie_internal.h"
 
 namespace dbie {
@@ -22,6 +24,7 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
                                                  double* __restrict__ acc) {
     constexpr int NA = TAN ? kAcc : kAccField;
     __shared__ double sa[kTP64], sb[kTP64], sx[kTP64], sy[kTP64], sz[kTP64];
+    __shared__ int s_wide;
     const Tile t = tiles[blockIdx.x];
     const int trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
@@ -39,6 +42,21 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
         double lm[3];
 #pragma unroll
         for (int p = 0; p < 3; ++p) lm[p] = lam[((int64_t)trial * 3 + p) * N + i] * bd.h;
+        // the largest |lambda r| of the workgroup's pairs (grid positions lie in [0, nx - 1] x
+        // [0, ny - 1]) selects the sin/cos: the branch-free reduced form, or the library's for
+        // arguments beyond its range (and for NaN lambda)
+        {
+            const double dxm = fmax(fabs(u), fabs((double)(bd.nx - 1) - u));
+            const double dym = fmax(fabs(v), fabs((double)(bd.ny - 1) - v));
+            const double rmax = sqrt(dxm * dxm + dym * dym + w2);
+            const double tmax = fmax(fabs(lm[0]), fmax(fabs(lm[1]), fabs(lm[2]))) * rmax;
+            __syncthreads();
+            if (threadIdx.x == 0) s_wide = 0;
+            __syncthreads();
+            if (live && !(tmax < kSincosBound)) s_wide = 1;
+            __syncthreads();
+        }
+        const bool wide = s_wide != 0;
         double tot[NA];
 #pragma unroll
         for (int r = 0; r < NA; ++r) tot[r] = 0.0;
@@ -57,8 +75,12 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
             double part[NA];
 #pragma unroll
             for (int r = 0; r < NA; ++r) part[r] = 0.0;
-            for (int k = 0; k < kn; ++k)
-                pair_fp64<TAN>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
+            if (wide)
+                for (int k = 0; k < kn; ++k)
+                    pair_fp64<TAN, true>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
+            else
+                for (int k = 0; k < kn; ++k)
+                    pair_fp64<TAN, false>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
 #pragma unroll
             for (int r = 0; r < NA; ++r) tot[r] += part[r];
         }

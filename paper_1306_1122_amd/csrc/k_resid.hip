@@ -31,7 +31,7 @@ __device__ __forceinline__ void scale_sums(const double* a, double w, double h, 
 }
 
 // FP64 pairs of the near-field window (the bits set in dbie_init's classification).
-template <bool TAN>
+template <bool TAN, bool WIDE>
 __device__ __forceinline__ void add_near(const BoundaryDev& bd, const double* B0, uint32_t mask,
                                          int32_t wa, int32_t wb, double u, double v, double w2,
                                          const double lm[3], double* a) {
@@ -41,14 +41,14 @@ __device__ __forceinline__ void add_near(const BoundaryDev& bd, const double* B0
         const int ii = bit % kNearSide - kNearWin, jj = bit / kNearSide - kNearWin;
         const int32_t pa = wa + ii, pb = wb + jj;
         const int64_t k = (int64_t)pb * bd.nx + pa;
-        pair_fp64<TAN>((double)pa - u, (double)pb - v, w2, lm, B0[k], B0[bd.npix + k],
+        pair_fp64<TAN, WIDE>((double)pa - u, (double)pb - v, w2, lm, B0[k], B0[bd.npix + k],
                        B0[2 * (int64_t)bd.npix + k], a);
     }
 }
 
 // 9-node elements: every Gauss point of each element flagged near, at its FP64 position, with the
 // FP64 weighted field of the quadrature grid.
-template <bool TAN>
+template <bool TAN, bool WIDE>
 __device__ __forceinline__ void add_near_grid(const BoundaryDev& bd, const double* __restrict__ gpos,
                                               const double* __restrict__ gB, uint32_t mask, int32_t wa,
                                               int32_t wb, double u, double v, double w2, const double lm[3],
@@ -67,7 +67,7 @@ __device__ __forceinline__ void add_near_grid(const BoundaryDev& bd, const doubl
             for (int g = 0; g < bd.G; ++g) {
                 const int32_t c = bd.G * m + g;
                 const int64_t k = (int64_t)r * bd.gcols + c;
-                pair_fp64<TAN>(cpos[c] - u, dy, w2, lm, W[k], W[ng + k], W[2 * ng + k], a);
+                pair_fp64<TAN, WIDE>(cpos[c] - u, dy, w2, lm, W[k], W[ng + k], W[2 * ng + k], a);
             }
         }
     }
@@ -108,12 +108,24 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
             double nr[NA];
 #pragma unroll
             for (int r = 0; r < NA; ++r) nr[r] = 0.0;
-            if (bd.G > 0)
-                add_near_grid<TAN>(bd, gpos, gB, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i], w * w,
-                                   lm, nr);
-            else
-                add_near<TAN>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
-                              w * w, lm, nr);
+            // near pairs lie within a few pixels (a 3 x 3 window of elements at most): |lambda r| is
+            // bounded by 64 |lambda| pixels
+            const bool wide = !(fmax(fabs(lm[0]), fmax(fabs(lm[1]), fabs(lm[2]))) * 64.0 < kSincosBound);
+            if (bd.G > 0) {
+                if (wide)
+                    add_near_grid<TAN, true>(bd, gpos, gB, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
+                                             w * w, lm, nr);
+                else
+                    add_near_grid<TAN, false>(bd, gpos, gB, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
+                                              w * w, lm, nr);
+            } else {
+                if (wide)
+                    add_near<TAN, true>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], geo.u[i], geo.v[i],
+                                        w * w, lm, nr);
+                else
+                    add_near<TAN, false>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], geo.u[i],
+                                         geo.v[i], w * w, lm, nr);
+            }
 #pragma unroll
             for (int r = 0; r < NA; ++r) a[r] += nr[r];
         }

@@ -13,6 +13,7 @@
 // output is written by exactly one lane: deterministic, no atomics. FP64 in an FP64 context; in an
 // FP32C context the far pairs in FP32 (cascaded into FP64) and the near pairs in FP64.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "dbie_solver.h"
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                                                const double* __restrict__ coef, double* __restrict__ gW,
                                                int64_t slice_stride) {
     __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef][kVjpPts];
+    __shared__ int s_wide;
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
     const int32_t ngrid = bd.gcols * bd.grows;
@@ -71,12 +73,20 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
     for (int64_t i0 = p0; i0 < p1; i0 += kVjpPts) {
         const int n = (int)min<int64_t>(kVjpPts, p1 - i0);
         __syncthreads();
+        if (threadIdx.x == 0) s_wide = 0;
+        __syncthreads();
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const int64_t i = i0 + q;
-            su[q] = geo.u[i];
-            sv[q] = geo.v[i];
-            const double w = geo.w[i];
+            const double u = geo.u[i], v = geo.v[i], w = geo.w[i];
+            su[q] = u;
+            sv[q] = v;
             sw2[q] = w * w;
+            // the largest |lambda r| of this point over the grid (positions in [0, nx-1] x [0, ny-1])
+            // selects the sin/cos of the chunk: the branch-free reduced form or the library's
+            const double dxm = fmax(fabs(u), fabs((double)(bd.nx - 1) - u));
+            const double dym = fmax(fabs(v), fabs((double)(bd.ny - 1) - v));
+            const double lmax = fmax(fabs(coef[i]), fmax(fabs(coef[N + i]), fabs(coef[2 * N + i])));
+            if (!(lmax * sqrt(dxm * dxm + dym * dym + w * w) < kSincosBound)) s_wide = 1;
         }
         for (int q = threadIdx.x; q < kVjpCoef * n; q += blockDim.x) {
             const int r = q / n, e = q - r * n;
@@ -84,25 +94,33 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
         }
         __syncthreads();
         double part[3] = {0.0, 0.0, 0.0};
-        for (int e = 0; e < n; ++e) {
-            const double dx = a - su[e], dy = bb - sv[e];
-            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, sw2[e]));
-            const double ri = rsqrt(r2);
-            const double r = r2 * ri;
-            const double ri2 = ri * ri;
-            const double ri3 = ri2 * ri;
-            const double ri5 = ri3 * ri2;
+        // the chunk's pairs, with the library's sin/cos (WIDE) or the branch-free reduced form
+        auto chunk = [&](auto wide_tag) {
+            constexpr bool WIDE = decltype(wide_tag)::value;
+            for (int e = 0; e < n; ++e) {
+                const double dx = a - su[e], dy = bb - sv[e];
+                const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, sw2[e]));
+                const double ri = rsqrt(r2);
+                const double r = r2 * ri;
+                const double ri2 = ri * ri;
+                const double ri3 = ri2 * ri;
+                const double ri5 = ri3 * ri2;
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                const double t = sc[p][e] * r;
-                double s, c;
-                sincos(t, &s, &c);
-                const double nn = __builtin_fma(t, s, c);
-                const double hh = __builtin_fma(t, t * c, -3.0 * nn);
-                const double lin = __builtin_fma(sc[9 + p][e], dx, __builtin_fma(sc[12 + p][e], dy, sc[6 + p][e]));
-                part[p] = __builtin_fma(nn * ri3, sc[3 + p][e], __builtin_fma(hh * ri5, lin, part[p]));
+                for (int p = 0; p < 3; ++p) {
+                    const double t = sc[p][e] * r;
+                    double s, c;
+                    if (WIDE) sincos(t, &s, &c);
+                    else sincos_reduced(t, &s, &c);
+                    const double nn = __builtin_fma(t, s, c);
+                    const double hh = __builtin_fma(t, t * c, -3.0 * nn);
+                    const double lin =
+                        __builtin_fma(sc[9 + p][e], dx, __builtin_fma(sc[12 + p][e], dy, sc[6 + p][e]));
+                    part[p] = __builtin_fma(nn * ri3, sc[3 + p][e], __builtin_fma(hh * ri5, lin, part[p]));
+                }
             }
-        }
+        };
+        if (s_wide != 0) chunk(std::true_type{});
+        else chunk(std::false_type{});
         for (int p = 0; p < 3; ++p) acc[p] += part[p];
     }
     if (live) {
