@@ -76,34 +76,35 @@ struct Geo {
     int32_t* bidx;
 };
 
-// sin and cos of t for |t| < kSincosBound, to about one ulp, without branches: t = k pi/2 + r with
-// k = rint(2t/pi) and r from a two-constant Cody-Waite reduction (with FMA the first step is exact
-// for |k| < 2^20, the second leaves ~1e-27), polynomials on [-pi/4, pi/4] fitted by least squares on
-// Chebyshev nodes in 50-digit arithmetic (sin r = r + r^3 P(r^2), cos r = 1 - r^2/2 + r^4 Q(r^2),
-// both of degree 5; fit errors below 2e-17 with the coefficients rounded to double), and the
-// quadrant k mod 4 applied by selects. Larger arguments take the device library's sincos.
+// sin and cos of t for |t| < kSincosBound, to about one ulp, without branches: t = k pi + r with
+// k = rint(t/pi), |r| <= pi/2, r from a two-constant Cody-Waite reduction (with FMA the first step is
+// exact for |k| < 2^20, the second leaves ~1e-27), and polynomials on [-pi/2, pi/2] fitted by least
+// squares on Chebyshev nodes in 50-digit arithmetic (sin r = r + r^3 P(r^2), P of degree 7;
+// cos r = 1 - r^2/2 + r^4 Q(r^2), Q of degree 6; fit errors below 2e-17 with the coefficients
+// rounded to double). Returns sin r, cos r and the parity of k: sin t = (-1)^k sin r and
+// cos t = (-1)^k cos r, so the callers apply the common sign to what multiplies them.
 constexpr double kSincosBound = 524288.0;   // 2^19
-__device__ __forceinline__ void sincos_reduced(double t, double* s, double* c) {
-    const double k = __builtin_rint(t * 0.6366197723675814);
-    double r = __builtin_fma(-k, 1.5707963267948966, t);
-    r = __builtin_fma(-k, 6.123233995736766e-17, r);
+__device__ __forceinline__ int sincos_halfturn(double t, double* s, double* c) {
+    const double k = __builtin_rint(t * 0.3183098861837907);
+    double r = __builtin_fma(-k, 3.141592653589793, t);
+    r = __builtin_fma(-k, 1.2246467991473532e-16, r);
     const double z = r * r;
-    double p = __builtin_fma(z, 1.5896542207786722e-10, -2.5050753161004457e-08);
-    p = __builtin_fma(z, p, 2.7557313655329285e-06);
-    p = __builtin_fma(z, p, -0.00019841269829682216);
-    p = __builtin_fma(z, p, 0.008333333333322219);
-    p = __builtin_fma(z, p, -0.1666666666666663);
-    const double sr = __builtin_fma(r * z, p, r);
-    double q = __builtin_fma(z, -1.135923037716418e-11, 2.0875714493184434e-09);
-    q = __builtin_fma(z, q, -2.7557314281167143e-07);
-    q = __builtin_fma(z, q, 2.4801587289206567e-05);
-    q = __builtin_fma(z, q, -0.001388888888887362);
-    q = __builtin_fma(z, q, 0.041666666666666595);
-    const double cr = __builtin_fma(z * z, q, __builtin_fma(z, -0.5, 1.0));
-    const int qd = (int)k;
-    const double a = (qd & 1) ? cr : sr, b = (qd & 1) ? sr : cr;
-    *s = (qd & 2) ? -a : a;
-    *c = ((qd + 1) & 2) ? -b : b;
+    double p = __builtin_fma(z, 2.7221623441283363e-15, -7.64308811092882e-13);
+    p = __builtin_fma(z, p, 1.6058943534108974e-10);
+    p = __builtin_fma(z, p, -2.5052106951355734e-08);
+    p = __builtin_fma(z, p, 2.7557319212021904e-06);
+    p = __builtin_fma(z, p, -0.00019841269841214533);
+    p = __builtin_fma(z, p, 0.00833333333333321);
+    p = __builtin_fma(z, p, -0.16666666666666666);
+    *s = __builtin_fma(r * z, p, r);
+    double q = __builtin_fma(z, 4.615589456771727e-14, -1.1463582501750082e-11);
+    q = __builtin_fma(z, q, 2.0876590527674145e-09);
+    q = __builtin_fma(z, q, -2.755731702734344e-07);
+    q = __builtin_fma(z, q, 2.4801587285345367e-05);
+    q = __builtin_fma(z, q, -0.0013888888888827712);
+    q = __builtin_fma(z, q, 0.04166666666666578);
+    *c = __builtin_fma(z * z, q, __builtin_fma(z, -0.5, 1.0));
+    return (int)k & 1;
 }
 
 // One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
@@ -123,19 +124,19 @@ __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const double t = lam[p] * r;
-        double s, c;
+        double s, c, bp = b0[p];
         if (WIDE) sincos(t, &s, &c);
-        else sincos_reduced(t, &s, &c);
+        else if (sincos_halfturn(t, &s, &c)) bp = -bp;   // (-1)^k carried by B0
         const double n = __builtin_fma(t, s, c);
         const double hh = __builtin_fma(t, t * c, -3.0 * n);
-        const double nb = n * (ri3 * b0[p]);
-        const double hb = hh * (ri5 * b0[p]);
+        const double nb = n * (ri3 * bp);
+        const double hb = hh * (ri5 * bp);
         acc[4 * p + 0] += nb;
         acc[4 * p + 1] = __builtin_fma(hb, dx, acc[4 * p + 1]);
         acc[4 * p + 2] = __builtin_fma(hb, dy, acc[4 * p + 2]);
         acc[4 * p + 3] += hb;
         if (TAN) {
-            acc[12 + 3 * p + 0] = __builtin_fma(c * ri, b0[p], acc[12 + 3 * p + 0]);
+            acc[12 + 3 * p + 0] = __builtin_fma(c * ri, bp, acc[12 + 3 * p + 0]);
             acc[12 + 3 * p + 1] = __builtin_fma(nb, dx, acc[12 + 3 * p + 1]);
             acc[12 + 3 * p + 2] = __builtin_fma(nb, dy, acc[12 + 3 * p + 2]);
         }

@@ -109,8 +109,12 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                 for (int p = 0; p < 3; ++p) {
                     const double t = sc[p][e] * r;
                     double s, c;
-                    if (WIDE) sincos(t, &s, &c);
-                    else sincos_reduced(t, &s, &c);
+                    if (WIDE) {
+                        sincos(t, &s, &c);
+                    } else if (sincos_halfturn(t, &s, &c)) {   // t = k pi + r with k odd
+                        s = -s;
+                        c = -c;
+                    }
                     const double nn = __builtin_fma(t, s, c);
                     const double hh = __builtin_fma(t, t * c, -3.0 * nn);
                     const double lin =

@@ -1,4 +1,4 @@
-"""The branch-free FP64 sin/cos of the FP64 kernels (sincos_reduced in dbie_internal.h), checked on
+"""The branch-free FP64 sin/cos of the FP64 kernels (sincos_halfturn in dbie_internal.h), checked on
 the CPU: its constants are read from the source, every step is emulated in double precision with
 single-rounded FMAs (exact rational arithmetic, then one rounding), and the results are compared
 with 40-digit mpmath over random and adversarial arguments (near multiples of pi/2, zeros,
@@ -16,8 +16,8 @@ SRC = os.path.join(os.path.dirname(__file__), "..", "paper_1306_1122_amd", "csrc
 
 def _body():
     src = open(SRC).read()
-    m = re.search(r"void sincos_reduced\(double t, double\* s, double\* c\) \{(.*?)\n\}", src, re.S)
-    assert m, "sincos_reduced not found"
+    m = re.search(r"int sincos_halfturn\(double t, double\* s, double\* c\) \{(.*?)\n\}", src, re.S)
+    assert m, "sincos_halfturn not found"
     return m.group(1), src
 
 
@@ -28,24 +28,25 @@ def _fma(a, b, c):
 def _constants():
     body, src = _body()
     num = r"(-?[0-9.]+(?:e-?[0-9]+)?)"
-    k2pi = float(re.search(r"__builtin_rint\(t \* " + num + r"\)", body).group(1))
-    pio2 = [float(x) for x in re.findall(r"__builtin_fma\(-k, " + num + r", ", body)]
+    k1pi = float(re.search(r"__builtin_rint\(t \* " + num + r"\)", body).group(1))
+    pi_parts = [float(x) for x in re.findall(r"__builtin_fma\(-k, " + num + r", ", body)]
     p = re.findall(r"double p = __builtin_fma\(z, " + num + r", " + num + r"\)", body)[0]
     ps = [float(x) for x in re.findall(r"p = __builtin_fma\(z, p, " + num + r"\)", body)]
     q = re.findall(r"double q = __builtin_fma\(z, " + num + r", " + num + r"\)", body)[0]
     qs = [float(x) for x in re.findall(r"q = __builtin_fma\(z, q, " + num + r"\)", body)]
     bound = float(re.search(r"kSincosBound = " + num + ";", src).group(1))
     # highest degree first, as the Horner steps of the source
-    return k2pi, pio2, [float(p[0]), float(p[1])] + ps, [float(q[0]), float(q[1])] + qs, bound
+    return k1pi, pi_parts, [float(p[0]), float(p[1])] + ps, [float(q[0]), float(q[1])] + qs, bound
 
 
-K2PI, PIO2, PC, QC, BOUND = _constants()
+K1PI, PI_PARTS, PC, QC, BOUND = _constants()
 
 
-def sincos_reduced(t):
-    k = float(round(t * K2PI))          # rint, ties to even
-    r = _fma(-k, PIO2[0], t)
-    r = _fma(-k, PIO2[1], r)
+def sincos_halfturn(t):
+    """(sin t, cos t) from the device steps: sin r, cos r and the parity of k, t = k pi + r."""
+    k = float(round(t * K1PI))          # rint, ties to even
+    r = _fma(-k, PI_PARTS[0], t)
+    r = _fma(-k, PI_PARTS[1], r)
     z = r * r
     p = _fma(z, PC[0], PC[1])
     for cf in PC[2:]:
@@ -55,16 +56,14 @@ def sincos_reduced(t):
     for cf in QC[2:]:
         q = _fma(z, q, cf)
     cr = _fma(z * z, q, _fma(z, -0.5, 1.0))
-    qd = int(k)
-    a, b = (cr, sr) if qd & 1 else (sr, cr)
-    return (-a if qd & 2 else a), (-b if (qd + 1) & 2 else b)
+    return (-sr, -cr) if int(k) & 1 else (sr, cr)
 
 
 def test_constants_parsed():
-    assert len(PIO2) == 2 and len(PC) == 6 and len(QC) == 6
+    assert len(PI_PARTS) == 2 and len(PC) == 8 and len(QC) == 7
     assert BOUND == 2.0 ** 19
     mp.mp.dps = 40
-    assert abs(mp.mpf(PIO2[0]) + mp.mpf(PIO2[1]) - mp.pi / 2) < 1e-32
+    assert abs(mp.mpf(PI_PARTS[0]) + mp.mpf(PI_PARTS[1]) - mp.pi) < 1e-32
 
 
 @pytest.mark.parametrize("seed", [1, 2])
@@ -73,10 +72,12 @@ def test_within_one_ulp_of_40_digit_values(seed):
     rng = random.Random(seed)
     ts = [rng.uniform(-BOUND, BOUND) for _ in range(700)] + [rng.uniform(-8.0, 8.0) for _ in range(500)]
     ts += [float(mp.pi * k / 2) + d for k in range(-300000, 300001, 29989) for d in (0.0, 3e-13, -2e-9)]
-    ts += [0.0, -0.0, 1e-300, -5e-324, 0.7853981633974483, -0.7853981633974484, BOUND * 0.999999, -BOUND * 0.999999]
+    ts += [float(mp.pi * (k + mp.mpf(1) / 2)) + d for k in range(-150000, 150001, 14999) for d in (0.0, 1e-10)]
+    ts += [0.0, -0.0, 1e-300, -5e-324, 1.5707963267948966, -1.5707963267948968, 3.141592653589793,
+           BOUND * 0.999999, -BOUND * 0.999999]
     worst = 0.0
     for t in ts:
-        s, c = sincos_reduced(t)
+        s, c = sincos_halfturn(t)
         es, ec = abs(s - float(mp.sin(t))), abs(c - float(mp.cos(t)))
         worst = max(worst, es, ec)
         assert es <= 2.3e-16 and ec <= 2.3e-16, (t, es, ec)
