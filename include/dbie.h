@@ -106,7 +106,7 @@ typedef struct {
                                   * nodes 2m..2m+2 x 2n..2n+2). With DBIE_FP32C the elements
                                   * that come closer than nearfield_radius_h * h to a point (3 x 3
                                   * element window) are summed in FP64, every other pair in FP32. */
-    int32_t pixel_split;         /* FP32C: pixel slices per launch (grid z), each summing an even share of
+    int32_t pixel_split;         /* pixel slices per launch (grid z), each summing an even share of
                                   * the magnetogram's blocks into its own partial, added in order by the
                                   * finalize pass. 0 = automatic (about four workgroups per compute
                                   * unit when the point tiles alone are fewer, else 1), 1..32 fixed.
@@ -120,7 +120,9 @@ typedef struct {
     double eps;           /* convergence: max(f, g) <= eps (Eq. 12) */
     double init_step;     /* simplex edge (Nelder-Mead); <= 0 means 1 / (longer side of the magnetogram) */
     double lambda_cap;    /* |lambda| <= cap; <= 0 means pi / h */
-    int32_t fp64_accept;  /* FP32C contexts: re-evaluate the result in FP64 and set status from it */
+    int32_t fp64_accept;  /* FP32C contexts: re-evaluate the result in FP64 and set status from it
+                             (with B and fg both NULL only the points that converged are re-evaluated,
+                             and those that fail the FP64 test become DBIE_ST_BUDGET) */
     int32_t use_graph;    /* 1: replay the rounds from a captured HIP graph (bitwise the same results) */
 } dbie_solve_opts;
 
@@ -193,12 +195,14 @@ DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int3
                                  int32_t persistent);
 
 /* Solve tracing (time to solution): with enable != 0, dbie_solve_lambda records a HIP event on its
- * stream at the start and after every round. dbie_solve_trace_read synchronises and returns, for
- * the last solve, the elapsed milliseconds at the end of each round (t_ms) and the number of points
- * that converged in each round (converged), for up to max_rounds rounds; *n_rounds = rounds run. */
+ * stream at the start, after every round and at its end (after the FP64 acceptance pass).
+ * dbie_solve_trace_read synchronises and returns, for the last solve, the elapsed milliseconds at
+ * the end of each round (t_ms) and the number of points that converged in each round (converged),
+ * for up to max_rounds rounds; *n_rounds = rounds run; *t_end_ms = elapsed milliseconds at the end
+ * of the call. Any output pointer may be NULL. */
 DBIE_API int dbie_solve_trace(dbie_ctx* ctx, int32_t enable);
 DBIE_API int dbie_solve_trace_read(dbie_ctx* ctx, double* t_ms, int32_t* converged, int32_t max_rounds,
-                                   int32_t* n_rounds);
+                                   int32_t* n_rounds, double* t_end_ms);
 
 /* Sizes the context was built with: n_points, total pixels, FP32C tile shape (points per lane,
  * waves per workgroup, pixels per LDS tile) as chosen by defaults or the tuner. Any pointer may be
@@ -216,7 +220,7 @@ DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t*
  * Wavefront shuffles and a fixed-order block sum: deterministic. Synchronises `stream`. */
 DBIE_API int dbie_residual_stats(dbie_ctx* ctx, const double* fg, double eps, double* out, void* stream);
 
-/* Pixel slices per FP32C launch (dbie_options.pixel_split, or the automatic choice); 1 for FP64. */
+/* Pixel slices per launch of the bulk sum (dbie_options.pixel_split, or the automatic choice). */
 DBIE_API int dbie_query_split(const dbie_ctx* ctx, int32_t* slices);
 
 /* Caller-owned work memory (no operation of the paper: device-memory plumbing for callers that manage

@@ -67,7 +67,7 @@ SIGNATURES = {
     "dbie_trace_lines": (c_int32, [c_void_p, POINTER(dbie_lambda_grid), POINTER(c_double), c_double, c_int32,
                                    c_int32, c_double, c_void_p, c_void_p, c_void_p]),
     "dbie_solve_trace_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32,
-                                        POINTER(c_int32)]),
+                                        POINTER(c_int32), POINTER(c_double)]),
     "dbie_destroy": (None, [c_void_p]),
     "dbie_last_error": (c_char_p, [c_void_p]),
 }

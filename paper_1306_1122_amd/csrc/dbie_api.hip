@@ -105,7 +105,8 @@ struct dbie_ctx {
     void* scratch[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t scratch_bytes[4] = {0, 0, 0, 0};
     bool trace = false;
-    std::vector<hipEvent_t> trace_ev;
+    std::vector<hipEvent_t> trace_ev;   // solve tracing: start, then one per round
+    hipEvent_t trace_end = nullptr;     // end of the traced solve
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -189,6 +190,7 @@ void free_ctx(dbie_ctx* c) {
     solver_free(c->solver);
     for (int k = 0; k < 4; ++k) (void)hipFree(c->scratch[k]);
     for (auto e : c->trace_ev) (void)hipEventDestroy(e);
+    if (c->trace_end) (void)hipEventDestroy(c->trace_end);
     for (auto& p : c->ev) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
@@ -264,7 +266,7 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const int32_t* idx = set ? set->idx : nullptr;
     if (fp64)
         DBIE_HIP(c, launch_field64(set ? set->tiles64 : c->tiles64, set ? set->n_tiles64 : c->n_tiles64,
-                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, idx, tan, c->acc, s));
+                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, c->split, idx, tan, c->acc, s));
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
@@ -277,7 +279,7 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
     DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, idx, c->N,
                                 set ? set->n_dev : nullptr, c->N,
-                                L, fp64 ? 1 : c->split, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
+                                L, c->split, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
     return DBIE_OK;
 }
 
@@ -321,6 +323,7 @@ NearLists ctx_near_lists(const dbie_ctx* c) {
 }
 bool ctx_timing(const dbie_ctx* c) { return c->timing; }
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
+hipEvent_t& solver_trace_end(dbie_ctx* c) { return c->trace_end; }
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
 VjpTables ctx_vjp_tables(const dbie_ctx* c) { return c->vjp; }
@@ -585,6 +588,15 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
         DBIE_INIT_HIP(dalloc(&c->tiles64, t.size()));
         DBIE_INIT_HIP(hipMemcpy(c->tiles64, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
         c->n_tiles64 = (int64_t)t.size();
+        if (o.precision == DBIE_FP64) {
+            // pixel slices of the FP64 pass, as for FP32C: about four workgroups per compute unit
+            int64_t busy = 0;
+            for (const Tile& x : t) busy += x.count > 0;
+            c->split = o.pixel_split > 0 ? o.pixel_split
+                                         : (int32_t)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1,
+                                               (4 * (int64_t)c->cus + std::max<int64_t>(busy, 1) - 1) /
+                                                   std::max<int64_t>(busy, 1)));
+        }
     }
     DBIE_INIT_HIP(vjp_tables_init(c, &c->vjp_dev, &c->vjp));
     if (o.precision == DBIE_FP32C) {
@@ -779,10 +791,17 @@ int dbie_solve_trace(dbie_ctx* c, int32_t enable) {
 }
 
 int dbie_solve_trace_read(dbie_ctx* c, double* t_ms, int32_t* converged, int32_t max_rounds,
-                          int32_t* n_rounds) {
+                          int32_t* n_rounds, double* t_end_ms) {
     if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
     const int32_t n = (int32_t)c->trace_ev.size() - 1;   // the first event marks the start
     if (n_rounds) *n_rounds = std::max(n, 0);
+    if (t_end_ms) *t_end_ms = 0.0;
+    if (t_end_ms && c->trace_end && !c->trace_ev.empty()) {
+        DBIE_HIP(c, hipEventSynchronize(c->trace_end));
+        float ms = 0.0f;
+        DBIE_HIP(c, hipEventElapsedTime(&ms, c->trace_ev[0], c->trace_end));
+        *t_end_ms = ms;
+    }
     if (n <= 0) return DBIE_OK;
     DBIE_HIP(c, hipEventSynchronize(c->trace_ev.back()));
     const int32_t m = std::min(n, max_rounds);
@@ -874,7 +893,7 @@ int dbie_residual_stats(dbie_ctx* c, const double* fg, double eps, double* out, 
 
 int dbie_query_split(const dbie_ctx* c, int32_t* slices) {
     if (!c) return DBIE_E_INVAL;
-    if (slices) *slices = c->opt.precision == DBIE_FP32C ? c->split : 1;
+    if (slices) *slices = c->split;
     return DBIE_OK;
 }
 

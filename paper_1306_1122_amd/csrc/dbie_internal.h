@@ -238,7 +238,7 @@ hipError_t launch_expand_scalar(const double* lam, int32_t L, int64_t N, double*
 // with `idx` it is a run of entries of the active-point list idx (device schedules of the solver).
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                           const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
-                          int32_t L, const int32_t* idx, bool tan, double* acc, hipStream_t s);
+                          int32_t L, int32_t S, const int32_t* idx, bool tan, double* acc, hipStream_t s);
 
 // The weighted field of the 9-node element quadrature grid: gB = w_g w_q sum L_a(xi_g) L_b(xi_q) B0
 // (lw[3 * g + a] = w_g L_a(xi_g), G points per element side).

@@ -118,6 +118,7 @@ NearLists ctx_near_lists(const dbie_ctx* c);
 bool solver_tracing(const dbie_ctx* c);
 bool ctx_timing(const dbie_ctx* c);
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c);
+hipEvent_t& solver_trace_end(dbie_ctx* c);   // recorded at the end of a traced solve
 // FP32C tile shapes: one for the plain field pass and one for the pass with mu-tangents.
 int set_shape(dbie_ctx* c, F32Shape s, bool tan);
 F32Shape get_shape(const dbie_ctx* c, bool tan);

@@ -5,9 +5,11 @@
 // Grid: one workgroup per schedule tile (a run of <= tile points of one magnetogram) and one
 // grid row per lambda trial. Each lane owns one point; the magnetogram streams through LDS in
 // tiles of kTP64 pixels that all lanes read at the same address (LDS broadcast). Sums are cascaded:
-// a per-tile partial in FP64, then added to the running FP64 total. sin and cos come from the
-// branch-free reduced form unless some pair of the workgroup's points can exceed its argument
-// bound (then, and for NaN lambda, from the device library).
+// a per-tile partial in FP64, then added to the running FP64 total. Grid z splits the pixel tiles
+// into slices (few points: late solver rounds, the acceptance of converged points, field-line seeds),
+// each writing its own partial ([S][L][kAcc][N], added in order by the finalize pass). sin and cos
+// come from the branch-free reduced form unless some pair of the workgroup's points can exceed its
+// argument bound (then, and for NaN lambda, from the device library).
 #include "dbie_internal.h"
 
 namespace dbie {
@@ -60,7 +62,11 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
         double tot[NA];
 #pragma unroll
         for (int r = 0; r < NA; ++r) tot[r] = 0.0;
-        for (int k0 = 0; k0 < npix; k0 += kTP64) {
+        // pixel slice blockIdx.z of gridDim.z: an even share of the pixel tiles
+        const int ntile = (npix + kTP64 - 1) / kTP64;
+        const int kt0 = (int)((int64_t)blockIdx.z * ntile / gridDim.z);
+        const int kt1 = (int)((int64_t)(blockIdx.z + 1) * ntile / gridDim.z);
+        for (int k0 = kt0 * kTP64; k0 < min(npix, kt1 * kTP64); k0 += kTP64) {
             const int kn = min(kTP64, npix - k0);
             __syncthreads();
             for (int k = threadIdx.x; k < kn; k += blockDim.x) {
@@ -86,16 +92,17 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
         }
         if (live) {
 #pragma unroll
-            for (int r = 0; r < NA; ++r) acc[((int64_t)trial * kAcc + r) * N + i] = tot[r];
+            for (int r = 0; r < NA; ++r)
+                acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + i] = tot[r];
         }
     }
 }
 
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                           const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
-                          int32_t L, const int32_t* idx, bool tan, double* acc, hipStream_t s) {
+                          int32_t L, int32_t S, const int32_t* idx, bool tan, double* acc, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
-    const dim3 grid((unsigned)n_tiles, (unsigned)L);
+    const dim3 grid((unsigned)n_tiles, (unsigned)L, (unsigned)S);
     if (tan)
         hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx, acc);
     else

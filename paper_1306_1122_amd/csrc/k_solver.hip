@@ -628,6 +628,20 @@ __global__ void k_solve_accept(int64_t N, const double* __restrict__ fg, double 
     st[i] = (rho <= eps) ? kStConverged : kStBudget;
 }
 
+// FP64 confirmation of the points that converged in FP32C (re-evaluated alone): CONVERGED stays only
+// if max(f, g) <= eps in FP64; fg holds values for those points only.
+__global__ void k_solve_confirm(int64_t N, const double* __restrict__ fg, double eps, int32_t* __restrict__ st) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || st[i] != kStConverged) return;
+    if (!(fmax(fg[i], fg[N + i]) <= eps)) st[i] = kStBudget;
+}
+
+// active[i] = (status[i] == CONVERGED): the list the FP64 confirmation evaluates.
+__global__ void k_mark_converged(int64_t N, const int32_t* __restrict__ st, int32_t* __restrict__ active) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) active[i] = st[i] == kStConverged ? 1 : 0;
+}
+
 // The round counter read by the update kernels (a device word, so that captured rounds replay).
 __global__ void k_round_next(int32_t* __restrict__ round) { *round += 1; }
 
@@ -873,6 +887,9 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     std::vector<hipEvent_t>& trace = solver_trace_events(c);
     for (auto e : trace) (void)hipEventDestroy(e);
     trace.clear();
+    hipEvent_t& trace_end = solver_trace_end(c);
+    if (trace_end) (void)hipEventDestroy(trace_end);
+    trace_end = nullptr;
     const bool tracing = solver_tracing(c);
     if (tracing) {
         hipEvent_t e = nullptr;
@@ -970,7 +987,17 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     hipLaunchKernelGGL(k_solve_finish, dim3(gN), dim3(256), 0, s, N, b.C, lam, status, trials);
     SOLVE_HIP(hipGetLastError());
     const bool accept64 = !fp64 && opt->fp64_accept;
-    if (Bout || fgout || accept64) {
+    if (accept64 && !Bout && !fgout) {
+        // only the points that converged in FP32C need the FP64 test: compact them and evaluate
+        // those alone
+        hipLaunchKernelGGL(k_mark_converged, dim3(gN), dim3(256), 0, s, N, status, b.C.active);
+        SOLVE_HIP(hipGetLastError());
+        SOLVE_HIP(compact(b, perm, N, nb, per32, s));
+        rc = eval_set(c, lam, true, false, &set, b.C.Bw, b.C.dBw, b.C.fgw, nullptr, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_solve_confirm, dim3(gN), dim3(256), 0, s, N, b.C.fgw, opt->eps, status);
+        SOLVE_HIP(hipGetLastError());
+    } else if (Bout || fgout || accept64) {
         double* Bdst = Bout ? Bout : b.C.Bw;
         double* fgdst = fgout ? fgout : b.C.fgw;
         rc = eval_set(c, lam, fp64 || accept64, false, nullptr, Bdst, b.C.dBw, fgdst, nullptr, s);
@@ -979,6 +1006,10 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
             hipLaunchKernelGGL(k_solve_accept, dim3(gN), dim3(256), 0, s, N, fgdst, opt->eps, status);
             SOLVE_HIP(hipGetLastError());
         }
+    }
+    if (tracing) {
+        SOLVE_HIP(hipEventCreate(&trace_end));
+        SOLVE_HIP(hipEventRecord(trace_end, s));
     }
     return DBIE_OK;
 #undef SOLVE_HIP

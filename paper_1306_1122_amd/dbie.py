@@ -324,17 +324,21 @@ def dbie_solve_trace(ctx: Context, enable: bool = True):
     _check(_lib().dbie_solve_trace(ctx.handle, int(bool(enable))), ctx, "dbie_solve_trace")
 
 
-def dbie_solve_trace_read(ctx: Context, max_rounds: int = 100000):
-    """Returns (t_ms [rounds], converged [rounds]) of the last traced solve."""
+def dbie_solve_trace_read(ctx: Context, max_rounds: int = 100000, with_end: bool = False):
+    """Returns (t_ms [rounds], converged [rounds]) of the last traced solve, and with with_end the
+    elapsed milliseconds at the end of the call as a third item."""
     import numpy as np
     n = ctypes.c_int32()
-    _check(_lib().dbie_solve_trace_read(ctx.handle, None, None, 0, ctypes.byref(n)), ctx,
+    _check(_lib().dbie_solve_trace_read(ctx.handle, None, None, 0, ctypes.byref(n), None), ctx,
            "dbie_solve_trace_read")
     m = min(n.value, max_rounds)
     t = (ctypes.c_double * max(m, 1))()
     cv = (ctypes.c_int32 * max(m, 1))()
-    _check(_lib().dbie_solve_trace_read(ctx.handle, t, cv, m, ctypes.byref(n)), ctx, "dbie_solve_trace_read")
-    return np.array(t[:m]), np.array(cv[:m], dtype=np.int64)
+    te = ctypes.c_double()
+    _check(_lib().dbie_solve_trace_read(ctx.handle, t, cv, m, ctypes.byref(n), ctypes.byref(te)), ctx,
+           "dbie_solve_trace_read")
+    out = (np.array(t[:m]), np.array(cv[:m], dtype=np.int64))
+    return out + (te.value,) if with_end else out
 
 
 def dbie_trace_lines(ctx: Context, lam_grid: torch.Tensor, origin, spacing, box, ds: float, n_steps: int,

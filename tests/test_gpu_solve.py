@@ -103,6 +103,33 @@ def test_fp32c_lm_with_fp64_acceptance():
 
 
 @pytest.mark.parametrize("method", ["nm", "lm"])
+def test_fp64_confirmation_of_converged_points_only(method):
+    """With no B or fg requested, the FP64 acceptance re-evaluates only the points that converged in
+    FP32C: the same lambda and trials as the full acceptance, CONVERGED exactly where the full pass
+    has a point that converged in FP32C and passes in FP64, and every CONVERGED point passes the
+    oracle's FP64 test."""
+    w, bd, ctx = lowlou_ctx("fp32c")
+    N = w.n_points
+    z = lambda: torch.zeros(3, N, dtype=torch.float64, device="cuda:0")  # noqa: E731
+    eps = 0.05
+    full = D.dbie_solve_lambda(ctx, z(), method=method, max_trials=30, eps=eps, fp64_accept=True)
+    part = D.dbie_solve_lambda(ctx, z(), method=method, max_trials=30, eps=eps, fp64_accept=True,
+                               want_B=False, want_fg=False)
+    raw = D.dbie_solve_lambda(ctx, z(), method=method, max_trials=30, eps=eps, fp64_accept=False,
+                              want_B=False, want_fg=False)
+    torch.cuda.synchronize()
+    assert torch.equal(full["lam"], part["lam"]) and torch.equal(full["trials"], part["trials"])
+    st_full, st_part, st_raw = (r["status"].cpu().numpy() for r in (full, part, raw))
+    expect = (st_raw == oracle.ST_CONVERGED) & (st_full == oracle.ST_CONVERGED)
+    assert np.array_equal(st_part == oracle.ST_CONVERGED, expect)
+    lg = part["lam"].cpu().numpy()
+    conv = np.nonzero(st_part == oracle.ST_CONVERGED)[0]
+    assert conv.size > 0
+    Bo, dBo = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, conv], lg[:, conv])
+    assert np.all(oracle.residuals(Bo, dBo, bd.h)["rho"] <= eps * (1 + 1e-6))
+
+
+@pytest.mark.parametrize("method", ["nm", "lm"])
 def test_solve_is_deterministic_and_batched_equals_single(method):
     rng = np.random.default_rng(21)
     bds, xyzs, seg = [], [], [0]
@@ -216,3 +243,22 @@ def test_residual_statistics_on_the_device():
     e = D.dbie_eval_field(ctx, bad)
     s2 = D.dbie_residual_stats(ctx, e["fg"], eps=1e-4)
     assert s2["finite"] == n - 1
+
+
+def test_solve_trace_reports_rounds_and_the_end():
+    """Solve tracing: round times increase, the per-round convergence counts add up to the points
+    that converged in the search, the end of the call comes after the last round, and a traced
+    solve returns what an untraced one does."""
+    w, bd, ctx = lowlou_ctx("fp32c")
+    N = w.n_points
+    z = lambda: torch.zeros(3, N, dtype=torch.float64, device="cuda:0")  # noqa: E731
+    ref = D.dbie_solve_lambda(ctx, z(), method="lm", max_trials=12, eps=0.05, fp64_accept=False)
+    D.dbie_solve_trace(ctx, True)
+    r = D.dbie_solve_lambda(ctx, z(), method="lm", max_trials=12, eps=0.05, fp64_accept=False)
+    t, cv, t_end = D.dbie_solve_trace_read(ctx, with_end=True)
+    D.dbie_solve_trace(ctx, False)
+    for k in ("lam", "status", "trials"):
+        assert torch.equal(r[k], ref[k]), k
+    st = r["status"].cpu().numpy()
+    assert 1 <= len(t) <= 12 and np.all(np.diff(t) >= 0) and t_end >= t[-1] > 0
+    assert int(cv.sum()) == int(np.sum(st == oracle.ST_CONVERGED))
