@@ -322,17 +322,22 @@ def main():
               "(points would be sharded across GPUs with the magnetogram replicated).", file=sys.stderr)
         sys.exit(2)
 
+    from workloads import config2
+    w = config2()
+    # the CPU oracle's worker processes are forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_sample)
+
     import torch
     import paper_1306_1122_amd as D
     from paper_1306_1122_amd import _lib
-    from workloads import config2
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     _lib.load()   # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
-    w = config2()
     bd = w.boundaries[0]
     N = w.n_points
     pairs = w.pairs_per_trial()
@@ -406,10 +411,6 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_sample)
 
     line = {
         "metric": "boundary x volume kernel-pair evals/s per lambda trial",
