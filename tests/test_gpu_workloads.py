@@ -230,3 +230,34 @@ def test_fp32c_matches_fp64_on_every_point(which):
         print(which, k, "rel L2 %.2e, worst point %.2e, 99.9%% of points below %.2e" % (
             e, per.max(), np.quantile(per, 0.999)), flush=True)
         assert e <= 1e-5, (k, e)
+
+
+def test_benchmark_step_at_full_size():
+    """The benchmark's step as it runs there (tuned shapes, Levenberg-Marquardt with tangents, three
+    trials from the workload's lambda, no FP64 acceptance) on all 2^20 points: repeated calls give the
+    same trajectory bitwise, with and without B and (f, g) requested; at a z-stratified sample the
+    field and residuals at the returned lambda match the oracle's to the FP32C bar, and LM never
+    ends above its start by more than the FP32C-vs-FP64 difference."""
+    from workloads import z_stratified_subsample
+    w = config2()
+    bd = w.boundaries[0]
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision="fp32c", tune=True)
+    lam0 = T(w.lam)
+    a = D.dbie_solve_lambda(ctx, lam0.clone(), method="lm", max_trials=3, eps=1e-4, fp64_accept=False,
+                            want_B=False, want_fg=False)
+    b = D.dbie_solve_lambda(ctx, lam0.clone(), method="lm", max_trials=3, eps=1e-4, fp64_accept=False)
+    torch.cuda.synchronize()
+    for k in ("lam", "status", "trials"):
+        assert torch.equal(a[k], b[k]), k
+    tr = b["trials"].cpu().numpy()
+    assert tr.min() >= 1 and tr.max() <= 3
+    idx = z_stratified_subsample(w.xyz, 256, seed=61)
+    lg = b["lam"].cpu().numpy()[:, idx]
+    Bo, dBo = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], lg)
+    res = oracle.residuals(Bo, dBo, bd.h)
+    assert rel(b["B"][:, idx].cpu(), Bo) <= 1e-5
+    fg = b["fg"][:, idx].cpu().numpy()
+    assert rel(fg[0], res["f"]) <= 1e-4 and rel(fg[1], res["g"]) <= 1e-4
+    B0_, dB0_ = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], np.abs(w.lam[:, idx]))
+    phi0 = oracle.residuals(B0_, dB0_, bd.h)["Phi"]
+    assert np.mean(res["Phi"] <= phi0 * (1 + 1e-4) + 1e-12) >= 0.99
