@@ -144,8 +144,10 @@ def test_nearfield_radius_zero_is_plain_fp32():
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_several_boundaries_of_uneven_size(precision):
     rng = np.random.default_rng(5)
-    shapes = [(17, 23, 1.0, 0.0, 0.0), (64, 40, 0.5, -3.0, 2.0), (5, 9, 2.0, 1.0, -1.0)]
-    npts = [300, 1, 700]
+    # including the degenerate magnetograms: one pixel, one column, one row
+    shapes = [(17, 23, 1.0, 0.0, 0.0), (64, 40, 0.5, -3.0, 2.0), (5, 9, 2.0, 1.0, -1.0), (1, 1, 1.0, 4.0, 4.0),
+              (1, 13, 0.5, 0.0, 0.0), (11, 1, 1.0, -2.0, 0.0)]
+    npts = [300, 1, 700, 5, 40, 33]
 
     class Bd:
         pass
