@@ -229,8 +229,10 @@ int set_tiles32(dbie_ctx* c, F32Shape s, bool tan) {
 
 namespace dbie {
 
-int ensure_acc(dbie_ctx* c, int64_t L) {
-    const int64_t need = L * c->split;   // L trials x pixel slices
+int ensure_acc(dbie_ctx* c, int64_t L) { return ensure_acc_slices(c, L * c->split); }
+
+// room for `need` partial-sum slices of [kAcc][N] (trials x pixel slices)
+int ensure_acc_slices(dbie_ctx* c, int64_t need) {
     if (c->acc && c->acc_L >= need) return DBIE_OK;
     if (c->ws) {
         const size_t per = (size_t)kAcc * std::max<int64_t>(c->N, 1) * sizeof(double);
@@ -252,10 +254,24 @@ int ensure_acc(dbie_ctx* c, int64_t L) {
     return DBIE_OK;
 }
 
-// Bulk sum + finalize for L trials on the given lambda; the building block of every call.
+// Pixel slices for an evaluation of about n points: about four workgroups per compute unit, at
+// most kMaxSplit, and no more than the accumulator holds (a caller's workspace) or than 256 MB of
+// partial sums allow.
+int32_t split_for_points(dbie_ctx* c, int64_t n) {
+    const int64_t tiles = std::max<int64_t>(1, (n + 255) / 256);
+    int64_t S = std::min<int64_t>(kMaxSplit, (4 * (int64_t)c->cus + tiles - 1) / tiles);
+    const int64_t per = (int64_t)kAcc * std::max<int64_t>(c->N, 1) * (int64_t)sizeof(double);
+    const int64_t cap = c->ws ? (int64_t)c->ws_size[kWsAcc] / per : std::max<int64_t>(c->acc_L, (256ll << 20) / per);
+    return (int32_t)std::max<int64_t>(1, std::min(S, cap));
+}
+
+// Bulk sum + finalize for L trials on the given lambda; the building block of every call. S > 0
+// overrides the context's pixel slices.
 static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const EvalSet* set,
-                     double* B, double* dB, double* fg, double* tn, hipStream_t s, bool scalar = false) {
-    int rc = ensure_acc(c, L);
+                     double* B, double* dB, double* fg, double* tn, hipStream_t s, bool scalar = false,
+                     int32_t S = 0) {
+    if (S <= 0) S = c->split;
+    int rc = ensure_acc_slices(c, (int64_t)L * S);
     if (rc) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -266,11 +282,11 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const int32_t* idx = set ? set->idx : nullptr;
     if (fp64)
         DBIE_HIP(c, launch_field64(set ? set->tiles64 : c->tiles64, set ? set->n_tiles64 : c->n_tiles64,
-                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, c->split, idx, tan, c->acc, s));
+                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, S, idx, tan, c->acc, s));
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
-                                    c->pixf, c->gposf, c->geo, lam, c->N, L, c->split, set ? idx : c->perm, c->work, tan,
+                                    c->pixf, c->gposf, c->geo, lam, c->N, L, S, set ? idx : c->perm, c->work, tan,
                                     scalar, tan ? c->shape_tan : c->shape, c->acc, s));
     if (c->timing && e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
@@ -279,14 +295,14 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
     DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, idx, c->N,
                                 set ? set->n_dev : nullptr, c->N,
-                                L, c->split, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
+                                L, S, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
     return DBIE_OK;
 }
 
 int eval_set(dbie_ctx* c, const double* lam, bool fp64, bool tan, const EvalSet* set, double* B, double* dB,
-             double* fg, double* tn, hipStream_t s) {
+             double* fg, double* tn, hipStream_t s, int32_t S) {
     if (fp64 == false && !c->pixf) return fail(c, DBIE_E_UNSUPPORTED, "FP32C evaluation in an FP64 context");
-    return eval_core(c, lam, 1, fp64, tan, set, B, dB, fg, tn, s);
+    return eval_core(c, lam, 1, fp64, tan, set, B, dB, fg, tn, s, false, S);
 }
 
 const Geo& ctx_geo(const dbie_ctx* c) { return c->geo; }

@@ -50,12 +50,18 @@ struct EvalSet {
     int64_t n_tiles64;
 };
 
-// Make sure the accumulator workspace holds L trials (allocates; never called during capture).
+// Make sure the accumulator workspace holds L trials (allocates; never called during capture), or
+// `slices` partial-sum slices of [kAcc][N].
 int ensure_acc(dbie_ctx* c, int64_t L);
+int ensure_acc_slices(dbie_ctx* c, int64_t slices);
 
-// One lambda trial (L = 1) through the bulk kernel and the finalize pass.
+// Pixel slices for an evaluation of about n points (bounded by the accumulator memory).
+int32_t split_for_points(dbie_ctx* c, int64_t n);
+
+// One lambda trial (L = 1) through the bulk kernel and the finalize pass; S > 0 overrides the
+// context's pixel slices.
 int eval_set(dbie_ctx* c, const double* lam, bool fp64, bool tan, const EvalSet* set, double* B, double* dB,
-             double* fg, double* tn, hipStream_t s);
+             double* fg, double* tn, hipStream_t s, int32_t S = 0);
 
 // context accessors (defined in dbie_api.hip)
 const Geo& ctx_geo(const dbie_ctx* c);

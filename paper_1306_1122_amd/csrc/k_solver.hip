@@ -993,10 +993,17 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         hipLaunchKernelGGL(k_mark_converged, dim3(gN), dim3(256), 0, s, N, status, b.C.active);
         SOLVE_HIP(hipGetLastError());
         SOLVE_HIP(compact(b, perm, N, nb, per32, s));
-        rc = eval_set(c, lam, true, false, &set, b.C.Bw, b.C.dBw, b.C.fgw, nullptr, s);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_solve_confirm, dim3(gN), dim3(256), 0, s, N, b.C.fgw, opt->eps, status);
-        SOLVE_HIP(hipGetLastError());
+        // their number sizes the pixel slices (few points: many slices)
+        int32_t* cnt = ctx_solver(c).count_h;
+        SOLVE_HIP(hipMemcpyAsync(cnt, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SOLVE_HIP(hipStreamSynchronize(s));
+        if (*cnt > 0) {
+            rc = eval_set(c, lam, true, false, &set, b.C.Bw, b.C.dBw, b.C.fgw, nullptr, s,
+                          split_for_points(c, *cnt));
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_solve_confirm, dim3(gN), dim3(256), 0, s, N, b.C.fgw, opt->eps, status);
+            SOLVE_HIP(hipGetLastError());
+        }
     } else if (Bout || fgout || accept64) {
         double* Bdst = Bout ? Bout : b.C.Bw;
         double* fgdst = fgout ? fgout : b.C.fgw;
