@@ -164,7 +164,8 @@ extern "C" int dbie_trace_lines(dbie_ctx* c, const dbie_lambda_grid* lg, const d
     const int64_t N = ctx_n(c);
     if (N == 0) return DBIE_OK;
     if (!xyz_out || !count) return ctx_fail(c, DBIE_E_INVAL, "xyz_out and count are required");
-    if ((int64_t)(n_steps + 1) * 3 * N > ((int64_t)1 << 40)) return ctx_fail(c, DBIE_E_INVAL, "output too large");
+    // (n_steps + 1) x 3 x N doubles of output; beyond 2^34 values (128 GB) the call is refused
+    if (((int64_t)n_steps + 1) * 3 * N > ((int64_t)1 << 34)) return ctx_fail(c, DBIE_E_INVAL, "output too large");
     hipStream_t s = (hipStream_t)stream;
     // workspace: seeds (3N), x (3N), kprev (3N), ksum (3N), lam (3N), B (3N), dB (9N), ok, alive, flag
     const size_t nd = (size_t)N * 27;
@@ -186,7 +187,7 @@ extern "C" int dbie_trace_lines(dbie_ctx* c, const dbie_lambda_grid* lg, const d
     const Box bx{{box[0], box[1], box[2]}, {box[3], box[4], box[5]}};
     const LamGrid g{lg->nx, lg->ny, lg->nz, lg->x0, lg->y0, lg->z0, lg->dx, lg->dy, lg->dz, lg->lambda};
     const unsigned gN = (unsigned)((N + 255) / 256);
-    const int64_t total = (int64_t)(n_steps + 1) * 3 * N;
+    const int64_t total = ((int64_t)n_steps + 1) * 3 * N;
 #define TR_HIP(call)                                                                    \
     do {                                                                                \
         hipError_t e_ = (call);                                                         \
