@@ -131,9 +131,10 @@ def adjoint_and_scalar(D, ctx, lam, pairs):
                 scalar_lambda_field_grad_ms=ms_sc, scalar_lambda_pairs_per_s=pairs / (ms_sc * 1e-3))
 
 
-def time_to_solution(D, dev, n_sample=65536, eps=1e-4):
+def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3"):
     """Plain form (FP64 Nelder-Mead, 200 trials) vs fast form (FP32C Levenberg-Marquardt, 20 trials,
-    FP64 acceptance) on a z-stratified sample of the 256x256x128 bipole grid, from lambda = 0; the
+    FP64 acceptance) on a z-stratified sample of the 256x256x128 bipole grid (or of the clustered
+    points of the 512x256 active region, workload="config5"), from lambda = 0; the
     FP32C Nelder-Mead (200 trials, FP64 acceptance) separates the precision from the method.
     q* = the solved fraction (max(f, g) <= eps in FP64) the plain form reaches within its budget;
     TTS(form) = solve time until that form's solved fraction reaches q* (round-end HIP events), where
@@ -142,8 +143,9 @@ def time_to_solution(D, dev, n_sample=65536, eps=1e-4):
     and the FP32C forms add the duration of that pass (the solve's end minus the end of its last
     round)."""
     import torch
-    from workloads import config3, z_stratified_subsample
-    w = config3()
+    import workloads
+    from workloads import z_stratified_subsample
+    w = getattr(workloads, workload)()
     bd = w.boundaries[0]
     idx = z_stratified_subsample(w.xyz, n_sample, 3)
     xyz = torch.tensor(np.ascontiguousarray(w.xyz[:, idx]), dtype=torch.float64, device=dev)
@@ -394,6 +396,8 @@ def main():
                          ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs)),
                          ("time_to_solution", lambda: time_to_solution(D, dev)),
                          ("time_to_solution_eps_0.1", lambda: time_to_solution(D, dev, eps=0.1)),
+                         ("time_to_solution_active_region",
+                          lambda: time_to_solution(D, dev, workload="config5")),
                          ("batched_64_magnetograms", lambda: batched(D, dev)),
                          ("active_region_512x256_arcs", lambda: active_region(D, dev)),
                          ("quad9_elements_127x127", lambda: quad9_elements(D, dev)),

@@ -159,9 +159,15 @@ def grid_points(nx, ny, nz, x0=0.0, y0=0.0, h=1.0, zstep=1.0):
 
 
 def z_stratified_subsample(xyz: np.ndarray, n_sub: int, seed: int) -> np.ndarray:
-    """Indices of a seeded subsample with the same number of points on every z level."""
+    """Indices of a seeded subsample with the same number of points on every z level; with more
+    distinct heights than n_sub (continuous z), one point from each of n_sub equal-count bins of z."""
     rng = np.random.default_rng(seed)
     levels = np.unique(xyz[2])
+    if len(levels) > n_sub:
+        order = np.argsort(xyz[2], kind="stable")
+        edges = np.linspace(0, order.size, n_sub + 1).astype(np.int64)   # n_sub bins of equal count
+        pick = edges[:-1] + (rng.random(n_sub) * (edges[1:] - edges[:-1])).astype(np.int64)
+        return np.sort(order[pick])
     per = max(1, n_sub // len(levels))
     idx = []
     for zl in levels:
