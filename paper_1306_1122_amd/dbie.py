@@ -415,3 +415,34 @@ def dbie_destroy(ctx: Context):
 def dbie_last_error(ctx: Optional[Context] = None) -> str:
     m = _lib().dbie_last_error(ctx.handle if ctx is not None else None)
     return m.decode() if m else ""
+
+
+class Field:
+    """The context with its calls as methods (argument marshalling only):
+
+        f = Field([dict(B0=..., x0=..., y0=..., h=...)], xyz, precision="fp32c")
+        out = f.eval(lam); sol = f.solve(lam0, method="lm"); g = f.grad(lam, gB=...)
+
+    The keyword arguments of dbie_init, dbie_eval_field, dbie_solve_lambda, dbie_grad and
+    dbie_trace_lines pass through unchanged."""
+
+    def __init__(self, boundaries: List[Dict], xyz: torch.Tensor, **init_kw):
+        self.ctx = dbie_init(boundaries, xyz, **init_kw)
+
+    def eval(self, lam: torch.Tensor, **kw):
+        return dbie_eval_field(self.ctx, lam, **kw)
+
+    def eval_scalar(self, lam: torch.Tensor, **kw):
+        return dbie_eval_field_scalar(self.ctx, lam, **kw)
+
+    def solve(self, lambda_inout: torch.Tensor, **kw):
+        return dbie_solve_lambda(self.ctx, lambda_inout, **kw)
+
+    def grad(self, lam: torch.Tensor, **kw):
+        return dbie_grad(self.ctx, lam, **kw)
+
+    def trace(self, lam_grid: torch.Tensor, origin, spacing, box, ds: float, n_steps: int, **kw):
+        return dbie_trace_lines(self.ctx, lam_grid, origin, spacing, box, ds, n_steps, **kw)
+
+    def close(self):
+        self.ctx.close()

@@ -165,3 +165,22 @@ def test_full_size_adjoint_sampled(precision):
     err = rel(got, ref)
     print("full-size adjoint", precision, f"{err:.1e}", flush=True)
     assert err <= (1e-10 if precision == "fp64" else 1e-5)
+
+
+def test_field_object_matches_the_calls():
+    """Field wraps a context: its methods return what the free functions return on the same
+    context, bitwise."""
+    B0, x0, y0, h, xyz, lam, gB, gdB = case(seed=37, n=300)
+    f = D.Field([dict(B0=T(B0), x0=x0, y0=y0, h=h)], T(xyz), precision="fp32c")
+    a = f.eval(T(lam), want_tan=True)
+    b = D.dbie_eval_field(f.ctx, T(lam), want_tan=True)
+    for k in ("B", "dB", "fg", "tan"):
+        assert torch.equal(a[k], b[k]), k
+    ga = f.grad(T(lam), gB=T(gB), gdB=T(gdB))
+    gb = D.dbie_grad(f.ctx, T(lam), gB=T(gB), gdB=T(gdB))
+    assert torch.equal(ga["gB0"], gb["gB0"]) and torch.equal(ga["glambda"], gb["glambda"])
+    sa = f.solve(T(lam), method="lm", max_trials=4, fp64_accept=False)
+    sb = D.dbie_solve_lambda(f.ctx, T(lam), method="lm", max_trials=4, fp64_accept=False)
+    for k in ("lam", "status", "trials"):
+        assert torch.equal(sa[k], sb[k]), k
+    f.close()
