@@ -117,17 +117,21 @@ def per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s):
     return out
 
 
-def adjoint_and_scalar(D, ctx, lam, pairs):
-    """dbie_grad (B0 adjoint + lambda gradient, FP32C) and the single-lambda evaluation on the
+def adjoint_and_scalar(D, ctx, lam, pairs, B0, xyz, bd):
+    """dbie_grad (B0 adjoint, FP32C and FP64 contexts) and the single-lambda evaluation on the
     benchmark workload."""
     import torch
     N = ctx.n_points
     g = torch.ones(3, N, dtype=torch.float64, device=lam.device)
     gd = torch.ones(9, N, dtype=torch.float64, device=lam.device)
     ms_adj = _timed(lambda: D.dbie_grad(ctx, lam, gB=g, gdB=gd, want_glambda=False), 2)
+    c64 = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision="fp64")
+    ms_adj64 = _timed(lambda: D.dbie_grad(c64, lam, gB=g, gdB=gd, want_glambda=False), 1)
+    c64.close()
     lam1 = lam[0].contiguous()
     ms_sc = _timed(lambda: D.dbie_eval_field_scalar(ctx, lam1), 3)
     return dict(adjoint_gB0_ms=ms_adj, adjoint_pairs_per_s=pairs / (ms_adj * 1e-3),
+                adjoint_gB0_fp64_ms=ms_adj64, adjoint_fp64_pairs_per_s=pairs / (ms_adj64 * 1e-3),
                 scalar_lambda_field_grad_ms=ms_sc, scalar_lambda_pairs_per_s=pairs / (ms_sc * 1e-3))
 
 
@@ -393,7 +397,7 @@ def main():
     extras = {}
     if not args.no_extras:
         for name, fn in (("per_trial_rates", lambda: per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s)),
-                         ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs)),
+                         ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs, B0, xyz, bd)),
                          ("time_to_solution", lambda: time_to_solution(D, dev)),
                          ("time_to_solution_eps_0.1", lambda: time_to_solution(D, dev, eps=0.1)),
                          ("time_to_solution_active_region",
