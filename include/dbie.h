@@ -165,7 +165,8 @@ DBIE_API int dbie_eval_field_scalar(dbie_ctx* ctx, const double* lambda, int32_t
  * One trial is one evaluation of (B, grad B) at one lambda triple for one point. Nelder-Mead uses the
  * simplex {lambda0, lambda0 + step e_p}, coefficients 1, 2, 1/2, 1/2; a proposal outside the cap
  * costs a trial and counts as Phi = +inf. LM starts at mu = lambda0^2. The host reads one active-point
- * count per few rounds (synchronising `stream`) and returns when every point is done. The rounds
+ * count per few rounds (synchronising `stream`), and the number of converged points once more before an
+ * FP64 confirmation, and returns when every point is done. The rounds
  * between two reads are captured once into a HIP graph per context and configuration and replayed
  * (not while timing or tracing is enabled). */
 DBIE_API int dbie_solve_lambda(dbie_ctx* ctx, double* lambda_inout, const dbie_solve_opts* opt,
