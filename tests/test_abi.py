@@ -40,6 +40,25 @@ def test_library_exports_every_declared_symbol(lib):
         assert n in L.SIGNATURES, n
 
 
+def declared_arity():
+    """Number of parameters of every declared entry point, from the header text."""
+    txt = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"DBIE_API\s+[\w\s\*]+?\b(dbie_\w+)\s*\((.*?)\)\s*;", txt, re.S):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    """The ctypes declarations take as many arguments as the header declares (a changed signature
+    cannot go unnoticed by the binding)."""
+    ar = declared_arity()
+    assert len(ar) == len(declared_symbols())
+    for name, n in ar.items():
+        assert len(L.SIGNATURES[name][1]) == n, (name, n, len(L.SIGNATURES[name][1]))
+
+
 def test_defaults(lib):
     o = L.dbie_options()
     assert lib.dbie_default_options(ctypes.byref(o)) == 0
