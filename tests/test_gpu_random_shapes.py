@@ -55,3 +55,22 @@ def test_random_shape(seed, precision):
           flush=True)
     for k, v in errs.items():
         assert v <= TOL[precision], (k, v)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_random_shape_adjoint(seed, precision):
+    """The adjoint on the same kind of random cases (nodal rule): dL/dB0 and dL/dlambda against the
+    oracle's VJP for seeded upstream gradients."""
+    _, B0, x0, y0, h, xyz, lam = case(100 + seed)
+    rng = np.random.default_rng(6000 + seed)
+    gB = rng.normal(size=(3, xyz.shape[1]))
+    gdB = rng.normal(size=(9, xyz.shape[1]))
+    ctx = D.dbie_init([dict(B0=T(B0), x0=x0, y0=y0, h=h)], T(xyz), precision=precision)
+    r = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB))
+    torch.cuda.synchronize()
+    gB0, glam, _ = oracle.vjp(B0, x0, y0, h, xyz, lam, gB, gdB)
+    e0 = rel(r["gB0"].view(3, *B0.shape[1:]).cpu(), gB0)
+    e1 = rel(r["glambda"].cpu(), glam)
+    print("random adjoint", seed, precision, B0.shape[1:], xyz.shape[1], f"{e0:.1e} {e1:.1e}", flush=True)
+    assert e0 <= TOL[precision] and e1 <= TOL[precision]
