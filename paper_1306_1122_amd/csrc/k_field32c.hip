@@ -13,7 +13,7 @@
 //   dx_c = (a0 + c - floor(u)) - frac(u)           (exact integer difference, one rounding)
 // are kept in registers; for each row dy = (b0 + r - floor(v)) - frac(v) and q = dy^2 + w^2; then
 //   rho^2 = dx_c^2 + q, rho^-1 = rsq(rho^2), and per component t = Lambda rho, sin/cos in
-//   revolutions (range-reduced by fract only when a wavefront's |Lambda| rho / 2pi can exceed the
+//   revolutions (minus the nearest integer, only when a wavefront's |Lambda| rho / 2pi can exceed the
 //   hardware's accurate range of 256 revolutions), N = t sin t + cos t and, in place of
 //   H = t^2 cos t - 3 N, the two-operation form Q = -H / 3 = N - (Lambda^2 / 3) rho^2 cos t;
 //   A0 += N rho^-3 B0,  A1 += Q rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += Q rho^-3 B0 rho^-2
@@ -44,15 +44,14 @@ struct PointState {
 
 constexpr float kTwoPiF = 6.28318530717958647692f;
 
-// Phase in revolutions (hi = lr r as rounded), reduced to about [0, 1) when FRACT: the rounding
-// error of the product (half an ulp of |lr r|, up to 1.5e-5 revolutions at the 256-revolution
-// bound) is recovered exactly by an FMA and added back after the reduction, leaving r's own
-// rounding as the phase error.
+// Phase in revolutions (hi = lr r as rounded), reduced to about [-1/2, 1/2] when FRACT: with
+// k = rint(hi), one FMA forms lr r - k from the exact product with a single rounding (the product's
+// own rounding, half an ulp of |lr r|, up to 1.5e-5 revolutions at the 256-revolution bound, is not
+// incurred), leaving r's rounding as the phase error.
 template <bool FRACT>
 __device__ __forceinline__ float phase_rev(float lr, float r, float hi) {
     if (!FRACT) return hi;
-    const float lo = fmaf(lr, r, -hi);
-    return __builtin_amdgcn_fractf(hi) + lo;
+    return fmaf(lr, r, -__builtin_rintf(hi));
 }
 
 // One pair given dx, dy (pixels), q = dy^2 + w^2 and the field of the pixel.

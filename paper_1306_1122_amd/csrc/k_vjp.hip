@@ -175,10 +175,10 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
         const float ri5 = ri3 * ri2;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            // phase in revolutions; FRACT (a chunk beyond the sin/cos range): reduced, with the
-            // product's rounding recovered by an FMA
+            // phase in revolutions; FRACT (a chunk beyond the sin/cos range): minus its nearest
+            // integer, formed from the exact product by one FMA
             const float th = sp[8 + p][e] * r;
-            const float tr = FRACT ? __builtin_amdgcn_fractf(th) + fmaf(sp[8 + p][e], r, -th) : th;
+            const float tr = FRACT ? fmaf(sp[8 + p][e], r, -__builtin_rintf(th)) : th;
             const float sn = __builtin_amdgcn_sinf(tr);
             const float cs = __builtin_amdgcn_cosf(tr);
             const float t = th * kTwoPiF;
