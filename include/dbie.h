@@ -200,7 +200,8 @@ DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int3
  * dbie_solve_trace_read synchronises and returns, for the last solve, the elapsed milliseconds at
  * the end of each round (t_ms) and the number of points that converged in each round (converged),
  * for up to max_rounds rounds; *n_rounds = rounds run; *t_end_ms = elapsed milliseconds at the end
- * of the call. Any output pointer may be NULL. */
+ * of the call. Any output pointer may be NULL. DBIE_E_INVAL for max_rounds < 0, and for converged
+ * != NULL when the last traced solve returned an error; dbie_set_workspace discards the trace. */
 DBIE_API int dbie_solve_trace(dbie_ctx* ctx, int32_t enable);
 DBIE_API int dbie_solve_trace_read(dbie_ctx* ctx, double* t_ms, int32_t* converged, int32_t max_rounds,
                                    int32_t* n_rounds, double* t_end_ms);

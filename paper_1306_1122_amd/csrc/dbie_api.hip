@@ -340,6 +340,14 @@ NearLists ctx_near_lists(const dbie_ctx* c) {
 bool ctx_timing(const dbie_ctx* c) { return c->timing; }
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c) { return c->trace_ev; }
 hipEvent_t& solver_trace_end(dbie_ctx* c) { return c->trace_end; }
+void solver_forget_last(dbie_ctx* c) {
+    for (auto e : c->trace_ev) (void)hipEventDestroy(e);
+    c->trace_ev.clear();
+    if (c->trace_end) (void)hipEventDestroy(c->trace_end);
+    c->trace_end = nullptr;
+    c->solver.last_conv = nullptr;
+    c->solver.last_rounds = 0;
+}
 int32_t ctx_nb(const dbie_ctx* c) { return c->nb; }
 const double* ctx_B0d(const dbie_ctx* c) { return c->B0d; }
 VjpTables ctx_vjp_tables(const dbie_ctx* c) { return c->vjp; }
@@ -809,6 +817,7 @@ int dbie_solve_trace(dbie_ctx* c, int32_t enable) {
 int dbie_solve_trace_read(dbie_ctx* c, double* t_ms, int32_t* converged, int32_t max_rounds,
                           int32_t* n_rounds, double* t_end_ms) {
     if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    if (max_rounds < 0) return fail(c, DBIE_E_INVAL, "max_rounds < 0");
     const int32_t n = (int32_t)c->trace_ev.size() - 1;   // the first event marks the start
     if (n_rounds) *n_rounds = std::max(n, 0);
     if (t_end_ms) *t_end_ms = 0.0;
@@ -826,8 +835,10 @@ int dbie_solve_trace_read(dbie_ctx* c, double* t_ms, int32_t* converged, int32_t
         DBIE_HIP(c, hipEventElapsedTime(&ms, c->trace_ev[0], c->trace_ev[r + 1]));
         if (t_ms) t_ms[r] = ms;
     }
-    if (converged && c->solver.last_conv)
+    if (converged) {
+        if (!c->solver.last_conv) return fail(c, DBIE_E_INVAL, "the last solve did not complete");
         DBIE_HIP(c, hipMemcpy(converged, c->solver.last_conv, m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
     return DBIE_OK;
 }
 
@@ -858,6 +869,7 @@ int dbie_set_workspace(dbie_ctx* c, void* dev, int64_t bytes) {
     if (int rc = ctx_check_device(c)) return rc;
     // nothing may still use the buffers being given up
     DBIE_HIP(c, hipDeviceSynchronize());
+    solver_forget_last(c);   // the per-round counts lie in the solver block given up here
     if (c->acc_owned) (void)hipFree(c->acc);
     c->acc = nullptr;
     c->acc_L = 0;

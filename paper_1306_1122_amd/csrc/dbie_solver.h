@@ -125,6 +125,9 @@ bool solver_tracing(const dbie_ctx* c);
 bool ctx_timing(const dbie_ctx* c);
 std::vector<hipEvent_t>& solver_trace_events(dbie_ctx* c);
 hipEvent_t& solver_trace_end(dbie_ctx* c);   // recorded at the end of a traced solve
+// Drops what the last solve left for dbie_solve_trace_read (its events and per-round counts); called
+// before a solve may move the solver block and when the workspace changes.
+void solver_forget_last(dbie_ctx* c);
 // FP32C tile shapes: one for the plain field pass and one for the pass with mu-tangents.
 int set_shape(dbie_ctx* c, F32Shape s, bool tan);
 F32Shape get_shape(const dbie_ctx* c, bool tan);

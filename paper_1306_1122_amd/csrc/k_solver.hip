@@ -839,6 +839,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     hipStream_t s = (hipStream_t)stream;
     SolverBufs b;
     const bool lmm = opt->method == DBIE_LEVENBERG_MARQUARDT;
+    solver_forget_last(c);   // the block may move below
     int rc = solver_bufs(c, opt->max_trials, lmm, b);
     if (rc) return rc;
     const int32_t nb = ctx_nb(c);
@@ -885,11 +886,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     int32_t rounds = 0;
     const int32_t check_every = 4;
     std::vector<hipEvent_t>& trace = solver_trace_events(c);
-    for (auto e : trace) (void)hipEventDestroy(e);
-    trace.clear();
     hipEvent_t& trace_end = solver_trace_end(c);
-    if (trace_end) (void)hipEventDestroy(trace_end);
-    trace_end = nullptr;
     const bool tracing = solver_tracing(c);
     if (tracing) {
         hipEvent_t e = nullptr;

@@ -60,15 +60,21 @@ __device__ __forceinline__ void interp_lambda(const LamGrid& g, double x, double
 __global__ void k_trace_init(int64_t N, const double* __restrict__ seeds, Box box, int64_t total,
                              double* __restrict__ out, int32_t* __restrict__ count, int32_t* __restrict__ alive,
                              double* __restrict__ x) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < total && e >= 3 * N) out[e] = __builtin_nan("");
-    if (e >= N) return;
-    for (int p = 0; p < 3; ++p) {
-        x[p * N + e] = seeds[p * N + e];
-        out[p * N + e] = seeds[p * N + e];
+    // grid-stride: the output (up to 2^34 values) can exceed one launch's 2^32 work-items
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        if (e >= 3 * N) {
+            out[e] = __builtin_nan("");
+            continue;
+        }
+        if (e >= N) continue;
+        for (int p = 0; p < 3; ++p) {
+            x[p * N + e] = seeds[p * N + e];
+            out[p * N + e] = seeds[p * N + e];
+        }
+        count[e] = 1;
+        alive[e] = inside(box, seeds[e], seeds[N + e], seeds[2 * N + e]) ? 1 : 0;
     }
-    count[e] = 1;
-    alive[e] = inside(box, seeds[e], seeds[N + e], seeds[2 * N + e]) ? 1 : 0;
 }
 
 // Stage st (0..3) positions y = x + c_st ds k_prev (c = 0, 1/2, 1/2, 1); a line whose stage point
@@ -194,27 +200,30 @@ extern "C" int dbie_trace_lines(dbie_ctx* c, const dbie_lambda_grid* lg, const d
         if (e_ != hipSuccess) return ctx_fail(c, DBIE_E_DEVICE, hipGetErrorString(e_)); \
     } while (0)
     TR_HIP(hipMemcpyAsync(seeds, pts, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_trace_init, dim3((unsigned)((std::max<int64_t>(total, N) + 255) / 256)), dim3(256), 0, s,
-                       N, seeds, bx, total, xyz_out, count, alive, x);
-    TR_HIP(hipGetLastError());
-    int rc = DBIE_OK;
-    for (int32_t step = 1; step <= n_steps && rc == DBIE_OK; ++step) {
-        for (int st = 0; st < 4; ++st) {
-            hipLaunchKernelGGL(k_trace_stage, dim3(gN), dim3(256), 0, s, N, st, ds, bx, g, x, kprev, alive, ok, pts,
-                               lam);
-            TR_HIP(hipGetLastError());
-            TR_HIP(ctx_prep_points(c, flag, s));
-            rc = eval_set(c, lam, fp64, false, nullptr, B, cur ? dB : nullptr, nullptr, nullptr, s);
-            if (rc) break;
-            hipLaunchKernelGGL(k_trace_dir, dim3(gN), dim3(256), 0, s, N, st, sense, cur ? 1 : 0, B, dB, kprev,
-                               ksum);
+    // the steps move the context's points; on every exit after this they are put back
+    auto steps = [&]() -> int {
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
+        hipLaunchKernelGGL(k_trace_init, dim3((unsigned)blocks), dim3(256), 0, s, N, seeds, bx, total, xyz_out, count,
+                           alive, x);
+        TR_HIP(hipGetLastError());
+        for (int32_t step = 1; step <= n_steps; ++step) {
+            for (int st = 0; st < 4; ++st) {
+                hipLaunchKernelGGL(k_trace_stage, dim3(gN), dim3(256), 0, s, N, st, ds, bx, g, x, kprev, alive, ok,
+                                   pts, lam);
+                TR_HIP(hipGetLastError());
+                TR_HIP(ctx_prep_points(c, flag, s));
+                if (int r = eval_set(c, lam, fp64, false, nullptr, B, cur ? dB : nullptr, nullptr, nullptr, s)) return r;
+                hipLaunchKernelGGL(k_trace_dir, dim3(gN), dim3(256), 0, s, N, st, sense, cur ? 1 : 0, B, dB, kprev,
+                                   ksum);
+                TR_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(k_trace_advance, dim3(gN), dim3(256), 0, s, N, step, ds, ok, ksum, alive, x, xyz_out,
+                               count);
             TR_HIP(hipGetLastError());
         }
-        if (rc) break;
-        hipLaunchKernelGGL(k_trace_advance, dim3(gN), dim3(256), 0, s, N, step, ds, ok, ksum, alive, x, xyz_out,
-                           count);
-        TR_HIP(hipGetLastError());
-    }
+        return DBIE_OK;
+    };
+    const int rc = steps();
     // the context's points and geometry back to the seeds
     TR_HIP(hipMemcpyAsync(pts, seeds, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
     TR_HIP(ctx_prep_points(c, flag, s));

@@ -331,7 +331,7 @@ def dbie_solve_trace_read(ctx: Context, max_rounds: int = 100000, with_end: bool
     n = ctypes.c_int32()
     _check(_lib().dbie_solve_trace_read(ctx.handle, None, None, 0, ctypes.byref(n), None), ctx,
            "dbie_solve_trace_read")
-    m = min(n.value, max_rounds)
+    m = max(0, min(n.value, max_rounds))
     t = (ctypes.c_double * max(m, 1))()
     cv = (ctypes.c_int32 * max(m, 1))()
     te = ctypes.c_double()

@@ -6,6 +6,7 @@ FP64 oracle re-evaluates it at the returned lambda; the GPU's (B, f, g) at lambd
 there; and with FP64 evaluations the simplex trajectories coincide with the oracle's except where
 rounding flips a near-tie decision.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -262,3 +263,27 @@ def test_solve_trace_reports_rounds_and_the_end():
     st = r["status"].cpu().numpy()
     assert 1 <= len(t) <= 12 and np.all(np.diff(t) >= 0) and t_end >= t[-1] > 0
     assert int(cv.sum()) == int(np.sum(st == oracle.ST_CONVERGED))
+
+
+def test_trace_is_dropped_when_the_workspace_changes():
+    """The per-round counts of a traced solve live in the solver's block: handing the context a
+    workspace frees that block, so the trace is dropped (0 rounds) rather than read from freed
+    memory; a negative round count is refused; a traced solve in the workspace reads back as before."""
+    w, bd, ctx = lowlou_ctx("fp32c")
+    N = w.n_points
+    z = lambda: torch.zeros(3, N, dtype=torch.float64, device="cuda:0")  # noqa: E731
+    D.dbie_solve_trace(ctx, True)
+    D.dbie_solve_lambda(ctx, z(), method="lm", max_trials=8, eps=0.05, fp64_accept=False)
+    t0, cv0 = D.dbie_solve_trace_read(ctx)
+    assert len(t0) >= 1
+    from paper_1306_1122_amd import _lib
+    n = ctypes.c_int32()
+    assert _lib.load().dbie_solve_trace_read(ctx.handle, None, None, -1, ctypes.byref(n), None) != 0
+    ws = torch.empty(D.dbie_workspace_bytes(ctx), dtype=torch.uint8, device="cuda:0")
+    D.dbie_set_workspace(ctx, ws)
+    t1, cv1 = D.dbie_solve_trace_read(ctx)
+    assert len(t1) == 0 and len(cv1) == 0
+    D.dbie_solve_lambda(ctx, z(), method="lm", max_trials=8, eps=0.05, fp64_accept=False)
+    t2, cv2 = D.dbie_solve_trace_read(ctx)
+    D.dbie_solve_trace(ctx, False)
+    assert len(t2) == len(t0) and np.array_equal(cv2, cv0)
