@@ -117,6 +117,23 @@ def per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s):
     return out
 
 
+def error_vs_fp64(D, ctx, ctx64, lam):
+    """Error of the FP32C evaluation against the FP64 path on the same points and lambda: relative
+    L2 over all points of B, grad B and the mu-tangents, the largest per-point |dB| / |B|, and the
+    largest change of f and g (computed in FP64 from either field)."""
+    import torch
+    a = D.dbie_eval_field(ctx, lam, want_tan=True)
+    b = D.dbie_eval_field(ctx64, lam, want_tan=True)
+    nrm = torch.linalg.vector_norm
+    out = {k + "_rel_l2": float(nrm(a[k] - b[k]) / nrm(b[k])) for k in ("B", "dB", "tan")}
+    pt = nrm(a["B"] - b["B"], dim=0) / nrm(b["B"], dim=0)
+    out["B_max_point_rel"] = float(pt[torch.isfinite(pt)].max())
+    d = (a["fg"] - b["fg"]).abs()
+    out["fg_max_abs"] = float(d[torch.isfinite(d)].max())
+    out["reference"] = "FP64 path (dbie_eval_field in an FP64 context), same workload, all points"
+    return out
+
+
 def adjoint_and_scalar(D, ctx, lam, pairs, B0, xyz, bd):
     """dbie_grad (B0 adjoint, FP32C and FP64 contexts) and the single-lambda evaluation on the
     benchmark workload."""
@@ -259,9 +276,12 @@ def active_region(D, dev):
     pairs = w.pairs_per_trial()
     ms = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
     mst = _timed(lambda: D.dbie_eval_field(ctx, lam, want_tan=True), 2)
+    c64 = D.dbie_init([dict(B0=T(bd.B0), x0=0.0, y0=0.0, h=1.0)], T(w.xyz), precision="fp64")
+    err = error_vs_fp64(D, ctx, c64, lam)
+    c64.close()
     ctx.close()
     return dict(points=w.n_points, pairs=pairs, field_grad_ms=ms, field_grad_pairs_per_s=pairs / (ms * 1e-3),
-                with_tangents_ms=mst, with_tangents_pairs_per_s=pairs / (mst * 1e-3))
+                with_tangents_ms=mst, with_tangents_pairs_per_s=pairs / (mst * 1e-3), fp32c_error_vs_fp64=err)
 
 
 def quad9_elements(D, dev):
@@ -413,6 +433,14 @@ def main():
             except Exception as exc:  # an extra must not hide the headline line
                 extras[name] = {"error": repr(exc)}
 
+    # the error of the timed FP32C arithmetic against the FP64 path on the benchmark workload
+    # (outside the timed region)
+    accuracy = None
+    if not args.no_extras:
+        c64 = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision="fp64")
+        accuracy = error_vs_fp64(D, ctx, c64, lam)
+        c64.close()
+
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -447,6 +475,7 @@ def main():
                      "flops_per_pair": FLOPS_FIELD_GRAD_TAN, "pairs_per_launch": pairs_per_launch,
                      "avg_launch_ms": kern_avg_ms, "launches": launches},
         "cpu_baseline": cpu,
+        "fp32c_error_vs_fp64": accuracy,
         "wall_s": wall,
         "extras": extras,
     }
