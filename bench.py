@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(points would be sharded across GPUs with the magnetogram replicated).", file=sys.stderr)
         sys.exit(2)
 

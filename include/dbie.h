@@ -46,7 +46,7 @@ enum {
     DBIE_E_INVAL = -1,       /* invalid argument (message says which) */
     DBIE_E_DEVICE = -2,      /* a HIP call failed */
     DBIE_E_WORKSPACE = -3,   /* device memory could not be allocated */
-    DBIE_E_UNSUPPORTED = -4  /* valid request this build does not support */
+    DBIE_E_UNSUPPORTED = -4  /* valid request this library does not support */
 };
 
 /* precision of the bulk pixel sum */
