@@ -81,11 +81,16 @@ struct Geo {
 // exact for |k| < 2^20, the second leaves ~1e-27), and polynomials on [-pi/2, pi/2] fitted by least
 // squares on Chebyshev nodes in 50-digit arithmetic (sin r = r + r^3 P(r^2), P of degree 7;
 // cos r = 1 - r^2/2 + r^4 Q(r^2), Q of degree 6; fit errors below 2e-17 with the coefficients
-// rounded to double). Returns sin r, cos r and the parity of k: sin t = (-1)^k sin r and
-// cos t = (-1)^k cos r, so the callers apply the common sign to what multiplies them.
+// rounded to double). k comes from one FMA that adds 1.5 2^52 to t/pi: doubles in that binade are
+// one apart, so the sum is t/pi rounded to an integer (ties to even) and its low word holds k in
+// two's complement (|t/pi| < 2^51). Returns sin r, cos r and, as a mask of the sign bit, the parity
+// of k: sin t = (-1)^k sin r and cos t = (-1)^k cos r, so the callers flip the sign of what
+// multiplies them (one XOR).
 constexpr double kSincosBound = 524288.0;   // 2^19
-__device__ __forceinline__ int sincos_halfturn(double t, double* s, double* c) {
-    const double k = __builtin_rint(t * 0.3183098861837907);
+constexpr double kRoundMagic = 6755399441055744.0;   // 1.5 2^52
+__device__ __forceinline__ uint64_t sincos_halfturn(double t, double* s, double* c) {
+    const double kb = __builtin_fma(t, 0.3183098861837907, kRoundMagic);
+    const double k = kb - kRoundMagic;
     double r = __builtin_fma(-k, 3.141592653589793, t);
     r = __builtin_fma(-k, 1.2246467991473532e-16, r);
     const double z = r * r;
@@ -104,33 +109,49 @@ __device__ __forceinline__ int sincos_halfturn(double t, double* s, double* c) {
     q = __builtin_fma(z, q, -0.0013888888888827712);
     q = __builtin_fma(z, q, 0.04166666666666578);
     *c = __builtin_fma(z * z, q, __builtin_fma(z, -0.5, 1.0));
-    return (int)k & 1;
+    return __builtin_bit_cast(uint64_t, kb) << 63;
+}
+
+// 1/sqrt(x) for finite x > 0 (a squared distance, at least w^2 > 0): the hardware estimate refined by
+// one third-order Householder step, y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, which takes the
+// estimate's relative error d to about (5/16) d^3.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
+// x with its sign bit flipped where `sign` (0 or the sign bit) says so
+__device__ __forceinline__ double flip_sign(double x, uint64_t sign) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) ^ sign);
 }
 
 // One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
 // dx = a_k - u, dy = b_k - v, w2 = w^2, all in pixels. Shared by the FP64 bulk kernel and the
 // FP64 near-field pass of the FP32C path. WIDE: the device library's sincos (any argument);
-// otherwise every |lambda r| must stay below kSincosBound.
+// otherwise every |lambda r| must stay below kSincosBound. H = t^2 cos t - 3 N is summed as
+// (-3 / r^5)(N - (lambda^2 / 3) r^2 cos t): one multiply and one FMA per component, the factor
+// -3 once per pair.
 template <bool TAN, bool WIDE>
 __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const double lam[3],
                                           double b0x, double b0y, double b0z, double* acc) {
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
-    const double ri = rsqrt(r2);
+    const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
     const double r = r2 * ri;
     const double ri2 = ri * ri;
     const double ri3 = ri2 * ri;
-    const double ri5 = ri3 * ri2;
+    const double ri5n3 = ri3 * (-3.0 * ri2);
     const double b0[3] = {b0x, b0y, b0z};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const double t = lam[p] * r;
         double s, c, bp = b0[p];
         if (WIDE) sincos(t, &s, &c);
-        else if (sincos_halfturn(t, &s, &c)) bp = -bp;   // (-1)^k carried by B0
+        else bp = flip_sign(bp, sincos_halfturn(t, &s, &c));   // (-1)^k carried by B0
         const double n = __builtin_fma(t, s, c);
-        const double hh = __builtin_fma(t, t * c, -3.0 * n);
+        const double q = __builtin_fma(lam[p] * lam[p] * (-1.0 / 3.0) * r2, c, n);   // -H / 3
         const double nb = n * (ri3 * bp);
-        const double hb = hh * (ri5 * bp);
+        const double hb = q * (ri5n3 * bp);
         acc[4 * p + 0] += nb;
         acc[4 * p + 1] = __builtin_fma(hb, dx, acc[4 * p + 1]);
         acc[4 * p + 2] = __builtin_fma(hb, dy, acc[4 * p + 2]);

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
             for (int e = 0; e < n; ++e) {
                 const double dx = a - su[e], dy = bb - sv[e];
                 const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, sw2[e]));
-                const double ri = rsqrt(r2);
+                const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
                 const double r = r2 * ri;
                 const double ri2 = ri * ri;
                 const double ri3 = ri2 * ri;
@@ -111,9 +111,10 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                     double s, c;
                     if (WIDE) {
                         sincos(t, &s, &c);
-                    } else if (sincos_halfturn(t, &s, &c)) {   // t = k pi + r with k odd
-                        s = -s;
-                        c = -c;
+                    } else {
+                        const uint64_t sg = sincos_halfturn(t, &s, &c);   // t = k pi + r: (-1)^k
+                        s = flip_sign(s, sg);
+                        c = flip_sign(c, sg);
                     }
                     const double nn = __builtin_fma(t, s, c);
                     const double hh = __builtin_fma(t, t * c, -3.0 * nn);

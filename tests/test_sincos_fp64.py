@@ -6,6 +6,7 @@ tiny values, the edges of the reduction interval and of the argument bound)."""
 import os
 import random
 import re
+import struct
 from fractions import Fraction
 
 import mpmath as mp
@@ -16,7 +17,7 @@ SRC = os.path.join(os.path.dirname(__file__), "..", "paper_1306_1122_amd", "csrc
 
 def _body():
     src = open(SRC).read()
-    m = re.search(r"int sincos_halfturn\(double t, double\* s, double\* c\) \{(.*?)\n\}", src, re.S)
+    m = re.search(r"uint64_t sincos_halfturn\(double t, double\* s, double\* c\) \{(.*?)\n\}", src, re.S)
     assert m, "sincos_halfturn not found"
     return m.group(1), src
 
@@ -28,23 +29,29 @@ def _fma(a, b, c):
 def _constants():
     body, src = _body()
     num = r"(-?[0-9.]+(?:e-?[0-9]+)?)"
-    k1pi = float(re.search(r"__builtin_rint\(t \* " + num + r"\)", body).group(1))
+    k1pi = float(re.search(r"double kb = __builtin_fma\(t, " + num + r", kRoundMagic\)", body).group(1))
+    assert re.search(r"double k = kb - kRoundMagic;", body)
+    assert re.search(r"return __builtin_bit_cast\(uint64_t, kb\) << 63;", body)
     pi_parts = [float(x) for x in re.findall(r"__builtin_fma\(-k, " + num + r", ", body)]
     p = re.findall(r"double p = __builtin_fma\(z, " + num + r", " + num + r"\)", body)[0]
     ps = [float(x) for x in re.findall(r"p = __builtin_fma\(z, p, " + num + r"\)", body)]
     q = re.findall(r"double q = __builtin_fma\(z, " + num + r", " + num + r"\)", body)[0]
     qs = [float(x) for x in re.findall(r"q = __builtin_fma\(z, q, " + num + r"\)", body)]
     bound = float(re.search(r"kSincosBound = " + num + ";", src).group(1))
+    magic = float(re.search(r"kRoundMagic = " + num + ";", src).group(1))
     # highest degree first, as the Horner steps of the source
-    return k1pi, pi_parts, [float(p[0]), float(p[1])] + ps, [float(q[0]), float(q[1])] + qs, bound
+    return k1pi, pi_parts, [float(p[0]), float(p[1])] + ps, [float(q[0]), float(q[1])] + qs, bound, magic
 
 
-K1PI, PI_PARTS, PC, QC, BOUND = _constants()
+K1PI, PI_PARTS, PC, QC, BOUND, MAGIC = _constants()
 
 
 def sincos_halfturn(t):
     """(sin t, cos t) from the device steps: sin r, cos r and the parity of k, t = k pi + r."""
-    k = float(round(t * K1PI))          # rint, ties to even
+    kb = _fma(t, K1PI, MAGIC)           # t/pi rounded to an integer (ties to even) by the addition
+    k = kb - MAGIC                      # exact
+    odd = struct.unpack("<Q", struct.pack("<d", kb))[0] & 1   # the sign mask is this bit moved to bit 63
+    assert k == int(k) and odd == int(k) & 1
     r = _fma(-k, PI_PARTS[0], t)
     r = _fma(-k, PI_PARTS[1], r)
     z = r * r
@@ -56,12 +63,14 @@ def sincos_halfturn(t):
     for cf in QC[2:]:
         q = _fma(z, q, cf)
     cr = _fma(z * z, q, _fma(z, -0.5, 1.0))
-    return (-sr, -cr) if int(k) & 1 else (sr, cr)
+    return (-sr, -cr) if odd else (sr, cr)
 
 
 def test_constants_parsed():
     assert len(PI_PARTS) == 2 and len(PC) == 8 and len(QC) == 7
     assert BOUND == 2.0 ** 19
+    # 1.5 2^52: spacing 1 in its binade, which |t/pi| < 2^51 never leaves
+    assert MAGIC == 1.5 * 2.0 ** 52 and BOUND * K1PI < 2.0 ** 51
     mp.mp.dps = 40
     assert abs(mp.mpf(PI_PARTS[0]) + mp.mpf(PI_PARTS[1]) - mp.pi) < 1e-32
 
