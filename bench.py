@@ -33,6 +33,11 @@ if ROOT not in sys.path:
 FLOPS_FIELD_GRAD = 68
 FLOPS_FIELD_GRAD_TAN = 89
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+# with packed FP32 switched off, one wave64 VALU instruction per SIMD per 4 cycles: 256 CUs x 4 SIMDs
+# x 2.4 GHz / 4 x 64 lanes = 3.93e13 lane-instructions/s; the kernel with tangents executes 61.09 of
+# them per pair (rocprofv3 SQ_INSTS_VALU), so its algorithmic ceiling is 89 x 3.93e13 / 61.09
+VALU_LANE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4 * 64
+VALU_PER_PAIR_TAN = 61.09
 TRIALS_PER_STEP = 3
 
 
@@ -413,6 +418,7 @@ def main():
     # a launch covers the points still active in its round: use the mean pairs per launch
     pairs_per_launch = pairs_per_step * args.steps / max(launches, 1)
     achieved = FLOPS_FIELD_GRAD_TAN * pairs_per_launch / (kern_avg_ms * 1e-3) / 1e12
+    ceiling = FLOPS_FIELD_GRAD_TAN * VALU_LANE_INSTS_PER_S / VALU_PER_PAIR_TAN / 1e12
 
     extras = {}
     if not args.no_extras:
@@ -472,6 +478,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": "k_field32c (FP32C bulk sum with mu-tangents)",
+                     "issue_ceiling": ceiling, "frac_of_issue_ceiling": achieved / ceiling,
                      "flops_per_pair": FLOPS_FIELD_GRAD_TAN, "pairs_per_launch": pairs_per_launch,
                      "avg_launch_ms": kern_avg_ms, "launches": launches},
         "cpu_baseline": cpu,
