@@ -34,10 +34,10 @@ FLOPS_FIELD_GRAD = 68
 FLOPS_FIELD_GRAD_TAN = 89
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 # with packed FP32 switched off, one wave64 VALU instruction per SIMD per 4 cycles: 256 CUs x 4 SIMDs
-# x 2.4 GHz / 4 x 64 lanes = 3.93e13 lane-instructions/s; the kernel with tangents executes 61.09 of
-# them per pair (rocprofv3 SQ_INSTS_VALU), so its algorithmic ceiling is 89 x 3.93e13 / 61.09
+# x 2.4 GHz / 4 x 64 lanes = 3.93e13 lane-instructions/s; divided by the VALU instructions the kernel
+# executes per pair (rocprofv3 SQ_INSTS_VALU, committed with the traffic counters) and times the
+# algorithmic flops per pair, this is the kernel's issue ceiling
 VALU_LANE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4 * 64
-VALU_PER_PAIR_TAN = 61.09
 TRIALS_PER_STEP = 3
 
 
@@ -76,9 +76,9 @@ def cpu_baseline(w, n_sample, seed=7):
                        f"(FP64 field + grad + mu-tangents + residuals), {dt:.2f} s wall")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+def measured_counters():
+    """The committed rocprofv3 counter summary of the dominant kernel (HBM bytes per launch, VALU
+    instructions per pair), or None when the kernel source has changed since it was taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic_k_field32c.json")) as fh:
@@ -87,7 +87,7 @@ def measured_traffic():
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    return float(t["hbm_bytes_per_launch"]) if t.get("source_sha256") == sha else None
+    return t if t.get("source_sha256") == sha else None
 
 
 def _timed(f, reps):
@@ -418,7 +418,9 @@ def main():
     # a launch covers the points still active in its round: use the mean pairs per launch
     pairs_per_launch = pairs_per_step * args.steps / max(launches, 1)
     achieved = FLOPS_FIELD_GRAD_TAN * pairs_per_launch / (kern_avg_ms * 1e-3) / 1e12
-    ceiling = FLOPS_FIELD_GRAD_TAN * VALU_LANE_INSTS_PER_S / VALU_PER_PAIR_TAN / 1e12
+    counters = measured_counters()
+    ceiling = (FLOPS_FIELD_GRAD_TAN * VALU_LANE_INSTS_PER_S / float(counters["valu_per_pair"]) / 1e12
+               if counters else None)
 
     extras = {}
     if not args.no_extras:
@@ -475,10 +477,11 @@ def main():
                    "tile_shape": [q["ppl"], q["waves"], q["tile_pixels"]],
                    "tile_shape_tangents": [qt["ppl"], qt["waves"], qt["tile_pixels"]]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": float(counters["hbm_bytes_per_launch"]) if counters else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": "k_field32c (FP32C bulk sum with mu-tangents)",
-                     "issue_ceiling": ceiling, "frac_of_issue_ceiling": achieved / ceiling,
+                     "issue_ceiling": ceiling, "frac_of_issue_ceiling": achieved / ceiling if ceiling else None,
                      "flops_per_pair": FLOPS_FIELD_GRAD_TAN, "pairs_per_launch": pairs_per_launch,
                      "avg_launch_ms": kern_avg_ms, "launches": launches},
         "cpu_baseline": cpu,
