@@ -261,12 +261,15 @@ enum { DBIE_TRACE_FIELD = 0, DBIE_TRACE_CURRENT = 1 };
  * outside the box gives a line of one point.
  *   xyz_out : device double [n_steps + 1][3][N]; point k of line i at [k][0..2][i], NaN after the end
  *   count   : device int32 [N], points per line (>= 1)
- * The context's points are moved during the call and restored before it returns; the call
- * synchronises `stream`. Uses the context's workspace (not concurrently with other calls on it). */
+ * The context's points are moved during the call and restored before it returns, also when it
+ * fails; the call synchronises `stream`. Uses the context's workspace (not concurrently with other
+ * calls on it). DBIE_E_INVAL for an output of more than 2^34 values ((n_steps + 1) x 3 x N). */
 DBIE_API int dbie_trace_lines(dbie_ctx* ctx, const dbie_lambda_grid* lambda_grid, const double* box, double ds,
                               int32_t n_steps, int32_t mode, double sense, double* xyz_out, int32_t* count,
                               void* stream);
 
+/* Free the context and every device allocation the library made for it (not the caller's workspace);
+ * the caller makes sure no work enqueued with it is still running. NULL is a no-op. */
 DBIE_API void dbie_destroy(dbie_ctx* ctx);
 
 /* Message of the last failure on ctx (or of the last failed dbie_init when ctx is NULL). */
