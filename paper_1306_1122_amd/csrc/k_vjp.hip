@@ -56,7 +56,9 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                                                const double* __restrict__ gpos,
                                                const double* __restrict__ coef, double* __restrict__ gW,
                                                int64_t slice_stride) {
-    __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef][kVjpPts];
+    // sc rows: Lambda[3], alpha[3], then -3 beta[3], -3 gx[3], -3 gy[3] and -Lambda^2/3 [3], so that
+    // H rho^-5 (beta + ...) is summed as (N - (Lambda^2/3) rho^2 cos t) rho^-5 (-3 beta + ...)
+    __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef + 3][kVjpPts];
     __shared__ int s_wide;
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
@@ -88,9 +90,15 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
             const double lmax = fmax(fabs(coef[i]), fmax(fabs(coef[N + i]), fabs(coef[2 * N + i])));
             if (!(lmax * sqrt(dxm * dxm + dym * dym + w * w) < kSincosBound)) s_wide = 1;
         }
-        for (int q = threadIdx.x; q < kVjpCoef * n; q += blockDim.x) {
+        for (int q = threadIdx.x; q < (kVjpCoef + 3) * n; q += blockDim.x) {
             const int r = q / n, e = q - r * n;
-            sc[r][e] = coef[r * N + i0 + e];
+            if (r < kVjpCoef) {
+                const double v = coef[r * N + i0 + e];
+                sc[r][e] = r >= 6 ? -3.0 * v : v;
+            } else {
+                const double l = coef[(r - kVjpCoef) * N + i0 + e];
+                sc[r][e] = l * l * (-1.0 / 3.0);
+            }
         }
         __syncthreads();
         double part[3] = {0.0, 0.0, 0.0};
@@ -117,10 +125,10 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                         c = flip_sign(c, sg);
                     }
                     const double nn = __builtin_fma(t, s, c);
-                    const double hh = __builtin_fma(t, t * c, -3.0 * nn);
+                    const double q = __builtin_fma(sc[kVjpCoef + p][e] * r2, c, nn);   // -H / 3
                     const double lin =
                         __builtin_fma(sc[9 + p][e], dx, __builtin_fma(sc[12 + p][e], dy, sc[6 + p][e]));
-                    part[p] = __builtin_fma(nn * ri3, sc[3 + p][e], __builtin_fma(hh * ri5, lin, part[p]));
+                    part[p] = __builtin_fma(nn * ri3, sc[3 + p][e], __builtin_fma(q * ri5, lin, part[p]));
                 }
             }
         };
