@@ -39,7 +39,7 @@ def case(seed):
     return G, B0, x0, y0, h, xyz, lam
 
 
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(48))
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_random_shape(seed, precision):
     G, B0, x0, y0, h, xyz, lam = case(seed)
@@ -57,7 +57,7 @@ def test_random_shape(seed, precision):
         assert v <= TOL[precision], (k, v)
 
 
-@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("seed", range(24))
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_random_shape_adjoint(seed, precision):
     """The adjoint on the same kind of random cases (nodal rule): dL/dB0 and dL/dlambda against the
