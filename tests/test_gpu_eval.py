@@ -276,3 +276,57 @@ def test_large_lambda_needs_range_reduction_and_nan_lambda_stays_local(precision
     Bs, dBs, tans = oracle.field(B0, 0.0, 0.0, 1.0, xyz, np.repeat(lam[:1], 3, axis=0), tangents=True)
     for k, r in (("B", Bs), ("dB", dBs), ("tan", tans)):
         assert rel(sc[k][0].cpu(), r) <= TOL[precision], k
+
+
+@pytest.mark.parametrize("G", [0, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_magnetograms_without_points(precision, G):
+    """seg may give a magnetogram no points (equal offsets): evaluation, adjoint and search over the
+    others are unchanged, and dL/dB0 of a magnetogram without points is zero (nodal rule and 9-node
+    elements; the adjoint of the others against the oracle's nodal VJP)."""
+    rng = np.random.default_rng(77)
+
+    class Bd:
+        pass
+
+    shapes = [(19, 15), (13, 31), (25, 7), (9, 9)]
+    npts = [0, 210, 0, 95]
+    bds, xyzs = [], []
+    for (nx, ny), n in zip(shapes, npts):
+        bd = Bd()
+        bd.B0 = rng.normal(size=(3, ny, nx))
+        bd.x0, bd.y0, bd.h = 0.0, 0.0, 1.0
+        bds.append(bd)
+        xyzs.append(np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0.4, 15, n)]))
+    xyz = np.concatenate(xyzs, axis=1)
+    n = xyz.shape[1]
+    lam = rng.uniform(-0.4, 0.4, size=(3, n))
+    seg = np.concatenate([[0], np.cumsum(npts)])
+    ctx = ctx_for(bds, xyz, precision, seg=seg, quad_points=G)
+    out = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+    gB, gdB = rng.normal(size=(3, n)), rng.normal(size=(9, n))
+    g = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB))
+    parts = D.split_gB0(ctx, g["gB0"])
+    torch.cuda.synchronize()
+    glam = g["glambda"].cpu().numpy()
+    for b, bd in enumerate(bds):
+        s, e = seg[b], seg[b + 1]
+        if s == e:
+            assert torch.count_nonzero(parts[b]).item() == 0, b
+            continue
+        if G:
+            B, dB, tan = oracle.field_quad9(bd.B0, 0.0, 0.0, 1.0, xyz[:, s:e], lam[:, s:e], G=G, tangents=True)
+        else:
+            B, dB, tan = oracle.field(bd.B0, 0.0, 0.0, 1.0, xyz[:, s:e], lam[:, s:e], tangents=True)
+        for name, ref in (("B", B), ("dB", dB), ("tan", tan)):
+            assert rel(out[name][:, s:e].cpu(), ref) <= TOL[precision], (b, name)
+        assert torch.count_nonzero(parts[b]).item() > 0, b
+        if G:
+            continue
+        gB0, gl, _ = oracle.vjp(bd.B0, 0.0, 0.0, 1.0, xyz[:, s:e], lam[:, s:e], gB[:, s:e], gdB[:, s:e])
+        assert rel(parts[b].cpu(), gB0) <= TOL[precision], b
+        assert rel(glam[:, s:e], gl) <= TOL[precision], b
+    r = D.dbie_solve_lambda(ctx, T(np.abs(lam)), method="lm", max_trials=4, eps=1e-3)
+    torch.cuda.synchronize()
+    tr = r["trials"].cpu().numpy()
+    assert tr.min() >= 1 and tr.max() <= 4
