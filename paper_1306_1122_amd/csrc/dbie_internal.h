@@ -286,11 +286,13 @@ bool field32c_shape_supported(F32Shape shape);
 int field32c_shapes(F32Shape* out, int max);   // the instantiated shapes; returns their number
 
 // Over idx[0 .. n) (n = *n_dev when n_dev is given, else n_idx), or over every point without idx.
-// acc holds S slices of [L][kAcc][N] (the pixel split of the FP32C pass), summed here in order.
+// acc holds S slices of [L][kAcc][N] (the pixel split of the bulk pass), summed here in order; with
+// many slices and few points they are first summed in place into slice 0 by a pass with one thread
+// per (point, trial, row) (same order, same result).
 hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const double* gpos, const double* gB,
                            Geo geo, const double* lam,
                            const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
-                           int32_t S, const double* acc,
+                           int32_t S, double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s);
 

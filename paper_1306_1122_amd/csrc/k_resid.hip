@@ -149,14 +149,38 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict_
     }
 }
 
+// The pixel slices of the first `rows` rows summed in place into slice 0, in slice order (the
+// finalize pass then reads one slice and gets the same sums). One thread per (point, trial, row):
+// with few points and many slices the finalize pass's own loop (S x rows loads per thread, one
+// thread per point) has too few threads in flight to hide the memory latency.
+__global__ __launch_bounds__(256) void k_reduce_slices(const int32_t* __restrict__ idx, int64_t n_idx,
+                                                       const int32_t* __restrict__ n_dev, int64_t N, int32_t L,
+                                                       int32_t S, double* __restrict__ acc) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (n_dev ? (int64_t)*n_dev : n_idx)) return;
+    const int64_t i = idx ? (int64_t)idx[j] : j;
+    const int64_t o = ((int64_t)blockIdx.y * kAcc + blockIdx.z) * N + i;   // (trial, row, point)
+    const int64_t slice = (int64_t)L * kAcc * N;
+    double a = acc[o];
+    for (int z = 1; z < S; ++z) a += acc[z * slice + o];
+    acc[o] = a;
+}
+
 hipError_t launch_finalize(const BoundaryDev* bnd, const double* B0d, const double* gpos, const double* gB,
                            Geo geo, const double* lam,
                            const int32_t* idx, int64_t n_idx, const int32_t* n_dev, int64_t N, int32_t L,
-                           int32_t S, const double* acc,
+                           int32_t S, double* acc,
                            bool add_near, bool tan, double dvds, double* B, double* dB, double* fg,
                            double* tanout, hipStream_t s) {
     if (n_idx == 0) return hipSuccess;
     const dim3 grid((unsigned)((n_idx + 255) / 256), (unsigned)L);
+    if (S >= 4 && n_idx * L <= ((int64_t)1 << 18)) {
+        hipLaunchKernelGGL(k_reduce_slices, dim3(grid.x, grid.y, (unsigned)(tan ? kAcc : kAccField)), dim3(256), 0,
+                           s, idx, n_idx, n_dev, N, L, S, acc);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        S = 1;
+    }
 #define DBIE_FIN(T, NR)                                                                            \
     hipLaunchKernelGGL((k_finalize<T, NR>), grid, dim3(256), 0, s, bnd, B0d, gpos, gB, geo, lam, idx, n_idx, \
                        n_dev, N, L, S, acc, dvds, B, dB, fg, tanout)
