@@ -78,13 +78,12 @@ __global__ void k_trace_init(int64_t N, const double* __restrict__ seeds, Box bo
 }
 
 // Stage st (0..3) positions y = x + c_st ds k_prev (c = 0, 1/2, 1/2, 1); a line whose stage point
-// leaves the box is marked to stop (ok = 0) and is evaluated at x instead. Writes the points to
-// evaluate and their lambda.
-__global__ void k_trace_stage(int64_t N, int st, double ds, Box box, LamGrid g, const double* __restrict__ x,
-                              const double* __restrict__ kprev, const int32_t* __restrict__ alive,
-                              int32_t* __restrict__ ok, double* __restrict__ pts, double* __restrict__ lam) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+// leaves the box is marked to stop (ok = 0) and is evaluated at x instead. Writes the point to
+// evaluate and its lambda.
+__device__ __forceinline__ void trace_stage(int64_t i, int64_t N, int st, double ds, const Box& box, const LamGrid& g,
+                                            const double* __restrict__ x, const double* __restrict__ kprev,
+                                            const int32_t* __restrict__ alive, int32_t* __restrict__ ok,
+                                            double* __restrict__ pts, double* __restrict__ lam) {
     double y[3];
     int32_t k = st == 0 ? alive[i] : ok[i];
     const double c = st == 3 ? ds : 0.5 * ds;
@@ -101,10 +100,9 @@ __global__ void k_trace_stage(int64_t N, int st, double ds, Box box, LamGrid g, 
 
 // Direction of stage st from the evaluated field: kprev = sense v / |v|; ksum accumulates
 // k1 + 2 k2 + 2 k3 + k4 in that order.
-__global__ void k_trace_dir(int64_t N, int st, double sense, int current, const double* __restrict__ B,
-                            const double* __restrict__ dB, double* __restrict__ kprev, double* __restrict__ ksum) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__device__ __forceinline__ void trace_dir(int64_t i, int64_t N, int st, double sense, int current,
+                                          const double* __restrict__ B, const double* __restrict__ dB,
+                                          double* __restrict__ kprev, double* __restrict__ ksum) {
     double v[3];
     if (current) {
         v[0] = dB[7 * N + i] - dB[5 * N + i];
@@ -124,11 +122,10 @@ __global__ void k_trace_dir(int64_t N, int st, double sense, int current, const 
 }
 
 // x <- x + ds/6 (k1 + 2 k2 + 2 k3 + k4) for the lines still going; record point `step`.
-__global__ void k_trace_advance(int64_t N, int32_t step, double ds, const int32_t* __restrict__ ok,
-                                const double* __restrict__ ksum, int32_t* __restrict__ alive,
-                                double* __restrict__ x, double* __restrict__ out, int32_t* __restrict__ count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__device__ __forceinline__ void trace_advance(int64_t i, int64_t N, int32_t step, double ds,
+                                              const int32_t* __restrict__ ok, const double* __restrict__ ksum,
+                                              int32_t* __restrict__ alive, double* __restrict__ x,
+                                              double* __restrict__ out, int32_t* __restrict__ count) {
     double xn[3];
     bool good = ok[i] != 0;
     for (int p = 0; p < 3; ++p) {
@@ -136,12 +133,30 @@ __global__ void k_trace_advance(int64_t N, int32_t step, double ds, const int32_
         good = good && isfinite(xn[p]);
     }
     alive[i] = good ? 1 : 0;
-    if (!good) return;
-    for (int p = 0; p < 3; ++p) {
-        x[p * N + i] = xn[p];
-        out[((int64_t)step * 3 + p) * N + i] = xn[p];
+    if (good) {
+        for (int p = 0; p < 3; ++p) {
+            x[p * N + i] = xn[p];
+            out[((int64_t)step * 3 + p) * N + i] = xn[p];
+        }
+        count[i] += 1;
     }
-    count[i] += 1;
+}
+
+// The per-line work between two evaluations in one launch, in this order: the direction of stage
+// dir_st (>= 0) from the field just evaluated, the advance of step adv_step (> 0) once the step's
+// four directions are in, and the positions and lambda of stage stage_st (>= 0) to evaluate next.
+// Every line touches only its own entries, so this equals the separate passes.
+__global__ void k_trace_fused(int64_t N, int dir_st, int32_t adv_step, int stage_st, double ds, double sense,
+                              int current, Box box, LamGrid g, const double* __restrict__ B,
+                              const double* __restrict__ dB, double* __restrict__ kprev, double* __restrict__ ksum,
+                              int32_t* __restrict__ ok, int32_t* __restrict__ alive, double* __restrict__ x,
+                              double* __restrict__ out, int32_t* __restrict__ count, double* __restrict__ pts,
+                              double* __restrict__ lam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (dir_st >= 0) trace_dir(i, N, dir_st, sense, current, B, dB, kprev, ksum);
+    if (adv_step > 0) trace_advance(i, N, adv_step, ds, ok, ksum, alive, x, out, count);
+    if (stage_st >= 0) trace_stage(i, N, stage_st, ds, box, g, x, kprev, alive, ok, pts, lam);
 }
 
 }  // namespace dbie
@@ -206,21 +221,24 @@ extern "C" int dbie_trace_lines(dbie_ctx* c, const dbie_lambda_grid* lg, const d
         hipLaunchKernelGGL(k_trace_init, dim3((unsigned)blocks), dim3(256), 0, s, N, seeds, bx, total, xyz_out, count,
                            alive, x);
         TR_HIP(hipGetLastError());
+        // before each evaluation: the previous stage's direction (or the previous step's last
+        // direction and its advance), then the positions of this stage
+        auto between = [&](int dir_st, int32_t adv_step, int stage_st) -> int {
+            hipLaunchKernelGGL(k_trace_fused, dim3(gN), dim3(256), 0, s, N, dir_st, adv_step, stage_st, ds, sense,
+                               cur ? 1 : 0, bx, g, B, dB, kprev, ksum, ok, alive, x, xyz_out, count, pts, lam);
+            TR_HIP(hipGetLastError());
+            return DBIE_OK;
+        };
         for (int32_t step = 1; step <= n_steps; ++step) {
             for (int st = 0; st < 4; ++st) {
-                hipLaunchKernelGGL(k_trace_stage, dim3(gN), dim3(256), 0, s, N, st, ds, bx, g, x, kprev, alive, ok,
-                                   pts, lam);
-                TR_HIP(hipGetLastError());
+                const int dir_st = st > 0 ? st - 1 : (step > 1 ? 3 : -1);
+                if (int r = between(dir_st, st == 0 && step > 1 ? step - 1 : 0, st)) return r;
                 TR_HIP(ctx_prep_points(c, flag, s));
                 if (int r = eval_set(c, lam, fp64, false, nullptr, B, cur ? dB : nullptr, nullptr, nullptr, s)) return r;
-                hipLaunchKernelGGL(k_trace_dir, dim3(gN), dim3(256), 0, s, N, st, sense, cur ? 1 : 0, B, dB, kprev,
-                                   ksum);
-                TR_HIP(hipGetLastError());
             }
-            hipLaunchKernelGGL(k_trace_advance, dim3(gN), dim3(256), 0, s, N, step, ds, ok, ksum, alive, x, xyz_out,
-                               count);
-            TR_HIP(hipGetLastError());
         }
+        if (n_steps > 0)
+            if (int r = between(3, n_steps, -1)) return r;
         return DBIE_OK;
     };
     const int rc = steps();
