@@ -380,6 +380,14 @@ class PointProblem:
         res = residuals(out[0], out[1], self.h, self.c)
         return out, res
 
+    def lm_eval(self, mu3):
+        """One trial of the gradient form at mu = lambda^2: the residual vector u (`residuals`), its
+        Jacobian du/dmu (`residual_jacobian`, from the tangents at lambda = sqrt(mu)), Phi, rho and
+        the status."""
+        (B, dB, tan), res = self.eval(np.sqrt(np.asarray(mu3, np.float64)), tangents=True)
+        Jac = residual_jacobian(B, dB, tan, self.h, self.c)[:, :, 0]
+        return res["u"][:, 0], Jac, float(res["Phi"][0]), float(res["rho"][0]), int(res["status"][0])
+
 
 def default_nm_step(boundary_nx: int, boundary_ny: int, h: float) -> float:
     """Initial simplex edge 1/L, L = the magnetogram's longer side in length units."""
@@ -423,12 +431,17 @@ def lm_direction(Jac, u, nu):
     return np.linalg.solve(A + nu * np.diag(dg), -gvec)
 
 
-def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu0: float = 1e-3):
-    """Projected Levenberg-Marquardt on Phi(mu) = |u(mu)|^2, mu in [0, mu_cap]^3.
+def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu0: float = 1e-3,
+                        radius0: float = math.inf):
+    """Projected Levenberg-Marquardt on Phi(mu) = |u(mu)|^2, mu in [0, mu_cap]^3, with a trust region
+    in lambda = sqrt(mu).
 
     evalfun(mu) -> (u [4], Jac [4, 3] = du/dmu, Phi, rho, status); one call is one trial.
-    Start at mu0; each iteration solves the damped normal equations, projects into the box,
-    evaluates, and accepts if Phi falls (nu /= 10) or rejects (nu *= 10). Stops when rho <= eps or
+    Start at mu0; each iteration solves the damped normal equations for a step d, and the proposal
+    mu + d is clipped, per component, into the box where sqrt(mu) lies within the radius Delta of the
+    accepted point's sqrt(mu) and inside [0, sqrt(mu_cap)]. The proposal is evaluated and accepted if
+    Phi falls (nu /= 10, Delta doubled up to sqrt(mu_cap)) or rejected (nu *= 10, Delta halved).
+    Delta starts at radius0; radius0 = inf leaves only the box [0, mu_cap]. Stops when rho <= eps or
     after `budget` trials. Returns (mu, status, trials, rho, Phi)."""
     mu = np.asarray(mu0, np.float64).copy()
     u, Jac, Phi, rho, st = evalfun(mu)
@@ -438,9 +451,14 @@ def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu
     if rho <= eps:
         return mu, ST_CONVERGED, trials, rho, Phi
     nu = nu0
+    cap = math.sqrt(mu_cap)
+    radius = radius0
     while trials < budget:
         d = lm_direction(Jac, u, nu)
-        mu_new = np.clip(mu + d, 0.0, mu_cap)
+        lam = np.sqrt(mu)
+        lo = np.maximum(lam - radius, 0.0)
+        hi = np.minimum(lam + radius, cap)
+        mu_new = np.minimum(np.maximum(mu + d, lo * lo), hi * hi)
         u2, Jac2, Phi2, rho2, st2 = evalfun(mu_new)
         trials += 1
         if rho2 <= eps:
@@ -448,27 +466,22 @@ def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu
         if Phi2 < Phi:
             mu, u, Jac, Phi, rho = mu_new, u2, Jac2, Phi2, rho2
             nu = nu / 10.0
+            radius = min(2.0 * radius, cap)
         else:
             nu = nu * 10.0
+            radius = 0.5 * radius
     return mu, ST_BUDGET, trials, rho, Phi
 
 
-def solve_point_lm(prob: PointProblem, lam0, budget: int, eps: float, lam_cap: float,
-                   nu0: float = 1e-3) -> Tuple[np.ndarray, int, int, float]:
-    """Gradient form for one point: LM in mu = lambda^2 >= 0 with the residual Jacobian from the
-    tangents; one trial = one evaluation of (B, grad B, tangents). Returns (|lambda*|, status,
-    trials, rho*)."""
-
-    def evalfun(mu):
-        (B, dB, tan), res = prob.eval(np.sqrt(mu), tangents=True)
-        Jac = residual_jacobian(B, dB, tan, prob.h, prob.c)[:, :, 0]
-        st = int(res["status"][0])
-        return res["u"][:, 0], Jac, float(res["Phi"][0]), float(res["rho"][0]), st
-
-    mu, st, trials, rho, _ = levenberg_marquardt(evalfun, np.asarray(lam0, np.float64) ** 2, budget,
-                                                 eps, lam_cap * lam_cap, nu0)
-    if st == ST_J_ZERO:
-        st = ST_BUDGET
+def solve_point_lm(prob, lam0, budget: int, eps: float, lam_cap: float, nu0: float = 1e-3,
+                   radius0: float = math.inf) -> Tuple[np.ndarray, int, int, float]:
+    """Gradient form for one point: LM in mu = lambda^2 >= 0 (`levenberg_marquardt`, box [0, cap^2],
+    trust radius radius0 in lambda); one trial = one call of prob.lm_eval(mu), which for a DBIE point
+    is one evaluation of (B, grad B, tangents) at lambda = sqrt(mu). Returns (|lambda*|, status,
+    trials, rho*); the status is CONVERGED, BUDGET (J_ZERO points included: f = 0 is a finite
+    residual), or the residual status of a start with non-finite Phi (DEGENERATE, NONFINITE)."""
+    mu, st, trials, rho, _ = levenberg_marquardt(prob.lm_eval, np.asarray(lam0, np.float64) ** 2, budget,
+                                                 eps, lam_cap * lam_cap, nu0, radius0)
     return np.sqrt(mu), st, trials, rho
 
 

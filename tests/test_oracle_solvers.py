@@ -107,6 +107,149 @@ def test_lm_phi_is_monotone_on_a_dbie_point():
 # ------------------------------------------------------------------------------------------------
 # the DBIE per-point solvers
 # ------------------------------------------------------------------------------------------------
+class _LinearMuProblem:
+    """A stand-in for PointProblem in the gradient form: the residual vector is linear in mu,
+    u(mu) = A mu - b, with orthogonal columns of A, so that the least-squares minimum over the box
+    0 <= mu <= cap^2 is the unconstrained minimum clipped per component. Records every mu it sees."""
+
+    def __init__(self, mu_star, status=oracle.ST_BUDGET, h=1.0):
+        q, _ = np.linalg.qr(np.random.default_rng(5).normal(size=(4, 4)))
+        self.A = q[:, :3] * np.array([2.0, 0.7, 1.3])
+        self.b = self.A @ np.asarray(mu_star, np.float64) + 0.3 * q[:, 3]   # residual 0.3 at the minimum
+        self.status, self.h, self.seen = status, h, []
+
+    def lm_eval(self, mu):
+        self.seen.append(np.array(mu, np.float64))
+        u = self.A @ mu - self.b
+        return u, self.A, float(u @ u), float(np.max(np.abs(u))), self.status
+
+
+def test_solve_point_lm_returns_lambda_of_the_box_constrained_minimum():
+    """Least squares in mu with one component beyond cap^2: the wrapper starts at mu = lambda0^2 and
+    returns sqrt of the minimum clipped to [0, cap^2] (cap = 1.2 tells cap^2 = 1.44 from cap, and
+    lambda from mu), with status BUDGET after exactly `budget` trials when eps = 0."""
+    mu_star = np.array([0.25, 2.0, 0.5])
+    cap = 1.2
+    prob = _LinearMuProblem(mu_star)
+    lam, st, trials, rho = oracle.solve_point_lm(prob, np.array([-0.3, 0.0, 0.1]), 60, 0.0, cap, radius0=0.1)
+    np.testing.assert_array_equal(prob.seen[0], np.array([-0.3, 0.0, 0.1]) ** 2)
+    np.testing.assert_allclose(lam, np.sqrt([0.25, cap * cap, 0.5]), rtol=1e-9)
+    assert st == oracle.ST_BUDGET and trials == 60 == len(prob.seen)
+    # every proposal stayed in the box
+    assert all(np.all(m >= 0.0) and np.all(m <= cap * cap) for m in prob.seen)
+    # rho is the residual at the returned point
+    assert abs(rho - np.max(np.abs(prob.A @ lam ** 2 - prob.b))) < 1e-12
+
+
+def test_solve_point_lm_trust_radius_is_in_lambda():
+    """From lambda = 0 with a full Gauss-Newton step beyond the radius Delta0 in every component, the
+    first proposal is sqrt(mu) = Delta0 in each (a radius applied to mu would give sqrt(Delta0));
+    after that acceptance the radius doubles, so the second proposal moves sqrt(mu) by at most
+    2 Delta0; with radius0 = inf the first proposal is the damped step itself."""
+    prob = _LinearMuProblem([0.25, 0.9, 0.5])
+    oracle.solve_point_lm(prob, np.zeros(3), 3, 0.0, 1.2, radius0=0.1)
+    np.testing.assert_allclose(np.sqrt(prob.seen[1]), [0.1, 0.1, 0.1], rtol=1e-15)
+    step2 = np.sqrt(prob.seen[2]) - np.sqrt(prob.seen[1])
+    assert np.all(step2 <= 0.2 * (1 + 1e-12)) and np.any(step2 >= 0.2 * (1 - 1e-12))
+    free = _LinearMuProblem([0.25, 0.9, 0.5])
+    oracle.solve_point_lm(free, np.zeros(3), 2, 0.0, 1.2)
+    d = oracle.lm_direction(free.A, -free.b, 1e-3)
+    np.testing.assert_allclose(free.seen[1], np.clip(d, 0.0, 1.44), rtol=1e-15)
+
+
+def test_solve_point_lm_status_mapping():
+    # converged at the start: one trial, |lambda0| returned
+    prob = _LinearMuProblem([0.25, 0.9, 0.5])
+    lam, st, tr, rho = oracle.solve_point_lm(prob, np.array([-0.5, 0.3, 0.0]), 20, 1e3, 2.0)
+    assert st == oracle.ST_CONVERGED and tr == 1
+    np.testing.assert_array_equal(lam, [0.5, 0.3, 0.0])
+    # J = 0 at every trial is not a failure of the point: BUDGET
+    prob = _LinearMuProblem([0.25, 0.9, 0.5], status=oracle.ST_J_ZERO)
+    assert oracle.solve_point_lm(prob, np.zeros(3), 7, 0.0, 2.0)[1:3] == (oracle.ST_BUDGET, 7)
+
+    class Degenerate:
+        def __init__(self, st):
+            self.st = st
+
+        def lm_eval(self, mu):
+            return np.zeros(4), np.zeros((4, 3)), math.inf, math.inf, self.st
+
+    for code in (oracle.ST_DEGENERATE, oracle.ST_NONFINITE):
+        lam, st, tr, rho = oracle.solve_point_lm(Degenerate(code), np.array([0.2, 0.0, 0.0]), 9, 1e-4, 2.0)
+        assert st == code and tr == 1 and rho == math.inf
+
+
+def test_lm_eval_jacobian_is_the_mu_derivative():
+    """PointProblem.lm_eval takes mu = lambda^2: its Jacobian (from the tangents, pinned separately)
+    equals central differences of its own residual vector in that argument (had it taken lambda, the
+    differences would be 2 lambda times larger)."""
+    w = config1()
+    b = w.boundaries[0]
+    prob = oracle.PointProblem(b.B0, b.x0, b.y0, b.h, w.xyz[:, 200])
+    mu = np.array([1.7, 0.6, 2.3])
+    u, Jac, Phi, rho, st = prob.lm_eval(mu)
+    assert abs(Phi - u @ u) < 1e-14 and st == oracle.ST_BUDGET
+    e = 1e-6
+    for p in range(3):
+        d = np.zeros(3)
+        d[p] = e
+        fd = (prob.lm_eval(mu + d)[0] - prob.lm_eval(mu - d)[0]) / (2 * e)
+        np.testing.assert_allclose(Jac[:, p], fd, rtol=1e-6, atol=1e-9 * np.max(np.abs(Jac)))
+
+
+class _QuadraticLambdaProblem:
+    """A stand-in for PointProblem in the derivative-free form: Phi(lambda) = |lambda - c|^2 + phi0,
+    rho = sqrt(Phi); records every lambda it evaluates."""
+
+    def __init__(self, c, phi0=0.01, status=oracle.ST_BUDGET, conv_at=None):
+        self.c, self.phi0, self.status, self.conv_at, self.seen = np.asarray(c, np.float64), phi0, status, conv_at, []
+
+    def eval(self, lam):
+        self.seen.append(np.array(lam, np.float64))
+        phi = float(np.sum((lam - self.c) ** 2) + self.phi0)
+        rho = math.sqrt(phi)
+        if self.conv_at is not None and len(self.seen) == self.conv_at:
+            rho = 0.0
+        return None, dict(Phi=np.array([phi]), rho=np.array([rho]), status=np.array([self.status]))
+
+
+def test_solve_point_nm_cap_counts_trials_without_evaluating():
+    """The optimum lies beyond the cap in x: proposals outside |lambda_p| <= cap cost a trial but are
+    never evaluated (Phi = +inf), the result is the best evaluated (hence feasible) vertex, and the
+    status is BUDGET after exactly `budget` trials."""
+    cap = 1.0
+    prob = _QuadraticLambdaProblem([3.0, 0.2, -0.1])
+    lam, st, trials, rho = oracle.solve_point_nm(prob, np.zeros(3), 80, 1e-6, 0.25, cap)
+    assert st == oracle.ST_BUDGET and trials == 80
+    assert all(np.all(np.abs(x) <= cap) for x in prob.seen)
+    assert len(prob.seen) < trials                      # some trials were infeasible proposals
+    phis = [float(np.sum((x - prob.c) ** 2) + 0.01) for x in prob.seen]
+    k = int(np.argmin(phis))
+    np.testing.assert_array_equal(lam, prob.seen[k])
+    assert rho == math.sqrt(phis[k])
+    # it moved to the face x = cap of the box, near the best feasible value (2^2 + 0.01)
+    assert lam[0] > 0.9 and phis[k] < 4.01 + 0.05 < phis[0]
+
+
+def test_solve_point_nm_status_mapping():
+    # a trial with rho <= eps ends the search with that trial's lambda
+    prob = _QuadraticLambdaProblem([0.3, 0.2, 0.1], conv_at=6)
+    lam, st, tr, rho = oracle.solve_point_nm(prob, np.zeros(3), 50, 1e-4, 0.25, 5.0)
+    assert st == oracle.ST_CONVERGED and tr == 6 and rho == 0.0
+    np.testing.assert_array_equal(lam, prob.seen[5])
+    # J = 0 at the best point: BUDGET
+    prob = _QuadraticLambdaProblem([0.3, 0.2, 0.1], status=oracle.ST_J_ZERO)
+    assert oracle.solve_point_nm(prob, np.zeros(3), 12, 1e-4, 0.25, 5.0)[1:3] == (oracle.ST_BUDGET, 12)
+
+    class Degenerate:
+        def eval(self, lam):
+            return None, dict(Phi=np.array([math.inf]), rho=np.array([math.inf]),
+                              status=np.array([oracle.ST_DEGENERATE]))
+
+    lam, st, tr, rho = oracle.solve_point_nm(Degenerate(), np.zeros(3), 9, 1e-4, 0.25, 5.0)
+    assert st == oracle.ST_DEGENERATE and tr == 9
+
+
 def test_point_solvers_are_deterministic_and_consistent():
     w = config1()
     b = w.boundaries[0]
