@@ -124,10 +124,17 @@ typedef struct {
                              (with B and fg both NULL only the points that converged are re-evaluated,
                              and those that fail the FP64 test become DBIE_ST_BUDGET) */
     int32_t use_graph;    /* 1: replay the rounds from a captured HIP graph (bitwise the same results) */
+    double lm_radius;     /* Levenberg-Marquardt trust radius in lambda at the start: every proposal keeps
+                             each sqrt(mu_p) within the radius of the accepted point's (and in [0, cap]);
+                             the radius doubles on acceptance (up to the cap) and halves on rejection.
+                             0 means the simplex edge (init_step, or 1 / the longer side); +inf means no
+                             trust region (proposals only clipped to [0, cap^2]); negative or NaN is
+                             DBIE_E_INVAL. Not used by Nelder-Mead. */
 } dbie_solve_opts;
 
 /* Fill defaults: FP32C, radius 2, dV/dSigma = 1/6, no tuning, nodal sum / Nelder-Mead, 50 trials, eps 1e-4,
- * default step and cap, FP64 acceptance on, graph replay on. Return DBIE_OK, or DBIE_E_INVAL for NULL. */
+ * default step and cap, FP64 acceptance on, graph replay on, LM trust radius = the simplex edge. Return
+ * DBIE_OK, or DBIE_E_INVAL for NULL. */
 DBIE_API int dbie_default_options(dbie_options* opt);
 DBIE_API int dbie_default_solve_opts(dbie_solve_opts* opt);
 

@@ -441,8 +441,9 @@ def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu
     mu + d is clipped, per component, into the box where sqrt(mu) lies within the radius Delta of the
     accepted point's sqrt(mu) and inside [0, sqrt(mu_cap)]. The proposal is evaluated and accepted if
     Phi falls (nu /= 10, Delta doubled up to sqrt(mu_cap)) or rejected (nu *= 10, Delta halved).
-    Delta starts at radius0; radius0 = inf leaves only the box [0, mu_cap]. Stops when rho <= eps or
-    after `budget` trials. Returns (mu, status, trials, rho, Phi)."""
+    Delta starts at radius0; radius0 = inf means no trust region: every proposal is mu + d clipped to
+    the box [0, mu_cap] and Delta never changes. Stops when rho <= eps or after `budget` trials.
+    Returns (mu, status, trials, rho, Phi)."""
     mu = np.asarray(mu0, np.float64).copy()
     u, Jac, Phi, rho, st = evalfun(mu)
     trials = 1
@@ -455,10 +456,13 @@ def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu
     radius = radius0
     while trials < budget:
         d = lm_direction(Jac, u, nu)
-        lam = np.sqrt(mu)
-        lo = np.maximum(lam - radius, 0.0)
-        hi = np.minimum(lam + radius, cap)
-        mu_new = np.minimum(np.maximum(mu + d, lo * lo), hi * hi)
+        if math.isinf(radius):
+            mu_new = np.clip(mu + d, 0.0, mu_cap)
+        else:
+            lam = np.sqrt(mu)
+            lo = np.maximum(lam - radius, 0.0)
+            hi = np.minimum(lam + radius, cap)
+            mu_new = np.minimum(np.maximum(mu + d, lo * lo), hi * hi)
         u2, Jac2, Phi2, rho2, st2 = evalfun(mu_new)
         trials += 1
         if rho2 <= eps:
@@ -466,10 +470,12 @@ def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu
         if Phi2 < Phi:
             mu, u, Jac, Phi, rho = mu_new, u2, Jac2, Phi2, rho2
             nu = nu / 10.0
-            radius = min(2.0 * radius, cap)
+            if not math.isinf(radius):
+                radius = min(2.0 * radius, cap)
         else:
             nu = nu * 10.0
-            radius = 0.5 * radius
+            if not math.isinf(radius):
+                radius = 0.5 * radius
     return mu, ST_BUDGET, trials, rho, Phi
 
 

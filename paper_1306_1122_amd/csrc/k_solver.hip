@@ -208,12 +208,14 @@ struct LMDev {
     double* u;        // [4][N]
     double* jac;      // [12][N]
     double* nu;       // [N]
+    double* rad;      // [N] trust radius in lambda (+inf: none)
     int32_t* phase;   // [N]
 };
 
 struct SolveCfg {
     int32_t method, max_trials;
     double eps, step, cap, dvds, nu0;
+    double radius0;   // LM trust radius at the start; 0: the simplex edge; +inf: none
 };
 
 __device__ __forceinline__ double cap_of(const SolveCfg& c, const BoundaryDev& bd) {
@@ -446,6 +448,7 @@ __global__ void k_solve_init(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
         }
         lm.phase[i] = 0;
         lm.nu[i] = cfg.nu0;
+        lm.rad[i] = cfg.radius0 > 0.0 ? cfg.radius0 : step_of(cfg, bd);
     }
 }
 
@@ -570,6 +573,8 @@ __global__ void k_lm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
         return;
     }
     double nu = lm.nu[i];
+    double rad = lm.rad[i];
+    const double cap = cap_of(cfg, bd);
     const bool accept = (phase == 0) || (R.Phi < lm.Phi[i]);
     if (accept) {
         double jac[12];
@@ -579,11 +584,16 @@ __global__ void k_lm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
         lm.rho[i] = R.rho;
         for (int q = 0; q < 4; ++q) lm.u[q * N + i] = R.u[q];
         for (int r = 0; r < 12; ++r) lm.jac[r * N + i] = jac[r];
-        if (phase != 0) nu = nu / 10.0;
+        if (phase != 0) {
+            nu = nu / 10.0;
+            if (!isinf(rad)) rad = fmin(2.0 * rad, cap);
+        }
     } else {
         nu = nu * 10.0;
+        if (!isinf(rad)) rad = 0.5 * rad;
     }
     lm.nu[i] = nu;
+    lm.rad[i] = rad;
     lm.phase[i] = 1;
     double mu[3];
     for (int p = 0; p < 3; ++p) {
@@ -599,10 +609,19 @@ __global__ void k_lm_update(SolveCfg cfg, const BoundaryDev* __restrict__ bnd,
     for (int r = 0; r < 12; ++r) jac[r] = lm.jac[r * N + i];
     for (int q = 0; q < 4; ++q) u[q] = lm.u[q * N + i];
     lm_direction(jac, u, nu, d);
-    const double cap = cap_of(cfg, bd);
+    // the proposal mu + d, clipped per component to where sqrt(mu) lies within rad of the accepted
+    // point's and inside [0, cap] (with no trust region: to [0, cap^2])
     const double cap2 = cap * cap;
     for (int p = 0; p < 3; ++p) {
-        const double m = fmin(fmax(mu[p] + d[p], 0.0), cap2);
+        double m;
+        if (isinf(rad)) {
+            m = fmin(fmax(mu[p] + d[p], 0.0), cap2);
+        } else {
+            const double l = sqrt(mu[p]);
+            const double lo = fmax(l - rad, 0.0);
+            const double hi = fmin(l + rad, cap);
+            m = fmin(fmax(mu[p] + d[p], lo * lo), hi * hi);
+        }
         lm.mu_try[p * N + i] = m;
         C.lam_cur[p * N + i] = sqrt(m);
     }
@@ -703,7 +722,7 @@ void solver_free(SolverState& s) {
 // nb magnetograms, max_rounds trials and per32 points per FP32C tile.
 struct SolverOffsets {
     size_t lam, best, bphi, bst, tr, st, act, B, dB, tan, fg, conv, V, F, Xr, Fr, ph, aux;
-    size_t mu, mut, phi, rho, u, jac, nu, lph, list, bsum, nact, rnd, cnt, rank, o32, o64, seg, t32, t64;
+    size_t mu, mut, phi, rho, u, jac, nu, rad, lph, list, bsum, nact, rnd, cnt, rank, o32, o64, seg, t32, t64;
     int64_t max32, max64;
     int32_t nblk;
     size_t bytes;
@@ -725,7 +744,7 @@ static SolverOffsets solver_layout(int64_t N, int32_t nb, int32_t max_rounds, in
     o.Fr = L.take<double>(n), o.ph = L.take<int32_t>(n), o.aux = L.take<int32_t>(n);
     o.mu = L.take<double>(3 * n), o.mut = L.take<double>(3 * n), o.phi = L.take<double>(n),
     o.rho = L.take<double>(n), o.u = L.take<double>(4 * n), o.jac = L.take<double>(12 * n),
-    o.nu = L.take<double>(n), o.lph = L.take<int32_t>(n);
+    o.nu = L.take<double>(n), o.rad = L.take<double>(n), o.lph = L.take<int32_t>(n);
     o.list = L.take<int32_t>(n), o.bsum = L.take<int32_t>((size_t)o.nblk + 1), o.nact = L.take<int32_t>(1),
     o.rnd = L.take<int32_t>(1), o.cnt = L.take<int32_t>((size_t)nb), o.rank = L.take<int32_t>((size_t)nb + 1),
     o.o32 = L.take<int32_t>((size_t)nb + 1), o.o64 = L.take<int32_t>((size_t)nb + 1),
@@ -785,7 +804,7 @@ static int solver_bufs(dbie_ctx* c, int32_t max_rounds, bool lm_mode, SolverBufs
     b.nm = NMDev{(double*)D(o.V), (double*)D(o.F), (double*)D(o.Xr), (double*)D(o.Fr), (int32_t*)D(o.ph),
                  (int32_t*)D(o.aux)};
     b.lm = LMDev{(double*)D(o.mu), (double*)D(o.mut), (double*)D(o.phi), (double*)D(o.rho), (double*)D(o.u),
-                 (double*)D(o.jac), (double*)D(o.nu), (int32_t*)D(o.lph)};
+                 (double*)D(o.jac), (double*)D(o.nu), (double*)D(o.rad), (int32_t*)D(o.lph)};
     b.list = (int32_t*)D(o.list);
     b.bsum = (int32_t*)D(o.bsum);
     b.n_active = (int32_t*)D(o.nact);
@@ -831,6 +850,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     if (!(opt->eps >= 0.0) || !std::isfinite(opt->eps)) return ctx_fail(c, DBIE_E_INVAL, "eps must be >= 0");
     if (!std::isfinite(opt->init_step) || !std::isfinite(opt->lambda_cap))
         return ctx_fail(c, DBIE_E_INVAL, "init_step and lambda_cap must be finite");
+    if (!(opt->lm_radius >= 0.0)) return ctx_fail(c, DBIE_E_INVAL, "lm_radius must be >= 0 (or +inf)");
     const int64_t N = ctx_n(c);
     if (int rc = ctx_check_device(c)) return rc;
     if (N > 0 && (!lam || !status || !trials))
@@ -848,7 +868,8 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     const bool fp64 = ctx_precision(c) == DBIE_FP64;
     const F32Shape sh = get_shape(c, lmm);
     const int32_t per32 = sh.ppl * sh.waves * 64;
-    SolveCfg cfg{opt->method, opt->max_trials, opt->eps, opt->init_step, opt->lambda_cap, ctx_dvds(c), 1e-3};
+    SolveCfg cfg{opt->method, opt->max_trials, opt->eps, opt->init_step, opt->lambda_cap, ctx_dvds(c), 1e-3,
+                 opt->lm_radius};
     const unsigned gN = (unsigned)((N + 255) / 256);
 #define SOLVE_HIP(call)                                                           \
     do {                                                                          \
@@ -920,6 +941,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         key.eps = opt->eps;
         key.step = opt->init_step;
         key.cap = opt->lambda_cap;
+        key.radius = opt->lm_radius;
         key.block = ctx_solver(c).block;
         key.stream = rs;
         key.per32 = per32;

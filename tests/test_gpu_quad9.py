@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+from _ties import Recording, has_near_tie
 import paper_1306_1122_amd as D
 
 pytestmark = pytest.mark.gpu
@@ -179,8 +180,9 @@ def test_fp32c_solve_with_fp64_acceptance():
 
 
 def test_lm_search_follows_the_oracle():
-    """Levenberg-Marquardt on the element field: trajectories (trials, status, lambda*) agree with the
-    oracle's LM on the same field for nearly every point (a tie in accept/reject may split them)."""
+    """Levenberg-Marquardt on the element field (the library's default trust radius, the simplex
+    edge): every trajectory (trials, status, lambda*) equals the oracle's LM on the same field, but
+    for points whose oracle trajectory holds a near-tie (tests/_ties.py)."""
     rng = np.random.default_rng(923)
     bd = magnetogram(rng, 17, 17)
     n = 48
@@ -193,14 +195,19 @@ def test_lm_search_follows_the_oracle():
     st_g = out["status"].cpu().numpy()
     tr_g = out["trials"].cpu().numpy()
     cap = np.pi / bd.h
-    same = 0
+    radius0 = oracle.default_nm_step(bd.B0.shape[2], bd.B0.shape[1], bd.h)
+    same, ties, bad = 0, 0, []
     for i in range(n):
-        prob = QuadProblem(bd.B0, bd.x0, bd.y0, bd.h, xyz[:, i], G=4)
-        lam, st, tr, _ = oracle.solve_point_lm(prob, lam0[:, i], 12, 1e-4, cap)
+        prob = Recording(QuadProblem(bd.B0, bd.x0, bd.y0, bd.h, xyz[:, i], G=4))
+        lam, st, tr, _ = oracle.solve_point_lm(prob, lam0[:, i], 12, 1e-4, cap, radius0=radius0)
         if st == st_g[i] and tr == tr_g[i] and np.allclose(lam, lam_g[:, i], rtol=1e-8, atol=1e-12):
             same += 1
-    print("quad9 LM identical trajectories", same, "of", n, flush=True)
-    assert same >= int(0.9 * n)
+        elif has_near_tie(prob.vals, 1e-4):
+            ties += 1
+        else:
+            bad.append(i)
+    print("quad9 LM identical trajectories", same, "of", n, "near-ties", ties, flush=True)
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("G", [2, 4])

@@ -157,6 +157,40 @@ def test_solve_point_lm_trust_radius_is_in_lambda():
     np.testing.assert_allclose(free.seen[1], np.clip(d, 0.0, 1.44), rtol=1e-15)
 
 
+class _ScriptedLM:
+    """A stand-in whose first calls return scripted (u, Phi): call 1 has u = 0 (so the next proposal
+    repeats mu), call 2 is accepted and points at a far target, call 3 is rejected."""
+
+    def __init__(self, target, cap):
+        self.A = np.diag([2.0, 0.7, 1.3, 0.0])[:, :3] + 0.0
+        self.t = np.asarray(target, np.float64)
+        self.cap, self.seen = cap, []
+
+    def lm_eval(self, mu):
+        self.seen.append(np.array(mu, np.float64))
+        k = len(self.seen)
+        u = np.zeros(4) if k == 1 else self.A @ (np.asarray(mu) - self.t)
+        phi = {1: 10.0, 2: 5.0, 3: 100.0}.get(k, float(u @ u))
+        return u, self.A, phi, 1.0, oracle.ST_BUDGET
+
+
+def test_solve_point_lm_infinite_radius_never_shrinks():
+    """radius0 = inf is no trust region at all: after an acceptance and a rejection the next proposal
+    still reaches the damped step's far target (a radius that became the cap on acceptance and was
+    halved on rejection would stop it at cap / 2); a finite radius0 does stop it."""
+    cap = 1.2
+    target = [0.81 * cap * cap, 0.01, 0.01]
+    free = _ScriptedLM(target, cap)
+    oracle.solve_point_lm(free, np.zeros(3), 4, 0.0, cap)
+    assert np.array_equal(free.seen[1], np.zeros(3))            # u = 0: no step
+    assert math.sqrt(free.seen[3][0]) > 0.85 * cap               # not limited after the rejection
+    boxed = _ScriptedLM(target, cap)
+    oracle.solve_point_lm(boxed, np.zeros(3), 4, 0.0, cap, radius0=0.25)
+    # 0.25 doubled on acceptance (0.5), halved on rejection (0.25): the fourth proposal moves 0.25
+    np.testing.assert_allclose(math.sqrt(boxed.seen[2][0]), 0.5, rtol=1e-15)
+    np.testing.assert_allclose(math.sqrt(boxed.seen[3][0]), 0.25, rtol=1e-15)
+
+
 def test_solve_point_lm_status_mapping():
     # converged at the start: one trial, |lambda0| returned
     prob = _LinearMuProblem([0.25, 0.9, 0.5])
