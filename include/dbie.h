@@ -157,6 +157,20 @@ DBIE_API int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_opti
 DBIE_API int dbie_eval_field(dbie_ctx* ctx, const double* lambda, int32_t L, double* B, double* dB,
                              double* fg, double* tan, void* stream);
 
+/* dbie_eval_field for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments, outputs and kernels,
+ * but the partial sums of the bulk pass live in a static device array of 64 MiB that the library
+ * holds on every device it runs on until the process ends, instead of the context's accumulator.
+ * The call allocates nothing (no hipMalloc / hipFree, no events) and records no kernel timing.
+ * Limit: L * n_points <= 399457 (21 doubles per point and trial); larger requests return
+ * DBIE_E_INVAL with a message. The pixel slices are the context's, or fewer if the array cannot hold
+ * them for L trials (results then differ from dbie_eval_field's in FP64 summation order only, ~1e-16
+ * relative; bitwise equal otherwise). All calls on one device share the array: calls that overlap
+ * on one device (two streams, two host threads, two contexts) race and give wrong results. Nothing in
+ * the array has to start at zero: every call writes each partial sum before reading it. */
+DBIE_API int dbie_eval_field_noalloc(dbie_ctx* ctx, const double* lambda, int32_t L, double* B, double* dB,
+                                     double* fg, double* tan, void* stream);
+
 /* dbie_eval_field with one lambda shared by the three components at each point (lambda_x = lambda_y
  * = lambda_z, e.g. a linear force-free trial): lambda is device double [L][N]; the outputs are those of
  * dbie_eval_field (tan rows are d/d mu of each row for the shared mu = lambda^2). The FP32C bulk sum

@@ -49,6 +49,8 @@ SIGNATURES = {
                                   c_void_p]),
     "dbie_eval_field_scalar": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                          c_void_p, c_void_p]),
+    "dbie_eval_field_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p]),
     "dbie_solve_lambda": (c_int32, [c_void_p, c_void_p, POINTER(dbie_solve_opts), c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p]),
     "dbie_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

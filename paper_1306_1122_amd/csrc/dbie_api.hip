@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,9 +15,35 @@
 
 using namespace dbie;
 
+// Work memory of dbie_eval_field_noalloc: the partial sums of its bulk pass ([S][L][kAcc][N] doubles)
+// live in this static array instead of the context's accumulator. Every device the library runs on
+// holds its own copy until the process ends; all calls on one device share it.
+static constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+// Device address of each device's copy of `scratch`, looked up once per device (with that device
+// current) by the first dbie_init on it. In host code `scratch` itself is only a stand-in symbol.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_scratch(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 constexpr int kTile64 = 256;         // points per workgroup of the FP64 kernels
 
@@ -96,6 +123,7 @@ struct dbie_ctx {
     int32_t split = 1;          // FP32C pixel slices per launch (grid z); acc holds split x L slices
     int32_t cus = 256;          // compute units of the device
     double* acc = nullptr;      // [split][L][kAcc][N]
+    double* noalloc_acc = nullptr;  // this device's static `scratch` (dbie_eval_field_noalloc)
     int64_t acc_L = 0;          // slices x trials the accumulator holds
     bool acc_owned = true;      // false: it lies in the caller's workspace
     char* ws = nullptr;         // caller-owned workspace (dbie_set_workspace), or NULL
@@ -266,15 +294,20 @@ int32_t split_for_points(dbie_ctx* c, int64_t n) {
 }
 
 // Bulk sum + finalize for L trials on the given lambda; the building block of every call. S > 0
-// overrides the context's pixel slices.
+// overrides the context's pixel slices. acc_in != NULL: partial sums there (room for L x S slices,
+// checked by the caller) instead of the context's accumulator, and no timing events.
 static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool tan, const EvalSet* set,
                      double* B, double* dB, double* fg, double* tn, hipStream_t s, bool scalar = false,
-                     int32_t S = 0) {
+                     int32_t S = 0, double* acc_in = nullptr) {
     if (S <= 0) S = c->split;
-    int rc = ensure_acc_slices(c, (int64_t)L * S);
-    if (rc) return rc;
+    double* acc = acc_in;
+    if (!acc) {
+        int rc = ensure_acc_slices(c, (int64_t)L * S);
+        if (rc) return rc;
+        acc = c->acc;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    if (c->timing && !acc_in) {
         e0 = pool_event(c);
         e1 = pool_event(c);
         if (e0 && e1) DBIE_HIP(c, hipEventRecord(e0, s));
@@ -282,20 +315,20 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
     const int32_t* idx = set ? set->idx : nullptr;
     if (fp64)
         DBIE_HIP(c, launch_field64(set ? set->tiles64 : c->tiles64, set ? set->n_tiles64 : c->n_tiles64,
-                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, S, idx, tan, c->acc, s));
+                                   c->bnd_d, c->gpos, c->gB, c->geo, lam, c->N, L, S, idx, tan, acc, s));
     else
         DBIE_HIP(c, launch_field32c(set ? set->tiles32 : (tan ? c->tiles32t : c->tiles32),
                                     set ? set->n_tiles32 : (tan ? c->n_tiles32t : c->n_tiles32), c->bnd_d,
                                     c->pixf, c->gposf, c->geo, lam, c->N, L, S, set ? idx : c->perm, c->work, tan,
-                                    scalar, tan ? c->shape_tan : c->shape, c->acc, s));
-    if (c->timing && e0 && e1) {
+                                    scalar, tan ? c->shape_tan : c->shape, acc, s));
+    if (e0 && e1) {
         DBIE_HIP(c, hipEventRecord(e1, s));
         c->ev.emplace_back(e0, e1);
     }
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
     DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, idx, c->N,
                                 set ? set->n_dev : nullptr, c->N,
-                                L, S, c->acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
+                                L, S, acc, near, tan, c->opt.dv_over_dsigma_h, B, dB, fg, tn, s));
     return DBIE_OK;
 }
 
@@ -470,6 +503,15 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     c->seg = seg;
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetDevice(&c->device);
+    {
+        void* p = nullptr;
+        const hipError_t e = noalloc_scratch(c->device, &p);
+        if (e != hipSuccess) {
+            free_ctx(c);
+            return fail(nullptr, DBIE_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        c->noalloc_acc = (double*)p;
+    }
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
@@ -737,6 +779,28 @@ int dbie_eval_field(dbie_ctx* c, const double* lambda, int32_t L, double* B, dou
     if (c->N == 0) return DBIE_OK;
     return eval_core(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, B, dB, fg, tan,
                      (hipStream_t)stream);
+}
+
+int dbie_eval_field_noalloc(dbie_ctx* c, const double* lambda, int32_t L, double* B, double* dB, double* fg,
+                            double* tan, void* stream) {
+    if (!c) return fail(nullptr, DBIE_E_INVAL, "ctx is NULL");
+    if (L < 1) return fail(c, DBIE_E_INVAL, "L must be >= 1");
+    if (c->N > 0 && (!lambda || !B)) return fail(c, DBIE_E_INVAL, "lambda and B are required");
+    if (int rc = ctx_check_device(c)) return rc;
+    if (c->N == 0) return DBIE_OK;
+    // pixel slices: the context's, or as many as the static array holds for L trials
+    const int64_t slice = (int64_t)kAcc * c->N * (int64_t)sizeof(double);
+    const int64_t fit = (int64_t)kNoAllocBytes / slice / L;
+    if (fit < 1) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "dbie_eval_field_noalloc: L * n_points = %lld exceeds %lld (%d MiB of static "
+                      "work memory, %d doubles per point and trial)", (long long)L * c->N,
+                      (long long)(kNoAllocBytes / (kAcc * sizeof(double))), (int)(kNoAllocBytes >> 20), kAcc);
+        return fail(c, DBIE_E_INVAL, msg);
+    }
+    const int32_t S = (int32_t)std::min<int64_t>(c->split, fit);
+    return eval_core(c, lambda, L, c->opt.precision == DBIE_FP64, tan != nullptr, nullptr, B, dB, fg, tan,
+                     (hipStream_t)stream, false, S, c->noalloc_acc);
 }
 
 int dbie_eval_field_scalar(dbie_ctx* c, const double* lambda, int32_t L, double* B, double* dB, double* fg,

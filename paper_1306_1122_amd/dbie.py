@@ -159,6 +159,18 @@ def dbie_init(boundaries: List[Dict], xyz: torch.Tensor, seg: Optional[Sequence[
 def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, tan=None,
                     want_dB: bool = True, want_fg: bool = True, want_tan: bool = False, stream=None):
     """lam: [3, N] or [L, 3, N]. Returns dict(B, dB, fg, tan) with a leading L axis only if lam has one."""
+    return _eval_field("dbie_eval_field", ctx, lam, B, dB, fg, tan, want_dB, want_fg, want_tan, stream)
+
+
+def dbie_eval_field_noalloc(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, tan=None,
+                            want_dB: bool = True, want_fg: bool = True, want_tan: bool = False, stream=None):
+    """dbie_eval_field through the entry point that allocates no device memory (its partial sums live
+    in the library's static work array; L * N is limited). Outputs not passed in are allocated here,
+    by torch, before the call."""
+    return _eval_field("dbie_eval_field_noalloc", ctx, lam, B, dB, fg, tan, want_dB, want_fg, want_tan, stream)
+
+
+def _eval_field(entry, ctx, lam, B, dB, fg, tan, want_dB, want_fg, want_tan, stream):
     N = ctx.n_points
     squeeze = lam.dim() == 2
     lam3 = lam.unsqueeze(0) if squeeze else lam
@@ -175,9 +187,9 @@ def dbie_eval_field(ctx: Context, lam: torch.Tensor, B=None, dB=None, fg=None, t
             # a 2-D output is accepted for one trial only
             _need(t, nm, (Lt, rows, N) if (t.dim() == 3 or Lt > 1) else (rows, N), device=ctx.device)
     with _on(ctx.device):
-        rc = _lib().dbie_eval_field(ctx.handle, _ptr(lam3), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
+        rc = getattr(_lib(), entry)(ctx.handle, _ptr(lam3), Lt, _ptr(B), _ptr(dB), _ptr(fg), _ptr(tan),
                                     _stream(stream))
-    _check(rc, ctx, "dbie_eval_field")
+    _check(rc, ctx, entry)
     out = dict(B=B, dB=dB, fg=fg, tan=tan)
     if squeeze:
         out = {k: (v[0] if v is not None and v.dim() == 3 else v) for k, v in out.items()}

@@ -151,6 +151,7 @@ def test_workspace_calls_on_null_context(lib):
 
 def test_calls_on_null_context_are_rejected(lib):
     assert lib.dbie_eval_field(None, None, 1, None, None, None, None, None) == L.DBIE_E_INVAL
+    assert lib.dbie_eval_field_noalloc(None, None, 1, None, None, None, None, None) == L.DBIE_E_INVAL
     assert lib.dbie_timing(None, 1) == L.DBIE_E_INVAL
     lib.dbie_destroy(None)
 
