@@ -2,8 +2,9 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload: the 128x128 FP32 bipole magnetogram (6 Gaussian bipoles, sheared horizontal field,
-20 G noise) with all 128x128x64 = 1,048,576 evaluation points; synthetic, seeded.
+Workload: the 256x256 FP32 bipole magnetogram (10 Gaussian bipoles, per-bipole shear alpha in
+[0.5, 2], 20 G noise) with all 256x256x128 = 8,388,608 evaluation points (5.5e11 kernel pairs per
+trial); synthetic, seeded. The 128x128 workload with 2^20 points runs the same step as an extra.
 One step = one call of dbie_solve_lambda in its gradient form (Levenberg-Marquardt in mu = lambda^2)
 with a budget of TRIALS_PER_STEP trials over every point: per trial the FP32C bulk sum of B, grad B
 and the mu-tangents, the FP64 near-field pairs and residuals, the LM update and the active-set
@@ -55,6 +56,7 @@ def cpu_baseline(w, n_sample, seed=7):
     from workloads import z_stratified_subsample
     bd = w.boundaries[0]
     idx = z_stratified_subsample(w.xyz, n_sample, seed)
+    # one worker per host core, at most 16 (the GPU machine's CPU share)
     cores = min(os.cpu_count() or 1, 16)
     chunks = np.array_split(idx, cores * 4)
     jobs = [(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, c], w.lam[:, c]) for c in chunks if c.size]
@@ -71,7 +73,7 @@ def cpu_baseline(w, n_sample, seed=7):
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    return dict(value=pairs / dt, unit="pairs/s", cores=cores, kind="oracle", cpu=model,
+    return dict(value=pairs / dt, unit="pairs/s", cores=cores, host_cpus=os.cpu_count(), kind="oracle", cpu=model,
                 sample=f"{n} z-stratified points of the {w.name} workload x all {bd.nx * bd.ny} pixels "
                        f"(FP64 field + grad + mu-tangents + residuals), {dt:.2f} s wall")
 
@@ -157,32 +159,56 @@ def adjoint_and_scalar(D, ctx, lam, pairs, B0, xyz, bd):
                 scalar_lambda_field_grad_ms=ms_sc, scalar_lambda_pairs_per_s=pairs / (ms_sc * 1e-3))
 
 
-def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3"):
-    """Plain form (FP64 Nelder-Mead, 200 trials) vs fast form (FP32C Levenberg-Marquardt, 20 trials,
-    FP64 acceptance) on a z-stratified sample of the 256x256x128 bipole grid (or of the clustered
-    points of the 512x256 active region, workload="config5"), from lambda = 0; the
-    FP32C Nelder-Mead (200 trials, FP64 acceptance) separates the precision from the method.
+def schrijver_metrics(B, b):
+    """Field-comparison metrics of Schrijver et al. (2006) used by the paper's Table 1: B the exact
+    field, b the model, both [3, N]."""
+    nB = np.sqrt(np.sum(B * B, axis=0))
+    nb = np.sqrt(np.sum(b * b, axis=0))
+    dot = np.sum(B * b, axis=0)
+    diff = np.sqrt(np.sum((b - B) ** 2, axis=0))
+    return dict(C_vec=float(np.sum(dot) / np.sqrt(np.sum(nB ** 2) * np.sum(nb ** 2))),
+                C_cs=float(np.mean(dot / (nB * nb))), E_n=float(1.0 - np.sum(diff) / np.sum(nB)),
+                E_m=float(1.0 - np.mean(diff / nB)), eps=float(np.sum(nb ** 2) / np.sum(nB ** 2)))
+
+
+def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3", nm_budget=200, lm_budget=20,
+                     forms=("plain", "fp32c_nm", "fast")):
+    """Plain form (FP64 Nelder-Mead, nm_budget trials) vs fast form (FP32C Levenberg-Marquardt with
+    the default trust region, lm_budget trials, FP64 acceptance), from lambda = 0, on the workload's
+    points (a z-stratified sample of n_sample of them, or all with n_sample=None); the FP32C
+    Nelder-Mead (nm_budget trials, FP64 acceptance) separates the precision from the method.
     q* = the solved fraction (max(f, g) <= eps in FP64) the plain form reaches within its budget;
     TTS(form) = solve time until that form's solved fraction reaches q* (round-end HIP events), where
     a point counts from the round of its last trial only if its final status is CONVERGED (for the
     FP32C forms: confirmed by the FP64 acceptance pass, which re-evaluates the points that converged),
     and the FP32C forms add the duration of that pass (the solve's end minus the end of its last
-    round)."""
+    round). For a workload with an exact field (Low & Lou) each form also reports the comparison
+    metrics of its FP64 field at lambda* against the exact field, next to those at lambda = 0."""
     import torch
     import workloads
     from workloads import z_stratified_subsample
     w = getattr(workloads, workload)()
     bd = w.boundaries[0]
-    idx = z_stratified_subsample(w.xyz, n_sample, 3)
-    xyz = torch.tensor(np.ascontiguousarray(w.xyz[:, idx]), dtype=torch.float64, device=dev)
+    idx = np.arange(w.n_points) if n_sample is None else z_stratified_subsample(w.xyz, n_sample, 3)
+    pts = np.ascontiguousarray(w.xyz[:, idx])
+    xyz = torch.tensor(pts, dtype=torch.float64, device=dev)
     B0 = torch.tensor(bd.B0, dtype=torch.float64, device=dev)
     n = xyz.shape[1]
-    res = {"workload": f"{n} z-stratified points of {w.name}", "eps": eps}
-    forms = (("plain_fp64_nelder_mead", "fp64", "nm", 200),
-             ("fp32c_nelder_mead", "fp32c", "nm", 200),
-             ("fast_fp32c_levenberg_marquardt", "fp32c", "lm", 20))
-    for form, prec, meth, budget in forms:
-        ctx = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision=prec)
+    ll = w.meta.get("ll") if w.meta else None
+    exact = ll.field(*pts) if ll is not None else None
+    ctx64 = D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision="fp64")
+    res = {"workload": (f"all {n} points of {w.name}" if n_sample is None else
+                        f"{n} z-stratified points of {w.name}"), "eps": eps}
+    if exact is not None:
+        b = D.dbie_eval_field(ctx64, torch.zeros(3, n, dtype=torch.float64, device=dev))["B"].cpu().numpy()
+        res["metrics_lambda0"] = schrijver_metrics(exact, b)
+    table = {"plain": ("plain_fp64_nelder_mead", "fp64", "nm", nm_budget),
+             "fp32c_nm": ("fp32c_nelder_mead", "fp32c", "nm", nm_budget),
+             "fast": ("fast_fp32c_levenberg_marquardt", "fp32c", "lm", lm_budget)}
+    run = [table[f] for f in forms]
+    for form, prec, meth, budget in run:
+        ctx = ctx64 if prec == "fp64" else D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz,
+                                                        precision=prec)
         lam = torch.zeros(3, n, dtype=torch.float64, device=dev)
         D.dbie_solve_trace(ctx, True)
         torch.cuda.synchronize()
@@ -192,11 +218,14 @@ def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3"):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         t, cv, t_end = D.dbie_solve_trace_read(ctx, with_end=True)
+        D.dbie_solve_trace(ctx, False)
         st = r["status"].cpu().numpy()
         tr = r["trials"].cpu().numpy()
-        # f and g at lambda* for the summary (after the timed solve, in the context's precision)
-        fg = D.dbie_eval_field(ctx, r["lam"], want_dB=False)["fg"].cpu().numpy()
-        ctx.close()
+        # field, f and g at lambda* in FP64 for the summary (after the timed solve)
+        ev = D.dbie_eval_field(ctx64, r["lam"], want_dB=False)
+        fg = ev["fg"].cpu().numpy()
+        if ctx is not ctx64:
+            ctx.close()
         # FP64-confirmed solved fraction at the end of each round (one trial per round)
         ok = tr[st == 0]
         frac = np.array([np.count_nonzero(ok <= k + 1) for k in range(len(t))]) / n
@@ -207,9 +236,13 @@ def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3"):
                          mean_f=float(np.nanmean(fg[0])), mean_g=float(np.nanmean(fg[1])),
                          median_rho=float(np.nanmedian(np.maximum(fg[0], fg[1]))),
                          curve_ms=[float(v) for v in t], curve_fraction=[float(v) for v in frac])
+        if exact is not None:
+            res[form]["metrics"] = schrijver_metrics(exact, ev["B"].cpu().numpy())
+    ctx64.close()
     q = res["plain_fp64_nelder_mead"]["solved_fraction"]
     res["q_star"] = q
-    for form, _, _, _ in forms:
+    res["q_star_points"] = int(round(q * n))
+    for form, _, _, _ in run:
         f = np.array(res[form]["curve_fraction"])
         tms = np.array(res[form]["curve_ms"])
         hit = np.nonzero(f >= q)[0] if q > 0 else np.array([], dtype=int)
@@ -219,30 +252,68 @@ def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3"):
         res[form]["curve_ms"] = [res[form]["curve_ms"][i] for i in k]
         res[form]["curve_fraction"] = [res[form]["curve_fraction"][i] for i in k]
     a = res["plain_fp64_nelder_mead"]["tts_ms"]
-    b = res["fast_fp32c_levenberg_marquardt"]["tts_ms"]
+    b = res.get("fast_fp32c_levenberg_marquardt", {}).get("tts_ms")
     res["tts_speedup"] = (a / b) if (a and b) else None
     # the precision alone (same derivative-free search in FP32C)
-    c = res["fp32c_nelder_mead"]["tts_ms"]
-    res["tts_speedup_fp32c_nelder_mead"] = (a / c) if (a and c) else None
+    c = res.get("fp32c_nelder_mead", {}).get("tts_ms")
+    if "fp32c_nelder_mead" in res:
+        res["tts_speedup_fp32c_nelder_mead"] = (a / c) if (a and c) else None
     return res
 
 
+def table1_metrics(D, dev, mapping):
+    """The paper's Table 1 case (Low & Lou n = 3, m = 1, l = 0.3, Phi = 4 pi / 5; 192^2 boundary, 64^3
+    region; one of two readings of its grid mapping): the comparison metrics over the 64^3 region
+    nodes against the exact field, for lambda = 0, the plain form (FP64 Nelder-Mead, 50 trials) and
+    the fast form (FP32C Levenberg-Marquardt with the default trust region, 20 trials, FP64
+    acceptance), each with its solve time."""
+    import torch
+    from workloads import lowlou_table1
+    w = lowlou_table1(mapping=mapping)
+    bd = w.boundaries[0]
+    jj, ii = w.meta["bottom_idx"]
+    bottom = bd.B0[:, jj, ii]
+    exact = np.concatenate([bottom, w.meta["ll"].field(*w.xyz)], axis=1)
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    xyz = T(w.xyz)
+    out = {"workload": w.name}
+    for name, prec, meth, budget in (("lambda0", "fp64", None, 0), ("plain_fp64_nelder_mead", "fp64", "nm", 50),
+                                     ("fast_fp32c_levenberg_marquardt", "fp32c", "lm", 20)):
+        ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], xyz, precision=prec)
+        lam = torch.zeros(3, w.n_points, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if meth is None:
+            o = D.dbie_eval_field(ctx, lam)
+            B, fg, conv = o["B"], o["fg"], float("nan")
+        else:
+            r = D.dbie_solve_lambda(ctx, lam, method=meth, max_trials=budget, eps=1e-4, fp64_accept=True)
+            B, fg = r["B"], r["fg"]
+            conv = float((r["status"] == 0).double().mean())
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        ctx.close()
+        m = schrijver_metrics(exact, np.concatenate([bottom, B.cpu().numpy()], axis=1))
+        fgn = fg.cpu().numpy()
+        m.update(solved_fraction=conv, mean_phi=float(np.nanmean(fgn[0] ** 2 + fgn[1] ** 2)), ms=ms)
+        out[name] = m
+    out["paper_present_dbie"] = dict(C_vec=0.99, C_cs=0.52, E_n=0.83, E_m=-0.53, eps=1.08)
+    return out
+
+
 def batched(D, dev):
-    """64 magnetograms of uneven size in one launch vs one launch per magnetogram (FP32C, B + grad B)."""
+    """64 magnetograms of uneven size in one launch (tuned shape) vs one launch per magnetogram (FP32C,
+    B + grad B); the tuned shape also in the persistent and the grid form."""
     import torch
     from workloads import config4
     w = config4()
     T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
     bds = [dict(B0=T(b.B0), x0=b.x0, y0=b.y0, h=b.h) for b in w.boundaries]
-    ctx = D.dbie_init(bds, T(w.xyz), seg=w.seg, precision="fp32c")
+    ctx = D.dbie_init(bds, T(w.xyz), seg=w.seg, precision="fp32c", tune=True)
     lam = T(w.lam)
     pairs = w.pairs_per_trial()
+    tuned = dict(shape=D.dbie_query(ctx), persistent=D.dbie_query_persistent(ctx), source=D.dbie_query_tuned(ctx))
     one = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
-    # the same launch in the persistent form (tiles pulled from a device counter)
-    q = D.dbie_query(ctx)
-    D.dbie_set_tile_shape(ctx, q["ppl"], q["waves"], q["tile_pixels"], True)
-    pers = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
-    D.dbie_set_tile_shape(ctx, q["ppl"], q["waves"], q["tile_pixels"], False)
     # Levenberg-Marquardt rounds over all 64 magnetograms, replayed from the captured graph
     lam_io = torch.empty_like(lam)
 
@@ -252,6 +323,12 @@ def batched(D, dev):
                             want_fg=False)
 
     ms_solve = _timed(solve, 1)
+    # the tuned shape in the persistent form (tiles pulled from a device counter) and in the grid form
+    q = D.dbie_query(ctx)
+    D.dbie_set_tile_shape(ctx, q["ppl"], q["waves"], q["tile_pixels"], True)
+    pers = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
+    D.dbie_set_tile_shape(ctx, q["ppl"], q["waves"], q["tile_pixels"], False)
+    grid = _timed(lambda: D.dbie_eval_field(ctx, lam), 2)
     ctx.close()
     parts = []
     for b in range(len(bds)):
@@ -265,8 +342,8 @@ def batched(D, dev):
     sep = _timed(each, 1)
     return dict(points=w.n_points, pairs=pairs, one_launch_ms=one, one_launch_pairs_per_s=pairs / (one * 1e-3),
                 persistent_launch_ms=pers, persistent_pairs_per_s=pairs / (pers * 1e-3),
-                separate_launches_ms=sep, separate_pairs_per_s=pairs / (sep * 1e-3),
-                lm_solve_4_trials_graph_ms=ms_solve)
+                grid_launch_ms=grid, grid_pairs_per_s=pairs / (grid * 1e-3), separate_launches_ms=sep, separate_pairs_per_s=pairs / (sep * 1e-3),
+                lm_solve_4_trials_graph_ms=ms_solve, tuned=tuned)
 
 
 def active_region(D, dev):
@@ -334,15 +411,49 @@ def field_lines(D, dev, n_lines=4096, n_steps=100):
                 pairs_per_s=4 * n_steps * n_lines * bd.nx * bd.ny / (ms * 1e-3))
 
 
+def lm_step_rate(D, dev, workload, steps=5, warmup=2):
+    """The headline step (Levenberg-Marquardt, TRIALS_PER_STEP trials, tuned shapes) on another
+    workload: pairs/s and the bulk kernel's mean launch time."""
+    import torch
+    import workloads
+    w = getattr(workloads, workload)()
+    bd = w.boundaries[0]
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    ctx = D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision="fp32c", tune=True)
+    lam = T(w.lam)
+    lam_io = torch.empty_like(lam)
+    trials = torch.empty(w.n_points, dtype=torch.int32, device=dev)
+
+    def step():
+        lam_io.copy_(lam)
+        D.dbie_solve_lambda(ctx, lam_io, method="lm", max_trials=TRIALS_PER_STEP, eps=1e-4, fp64_accept=False,
+                            trials=trials, want_B=False, want_fg=False)
+
+    for _ in range(warmup):
+        step()
+    D.dbie_timing(ctx, True)
+    D.dbie_timing_read(ctx)
+    ms = _timed(step, steps)
+    km, kl = D.dbie_timing_read(ctx)
+    D.dbie_timing(ctx, False)
+    pairs = int(trials.sum().item()) * bd.nx * bd.ny
+    ctx.close()
+    return dict(workload=w.name, ms_per_step=ms, pairs_per_step=pairs, pairs_per_s=pairs / (ms * 1e-3),
+                bulk_kernel_ms=km / max(kl, 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=98304)
+    ap.add_argument("--cpu-sample", type=int, default=24576)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="", help="comma-separated names of the extras to run (default: all)")
+    ap.add_argument("--tts-full", action="store_true",
+                    help="instead of the benchmark: time to solution over all 8,388,608 points of the 256x256 "
+                         "workload (plain FP64 Nelder-Mead, 200 trials, against the fast form; ~8 minutes)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB once (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--shape", default="", help="FP32C tile shape ppl,waves,tile_pixels")
@@ -353,11 +464,11 @@ def main():
               "(points would be sharded across GPUs with the magnetogram replicated).", file=sys.stderr)
         sys.exit(2)
 
-    from workloads import config2
-    w = config2()
+    from workloads import config3
+    w = config3()
     # the CPU oracle's worker processes are forked before anything touches the GPU
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.tts_full:
         cpu = cpu_baseline(w, args.cpu_sample)
 
     import torch
@@ -369,6 +480,11 @@ def main():
         sys.exit(2)
     _lib.load()   # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
+    if args.tts_full:
+        print("time to solution over all points of the 256x256 workload", flush=True)
+        r = time_to_solution(D, dev, n_sample=None, forms=("fast", "plain"))
+        print(json.dumps({"time_to_solution_full": r}), flush=True)
+        return
     bd = w.boundaries[0]
     N = w.n_points
     pairs = w.pairs_per_trial()
@@ -402,8 +518,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(s)
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step()
+        if k % 5 == 4:
+            torch.cuda.synchronize()
+            print(f"step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
     e1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -426,6 +545,11 @@ def main():
     if not args.no_extras:
         for name, fn in (("per_trial_rates", lambda: per_trial_rates(D, ctx, B0, xyz, lam, bd, pairs, s)),
                          ("adjoint_and_scalar_lambda", lambda: adjoint_and_scalar(D, ctx, lam, pairs, B0, xyz, bd)),
+                         ("lm_step_bipoles_128x128_1M_points", lambda: lm_step_rate(D, dev, "config2")),
+                         ("time_to_solution_lowlou_all_points",
+                          lambda: time_to_solution(D, dev, n_sample=None, workload="config1", nm_budget=50)),
+                         ("table1_region", lambda: table1_metrics(D, dev, "region")),
+                         ("table1_boundary", lambda: table1_metrics(D, dev, "boundary")),
                          ("time_to_solution", lambda: time_to_solution(D, dev)),
                          ("time_to_solution_eps_0.1", lambda: time_to_solution(D, dev, eps=0.1)),
                          ("time_to_solution_active_region",
@@ -436,6 +560,7 @@ def main():
                          ("field_lines_4096", lambda: field_lines(D, dev))):
             if args.extras and name not in args.extras.split(","):
                 continue
+            print(f"extra {name}", file=sys.stderr, flush=True)
             try:
                 extras[name] = fn()
             except Exception as exc:  # an extra must not hide the headline line
@@ -475,7 +600,8 @@ def main():
                    "step": "dbie_solve_lambda, Levenberg-Marquardt, 3-trial budget: per trial FP32C B, "
                            "grad B, mu-tangents + FP64 near field + FP64 residuals + LM update",
                    "tile_shape": [q["ppl"], q["waves"], q["tile_pixels"]],
-                   "tile_shape_tangents": [qt["ppl"], qt["waves"], qt["tile_pixels"]]},
+                   "tile_shape_tangents": [qt["ppl"], qt["waves"], qt["tile_pixels"]],
+                   "persistent": D.dbie_query_persistent(ctx), "tuned": D.dbie_query_tuned(ctx)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": float(counters["hbm_bytes_per_launch"]) if counters else None,

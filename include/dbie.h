@@ -97,8 +97,16 @@ typedef struct {
     int32_t precision;           /* DBIE_FP64 or DBIE_FP32C */
     double nearfield_radius_h;   /* FP32C only: pairs with r < this * h are summed in FP64; in [0, 2] */
     double dv_over_dsigma_h;     /* dV / dSigma of Eq. 9 in units of h (1/6: cube of side h) */
-    int32_t tune;                /* 1: choose FP32C tile shapes by timing candidates at init */
-    const char* tune_cache;      /* optional path of a text cache of tuned shapes (NULL: none) */
+    int32_t tune;                /* 1: choose the FP32C tile shapes (points per lane, waves per
+                                  * workgroup, grid or persistent form) and, when the point tiles alone
+                                  * cannot fill the device, the pixel split, by timing the bulk kernel at
+                                  * init on the largest tiles at lambda spread over |lambda| < 4 pi / L.
+                                  * Choices are reused within the process for contexts of the same
+                                  * device architecture, quadrature and size bucket (floor(log2) of the
+                                  * point count and of the mean quadrature points per magnetogram). */
+    const char* tune_cache;      /* optional path of a text cache of tuned choices, read before timing
+                                  * and appended to after (lines: arch quad_points log2N log2pixels tan
+                                  * ppl waves tile_pixels persistent split); NULL: none */
     int32_t quad_points;         /* 0: nodal sum over the pixel centres, weight h^2 (Eq. 16).
                                   * 2, 3 or 4: 9-node quadratic elements (Eq. 15), each element
                                   * integral by quad_points x quad_points Gauss-Legendre points; every
@@ -243,7 +251,12 @@ DBIE_API int dbie_query_persistent(const dbie_ctx* ctx, int32_t* plain, int32_t*
  * Wavefront shuffles and a fixed-order block sum: deterministic. Synchronises `stream`. */
 DBIE_API int dbie_residual_stats(dbie_ctx* ctx, const double* fg, double eps, double* out, void* stream);
 
-/* Pixel slices per launch of the bulk sum (dbie_options.pixel_split, or the automatic choice). */
+/* Where the context's FP32C shapes came from: 0 defaults (no tuning), 1 timed by its dbie_init, 2 reused
+ * from an earlier context of this process with the same key, 3 read from the tune_cache file. */
+DBIE_API int dbie_query_tuned(const dbie_ctx* ctx, int32_t* source);
+
+/* Pixel slices per launch of the bulk sum (dbie_options.pixel_split, the tuner's or the automatic
+ * choice). */
 DBIE_API int dbie_query_split(const dbie_ctx* ctx, int32_t* slices);
 
 /* Caller-owned work memory (no operation of the paper: device-memory plumbing for callers that manage

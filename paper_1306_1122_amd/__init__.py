@@ -9,11 +9,11 @@ from .autograd import DbieField, dbie_field
 from .dbie import (Context, DbieError, Field, dbie_default_options, dbie_default_solve_opts, dbie_destroy,
                    dbie_eval_field, dbie_eval_field_noalloc, dbie_eval_field_scalar, dbie_grad, dbie_init, dbie_last_error, dbie_query, dbie_solve_lambda,
                    dbie_timing, dbie_timing_read, split_gB0, dbie_query_tan, dbie_query_persistent, dbie_set_tile_shape,
-                   dbie_solve_trace, dbie_solve_trace_read, dbie_trace_lines, dbie_query_split,
+                   dbie_solve_trace, dbie_solve_trace_read, dbie_trace_lines, dbie_query_split, dbie_query_tuned,
                    dbie_workspace_bytes, dbie_set_workspace, dbie_residual_stats)
 
 __all__ = ["Context", "DbieError", "Field", "DbieField", "dbie_field", "dbie_init", "dbie_eval_field", "dbie_eval_field_noalloc", "dbie_eval_field_scalar", "dbie_solve_lambda", "dbie_grad",
            "dbie_timing", "dbie_timing_read", "dbie_query", "dbie_destroy", "dbie_last_error",
            "dbie_default_options", "dbie_default_solve_opts", "split_gB0", "dbie_query_tan", "dbie_query_persistent",
-           "dbie_set_tile_shape", "dbie_solve_trace", "dbie_solve_trace_read", "dbie_trace_lines", "dbie_query_split",
+           "dbie_set_tile_shape", "dbie_solve_trace", "dbie_solve_trace_read", "dbie_trace_lines", "dbie_query_split", "dbie_query_tuned",
            "dbie_workspace_bytes", "dbie_set_workspace", "dbie_residual_stats"]

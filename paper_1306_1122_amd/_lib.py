@@ -64,6 +64,7 @@ SIGNATURES = {
     "dbie_query_persistent": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "dbie_solve_trace": (c_int32, [c_void_p, c_int32]),
     "dbie_query_split": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "dbie_query_tuned": (c_int32, [c_void_p, POINTER(c_int32)]),
     "dbie_residual_stats": (c_int32, [c_void_p, c_void_p, c_double, POINTER(c_double), c_void_p]),
     "dbie_workspace_bytes": (c_int64, [c_void_p]),
     "dbie_set_workspace": (c_int32, [c_void_p, c_void_p, c_int64]),

@@ -115,6 +115,9 @@ struct dbie_ctx {
     int64_t n_tiles32 = 0;
     Tile* tiles32t = nullptr;    // static schedule of the FP32C pass with mu-tangents
     int64_t n_tiles32t = 0;
+    std::vector<Tile> tiles32_h, tiles32t_h;   // host copies of the two FP32C schedules
+    int32_t split_tuned = 0;     // pixel slices chosen by the tuner (0: none)
+    int32_t tuned = 0;           // 0 untuned, 1 timed at init, 2 from this process's cache, 3 from the file
     // untuned shapes: four-wave workgroups (at three resident waves per SIMD, the register count
     // of both nodal FP32C forms, eight-wave workgroups leave a third of the slots empty)
     F32Shape shape{1, 4, kRows * kCols, 0};
@@ -240,10 +243,14 @@ int set_tiles32(dbie_ctx* c, F32Shape s, bool tan) {
     dst = d;
     (tan ? c->n_tiles32t : c->n_tiles32) = (int64_t)t.size();
     (tan ? c->shape_tan : c->shape) = s;
+    (tan ? c->tiles32t_h : c->tiles32_h) = std::move(t);
     // Pixel slices: enough workgroups for about four per compute unit when the point tiles alone
-    // are fewer (few points: late solver rounds, field-line seeds), else one.
+    // are fewer (few points: late solver rounds, field-line seeds), else one; or the caller's or the
+    // tuner's choice.
     if (c->opt.pixel_split > 0) {
         c->split = c->opt.pixel_split;
+    } else if (c->split_tuned > 0) {
+        c->split = c->split_tuned;
     } else {
         const int64_t nt = std::max<int64_t>(1, std::min(c->n_tiles32 > 0 ? c->n_tiles32 : INT64_MAX,
                                                          c->n_tiles32t > 0 ? c->n_tiles32t : INT64_MAX));
@@ -755,7 +762,7 @@ int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt,
     if (o.precision == DBIE_FP32C && o.tune) {
         rc = tune_shapes(c, opt ? opt->tune_cache : nullptr, s);
         if (rc) return bail(rc);
-        // the tuning buffers (27 doubles per point) are not kept: later calls size these slots
+        // the tuning lambda (3 doubles per point) is not kept: later calls size these slots
         DBIE_INIT_HIP(hipStreamSynchronize(s));
         for (int k = 2; k < 4; ++k) {
             DBIE_INIT_HIP(hipFree(c->scratch[k]));
@@ -984,6 +991,12 @@ int dbie_residual_stats(dbie_ctx* c, const double* fg, double eps, double* out, 
     return DBIE_OK;
 }
 
+int dbie_query_tuned(const dbie_ctx* c, int32_t* source) {
+    if (!c) return DBIE_E_INVAL;
+    if (source) *source = c->tuned;
+    return DBIE_OK;
+}
+
 int dbie_query_split(const dbie_ctx* c, int32_t* slices) {
     if (!c) return DBIE_E_INVAL;
     if (slices) *slices = c->split;
@@ -1006,75 +1019,207 @@ int set_shape(dbie_ctx* c, F32Shape s, bool tan) {
 }
 F32Shape get_shape(const dbie_ctx* c, bool tan) { return tan ? c->shape_tan : c->shape; }
 
-// Time every instantiated shape on this problem (one full evaluation each, after a warm-up) and keep
-// the fastest, separately for the plain pass and the pass with tangents. The optional cache is a
-// text file of lines "<n_points> <n_pixels> <tan> <ppl> <waves> <tile_pixels> <persistent>".
+// The FP32C shape tuner. Candidates: every instantiated (points per lane, waves per workgroup) shape,
+// in the grid form and the persistent form; then, only where the point tiles alone cannot fill the
+// chip, the pixel split (1..32 slices). A candidate is timed on the bulk kernel alone over a prefix
+// of its cost-ordered schedule (the largest tiles: 16 workgroups per compute unit, or the whole
+// schedule if shorter; one warm-up launch, one timed), at lambda spread over |lambda| < 4 pi / L
+// per component (L the longer side of the point's magnetogram) so that the timed loop is the one
+// solves run, not the lambda = 0 special case. The fastest in pairs per second wins. Choices are
+// kept per process under the key (device architecture, quadrature, pass, size bucket), the bucket
+// being floor(log2) of the point count and of the mean quadrature points per magnetogram, and in
+// the optional text cache as lines "<arch> <quad_points> <log2 N> <log2 pixels> <tan> <ppl> <waves>
+// <tile_pixels> <persistent> <split>".
+namespace {
+
+struct TuneChoice {
+    F32Shape shape;
+    int32_t split;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, TuneChoice>> g_tune_cache;
+
+__global__ void k_tune_lambda(const int32_t* __restrict__ bidx, const BoundaryDev* __restrict__ bnd, int64_t N,
+                              double* __restrict__ lam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const BoundaryDev b = bnd[bidx[i]];
+    const double lm = 4.0 * 3.14159265358979323846 / ((double)max(b.nx, b.ny) * b.h);
+    for (int p = 0; p < 3; ++p) {
+        const double u = (double)(3 * i + p) * 0.6180339887498949;
+        lam[p * N + i] = lm * (2.0 * (u - floor(u)) - 1.0);
+    }
+}
+
+std::string tune_key(const dbie_ctx* c, int tan) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    const int64_t grid = c->G ? c->ngrid_total : c->npix_total;
+    const int bn = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(c->N, 1));
+    const int bp = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(grid / std::max(c->nb, 1), 1));
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%s %d %d %d %d", arch.c_str(), c->G, bn, bp, tan);
+    return buf;
+}
+
+}  // namespace
+
+// Time one candidate (shape sh, and the split c->split_tuned, or the automatic one when that is 0):
+// the bulk kernel over the schedule prefix; returns pairs per millisecond (0 with *rc set on failure).
+static double time_candidate(dbie_ctx* c, F32Shape sh, bool tan, const double* lam, hipEvent_t e0, hipEvent_t e1,
+                             hipStream_t s, int* rc) {
+    *rc = set_tiles32(c, sh, tan);
+    if (*rc) return 0.0;
+    const int32_t S = c->split;
+    const std::vector<Tile>& t = tan ? c->tiles32t_h : c->tiles32_h;
+    const int64_t n_sub = std::min<int64_t>((int64_t)t.size(), 16 * (int64_t)c->cus);
+    double pairs = 0.0;
+    for (int64_t k = 0; k < n_sub; ++k) {
+        const BoundaryDev& b = c->bnd_h[t[k].b];
+        pairs += (double)t[k].count * (double)(c->G ? (int64_t)b.gcols * b.grows : (int64_t)b.nx * b.ny);
+    }
+    if ((*rc = ensure_acc_slices(c, S))) return 0.0;
+    const Tile* dt = tan ? c->tiles32t : c->tiles32;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) {   // a warm-up launch, then the timed one
+        if (r == 1) e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+            e = launch_field32c(dt, n_sub, c->bnd_d, c->pixf, c->gposf, c->geo, lam, c->N, 1, S, c->perm, c->work,
+                                tan, false, sh, c->acc, s);
+    }
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+        *rc = hip_fail(c, e, "tuning events");
+        return 0.0;
+    }
+    return ms > 0.0f ? pairs / (double)ms : 0.0;
+}
+
+static int time_shapes(dbie_ctx* c, TuneChoice best[2], hipStream_t s);
+
 int tune_shapes(dbie_ctx* c, const char* cache_path, hipStream_t s) {
     if (c->N == 0) return DBIE_OK;
-    for (int tan = 0; tan < 2; ++tan) {
-        bool cached = false;
-        if (cache_path) {
-            FILE* f = fopen(cache_path, "r");
-            if (f) {
-                long long n, p;
-                int t, a, b, d, e;
-                while (fscanf(f, "%lld %lld %d %d %d %d %d", &n, &p, &t, &a, &b, &d, &e) == 7) {
-                    if (n == c->N && p == c->npix_total && t == tan && field32c_shape_supported(F32Shape{a, b, d, e})) {
-                        int rc = set_tiles32(c, F32Shape{a, b, d, e}, tan != 0);
-                        if (rc) { fclose(f); return rc; }
-                        cached = true;
-                    }
+    TuneChoice found[2];
+    int have[2] = {0, 0};   // 3: the file, 2: this process's cache
+    std::string key[2] = {tune_key(c, 0), tune_key(c, 1)};
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            char arch[64];
+            int G, bn, bp, t, a, b, d, e, sp;
+            while (fscanf(f, "%63s %d %d %d %d %d %d %d %d %d", arch, &G, &bn, &bp, &t, &a, &b, &d, &e, &sp) == 10) {
+                char k[128];
+                std::snprintf(k, sizeof k, "%s %d %d %d %d", arch, G, bn, bp, t);
+                const F32Shape sh{a, b, d, e};
+                if ((t == 0 || t == 1) && !have[t] && k == key[t] && field32c_shape_supported(sh) && sp >= 1 &&
+                    sp <= kMaxSplit) {
+                    found[t] = TuneChoice{sh, sp};
+                    have[t] = 3;
                 }
-                fclose(f);
             }
+            fclose(f);
         }
-        if (cached) continue;
-        double* lam = (double*)ctx_scratch(c, 3, (size_t)c->N * 3 * sizeof(double));
-        double* out = (double*)ctx_scratch(c, 2, (size_t)c->N * 24 * sizeof(double));
-        if (!lam || !out) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the tuning workspace");
-        DBIE_HIP(c, hipMemsetAsync(lam, 0, (size_t)c->N * 3 * sizeof(double), s));
-        F32Shape cand[16];
-        const int nc = std::min(field32c_shapes(cand, 16), 16);
-        float best = 1e30f;
-        F32Shape bs = tan ? c->shape_tan : c->shape;
-        struct Events {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            ~Events() {
-                if (e0) (void)hipEventDestroy(e0);
-                if (e1) (void)hipEventDestroy(e1);
-            }
-        } ev;
-        DBIE_HIP(c, hipEventCreate(&ev.e0));
-        DBIE_HIP(c, hipEventCreate(&ev.e1));
-        for (int k = 0; k < nc; ++k) {
-            int rc = set_tiles32(c, cand[k], tan != 0);
-            if (rc) return rc;
-            rc = eval_core(c, lam, 1, false, tan != 0, nullptr, out, out + 3 * c->N, nullptr,
-                           tan ? out + 12 * c->N : nullptr, s);
-            if (rc) return rc;
-            DBIE_HIP(c, hipEventRecord(ev.e0, s));
-            for (int r = 0; r < 2; ++r) {
-                rc = eval_core(c, lam, 1, false, tan != 0, nullptr, out, out + 3 * c->N, nullptr,
-                               tan ? out + 12 * c->N : nullptr, s);
-                if (rc) return rc;
-            }
-            DBIE_HIP(c, hipEventRecord(ev.e1, s));
-            DBIE_HIP(c, hipEventSynchronize(ev.e1));
-            float ms = 0.0f;
-            DBIE_HIP(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
-            if (ms < best) {
-                best = ms;
-                bs = cand[k];
-            }
-        }
-        int rc = set_tiles32(c, bs, tan != 0);
+    }
+    if (!(have[0] && have[1])) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        have[0] = have[1] = 0;
+        for (auto& kv : g_tune_cache)
+            for (int tan = 0; tan < 2; ++tan)
+                if (kv.first == key[tan]) {
+                    found[tan] = kv.second;
+                    have[tan] = 2;
+                }
+    }
+    const bool file_lacks = cache_path && !(have[0] == 3 && have[1] == 3);
+    TuneChoice best[2];
+    if (have[0] && have[1]) {
+        best[0] = found[0];
+        best[1] = found[1];
+        c->tuned = have[0];
+    } else {
+        const int rc = time_shapes(c, best, s);
         if (rc) return rc;
-        if (cache_path) {
-            FILE* f = fopen(cache_path, "a");
-            if (f) {
-                fprintf(f, "%lld %lld %d %d %d %d %d\n", (long long)c->N, (long long)c->npix_total, tan, bs.ppl,
-                        bs.waves, bs.tp, bs.persist);
-                fclose(f);
+        c->tuned = 1;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int tan = 0; tan < 2; ++tan) {
+            TuneChoice ch{best[tan].shape, best[0].split};
+            bool replaced = false;
+            for (auto& kv : g_tune_cache)
+                if (kv.first == key[tan]) {
+                    kv.second = ch;
+                    replaced = true;
+                }
+            if (!replaced) g_tune_cache.emplace_back(key[tan], ch);
+        }
+    }
+    // the split is tuned with the plain pass and shared by both
+    c->split_tuned = c->opt.pixel_split > 0 ? 0 : best[0].split;
+    int rc = set_tiles32(c, best[0].shape, false);
+    if (!rc) rc = set_tiles32(c, best[1].shape, true);
+    if (rc) return rc;
+    if (file_lacks) {
+        if (FILE* f = fopen(cache_path, "a")) {
+            for (int tan = 0; tan < 2; ++tan)
+                fprintf(f, "%s %d %d %d %d %d\n", key[tan].c_str(), best[tan].shape.ppl, best[tan].shape.waves,
+                        best[tan].shape.tp, best[tan].shape.persist, best[0].split);
+            fclose(f);
+        }
+    }
+    return DBIE_OK;
+}
+
+// Time the candidates (see tune_shapes) on this context; best[0] is the plain pass (with the split),
+// best[1] the pass with tangents.
+static int time_shapes(dbie_ctx* c, TuneChoice best[2], hipStream_t s) {
+    double* lam = (double*)ctx_scratch(c, 3, (size_t)c->N * 3 * sizeof(double));
+    if (!lam) return fail(c, DBIE_E_WORKSPACE, "cannot allocate the tuning workspace");
+    hipLaunchKernelGGL(k_tune_lambda, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, s, c->geo.bidx, c->bnd_d,
+                       c->N, lam);
+    DBIE_HIP(c, hipGetLastError());
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    DBIE_HIP(c, hipEventCreate(&ev.e0));
+    DBIE_HIP(c, hipEventCreate(&ev.e1));
+    F32Shape cand[16];
+    const int nc = std::min(field32c_shapes(cand, 16), 16);
+    for (int tan = 0; tan < 2; ++tan) {
+        double rate = -1.0;
+        best[tan] = TuneChoice{tan ? c->shape_tan : c->shape, c->split};
+        for (int k = 0; k < nc; ++k) {
+            int rc = 0;
+            c->split_tuned = tan ? best[0].split : 0;
+            const double r = time_candidate(c, cand[k], tan != 0, lam, ev.e0, ev.e1, s, &rc);
+            if (rc) return rc;
+            // the automatic split of this shape (set by set_tiles32) goes with it
+            if (r > rate) {
+                rate = r;
+                best[tan] = TuneChoice{cand[k], c->split};
+            }
+        }
+        // few points: the pixel split, with the chosen shape (the persistent form needs one slice)
+        if (tan == 0 && c->opt.pixel_split == 0 && best[0].split > 1) {
+            F32Shape sh = best[0].shape;
+            sh.persist = 0;
+            for (int32_t S = 1; S <= kMaxSplit; S *= 2) {
+                int rc = 0;
+                c->split_tuned = S;
+                const double r = time_candidate(c, sh, false, lam, ev.e0, ev.e1, s, &rc);
+                if (rc) return rc;
+                if (r > rate) {
+                    rate = r;
+                    best[0] = TuneChoice{sh, S};
+                }
             }
         }
     }

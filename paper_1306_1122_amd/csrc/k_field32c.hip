@@ -18,7 +18,8 @@
 //   H = t^2 cos t - 3 N, the two-operation form Q = -H / 3 = N - (Lambda^2 / 3) rho^2 cos t;
 //   A0 += N rho^-3 B0,  A1 += Q rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += Q rho^-3 B0 rho^-2
 //   (the totals of A1..A3 are multiplied by -3 when written), and with tangents
-//   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy.
+//   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy; there Q rho^-3 B0 is formed
+//   as N rho^-3 B0 + (-Lambda^2 / 3) (cos t rho^-1 B0), sharing the T0 term.
 // SCALAR: the three components share one lambda, so t, sin, cos, N and Q are computed once per pair.
 // Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
 // FP64 totals, so the error does not grow with the magnetogram size.
@@ -76,17 +77,21 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
         const float cs = __builtin_amdgcn_cosf(tr);
         const float t = hi * kTwoPiF;
         const float n = fmaf(t, sn, cs);
-        const float hh = fmaf(nl3[p] * r2, cs, n);   // -H / 3
-        const float rb = TAN ? ri * b0[p] : 0.0f;
-        const float b3 = TAN ? rb * ri2 : ri3 * b0[p];
-        const float hb = hh * b3;
+        float hb;
         if (TAN) {
-            const float nb = n * b3;
+            // -H/3 B0 / r^3 = N B0 / r^3 + (-Lambda^2 / 3) cos t B0 / r, since r^2 B0 / r^3 = B0 / r:
+            // cos t B0 / r is the T0 term, so -H/3 costs one FMA
+            const float rb = ri * b0[p];
+            const float nb = n * (rb * ri2);
+            const float crb = cs * rb;
+            hb = fmaf(nl3[p], crb, nb);
             acc[4 * p + 0] += nb;
-            acc[12 + 3 * p + 0] = fmaf(cs, rb, acc[12 + 3 * p + 0]);
+            acc[12 + 3 * p + 0] += crb;
             acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
             acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
         } else {
+            const float b3 = ri3 * b0[p];
+            hb = fmaf(nl3[p] * r2, cs, n) * b3;   // -H / 3 times B0 / r^3
             acc[4 * p + 0] = fmaf(n, b3, acc[4 * p + 0]);
         }
         acc[4 * p + 1] = fmaf(hb, dxr, acc[4 * p + 1]);

@@ -400,6 +400,14 @@ def dbie_query_split(ctx: Context) -> int:
     return int(v.value)
 
 
+def dbie_query_tuned(ctx: Context) -> int:
+    """0 untuned, 1 timed by this context's init, 2 reused from this process's tuner cache, 3 read from
+    the tune_cache file."""
+    v = ctypes.c_int32()
+    _check(_lib().dbie_query_tuned(ctx.handle, ctypes.byref(v)), ctx, "dbie_query_tuned")
+    return int(v.value)
+
+
 def dbie_workspace_bytes(ctx: Context) -> int:
     return int(_lib().dbie_workspace_bytes(ctx.handle))
 

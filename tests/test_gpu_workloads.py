@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import paper_1306_1122_amd as D
-from workloads import config2, config4, config5
+from workloads import config2, config3, config4, config5
 
 pytestmark = pytest.mark.gpu
 
@@ -102,12 +102,17 @@ def test_tuner_picks_an_instantiated_shape_and_results_do_not_change():
         ctx = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", tune=True,
                           tune_cache=cache)
         q, qt = D.dbie_query(ctx), D.dbie_query_tan(ctx)
-        lines = open(cache).read().split("\n")
-        assert len([l for l in lines if l.strip()]) == 2
-        # a second context reads the cache and gets the same shapes
+        # timed here, or reused from an earlier context of this process with the same key
+        assert D.dbie_query_tuned(ctx) in (1, 2)
+        lines = [l.split() for l in open(cache).read().split("\n") if l.strip()]
+        assert len(lines) == 2 and [l[4] for l in lines] == ["0", "1"]   # the plain pass, then tangents
+        assert lines[0][0].startswith("gfx") and lines[0][2:4] == ["16", "14"]   # 2^16 points, 2^14 pixels
+        # a second context reads the file and gets the same shapes and split
         ctx2 = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", tune=True,
                            tune_cache=cache)
+        assert D.dbie_query_tuned(ctx2) == 3
         assert D.dbie_query(ctx2) == q and D.dbie_query_tan(ctx2) == qt
+        assert D.dbie_query_split(ctx2) == D.dbie_query_split(ctx)
     r1 = D.dbie_eval_field(ctx, lam, want_tan=True)
     torch.cuda.synchronize()
     # a different tile shape changes only the order of the FP32 partial sums
@@ -118,6 +123,50 @@ def test_tuner_picks_an_instantiated_shape_and_results_do_not_change():
     assert D.dbie_query(ctx)["ppl"] == 1 and D.dbie_query(ctx)["waves"] == 8
     with pytest.raises(D.DbieError, match="not instantiated"):
         D.dbie_set_tile_shape(ctx, 3, 4, 256)
+
+
+def test_tuner_reuses_its_choice_within_a_size_bucket():
+    """A context whose key (architecture, quadrature, pass, floor(log2) of the point count and of the
+    pixels per magnetogram) matches an earlier one reuses that choice without timing; its results
+    agree with an untuned context's (the shape changes only which lane sums a point)."""
+    w4, w6 = config2(nz=4), config2(nz=6)     # 65,536 and 98,304 points: both 2^16 <= N < 2^17
+    B0 = T(w4.boundaries[0].B0)
+    a = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], T(w4.xyz), precision="fp32c", tune=True)
+    assert D.dbie_query_tuned(a) in (1, 2)
+    b = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], T(w6.xyz), precision="fp32c", tune=True)
+    assert D.dbie_query_tuned(b) == 2
+    shape = lambda c: {k: D.dbie_query(c)[k] for k in ("ppl", "waves", "tile_pixels")}  # noqa: E731
+    assert shape(b) == shape(a) and D.dbie_query_tan(b) == D.dbie_query_tan(a)
+    assert D.dbie_query_persistent(b) == D.dbie_query_persistent(a)
+    assert D.dbie_query_split(b) == D.dbie_query_split(a)
+    ref = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], T(w6.xyz), precision="fp32c")
+    assert D.dbie_query_tuned(ref) == 0
+    lam = T(w6.lam)
+    r0 = D.dbie_eval_field(ref, lam, want_tan=True)
+    r1 = D.dbie_eval_field(b, lam, want_tan=True)
+    torch.cuda.synchronize()
+    for k in ("B", "dB", "tan"):
+        assert rel(r1[k].cpu(), r0[k].cpu()) <= 1e-12, k
+
+
+def test_tuner_with_few_points_picks_a_split():
+    """With few points (a 2,000-point evaluation over the 256x256 magnetogram: 8 point tiles) the tuner
+    also times the pixel split; the result agrees with an untuned context's to FP64 regrouping."""
+    w = config3(nz=1)
+    bd = w.boundaries[0]
+    idx = np.random.default_rng(3).choice(w.n_points, 2000, replace=False)
+    xyz, lam = T(w.xyz[:, idx]), T(w.lam[:, idx])
+    B0 = T(bd.B0)
+    ctx = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", tune=True)
+    ref = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", pixel_split=1)
+    S = D.dbie_query_split(ctx)
+    print("tuned split for 2000 points:", S, "shape", D.dbie_query(ctx), flush=True)
+    assert 1 <= S <= 32 and D.dbie_query_tuned(ctx) in (1, 2)
+    r0 = D.dbie_eval_field(ref, lam, want_tan=True)
+    r1 = D.dbie_eval_field(ctx, lam, want_tan=True)
+    torch.cuda.synchronize()
+    for k in ("B", "dB", "tan"):
+        assert rel(r1[k].cpu(), r0[k].cpu()) <= 1e-12, k
 
 
 def test_persistent_form_equals_grid_launch(batched):
