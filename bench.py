@@ -207,6 +207,7 @@ def time_to_solution(D, dev, n_sample=65536, eps=1e-4, workload="config3", nm_bu
              "fast": ("fast_fp32c_levenberg_marquardt", "fp32c", "lm", lm_budget)}
     run = [table[f] for f in forms]
     for form, prec, meth, budget in run:
+        print(f"time to solution: {form} on {res['workload']}", file=sys.stderr, flush=True)
         ctx = ctx64 if prec == "fp64" else D.dbie_init([dict(B0=B0, x0=bd.x0, y0=bd.y0, h=bd.h)], xyz,
                                                         precision=prec)
         lam = torch.zeros(3, n, dtype=torch.float64, device=dev)

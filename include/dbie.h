@@ -146,10 +146,14 @@ typedef struct {
 DBIE_API int dbie_default_options(dbie_options* opt);
 DBIE_API int dbie_default_solve_opts(dbie_solve_opts* opt);
 
-/* Create a context on the current HIP device: copy B0 and xyz into library-owned device memory,
- * validate the points (z > 0 and finite; checked on the device, then synchronised), classify the
- * near-field pairs and build the tile schedule. `opt` may be NULL (defaults). On failure *out is
- * NULL. Synchronises `stream`. */
+/* Create a context on the current HIP device. It stages the problem of Section 2.1: the boundary
+ * condition B = B0 on z = 0 with the field zero outside the magnetogram (Eq. 3 and the text around
+ * it), so that the sums of Eq. 16 run over the given pixels only (with quad_points > 0, over the
+ * Gauss points of the Eq. 15 elements, whose weighted field is formed here), and the evaluation
+ * points above the boundary. It copies B0 and xyz into library-owned device memory (B0 also as FP32
+ * blocks for DBIE_FP32C), validates the points (z > 0 and finite; checked on the device, then
+ * synchronised), classifies the near-field pairs and builds the tile schedules (timing shapes when
+ * opt->tune). `opt` may be NULL (defaults). On failure *out is NULL. Synchronises `stream`. */
 DBIE_API int dbie_init(dbie_ctx** out, const dbie_problem* prob, const dbie_options* opt, void* stream);
 
 /* Evaluate L lambda trials at every point (Eqs. 6, 13, 14, 8, 9).
@@ -197,7 +201,8 @@ DBIE_API int dbie_eval_field_scalar(dbie_ctx* ctx, const double* lambda, int32_t
  * count per few rounds (synchronising `stream`), and the number of converged points once more before an
  * FP64 confirmation, and returns when every point is done. The rounds
  * between two reads are captured once into a HIP graph per context and configuration and replayed
- * (not while timing or tracing is enabled). */
+ * (not while timing or tracing is enabled). With the environment variable DBIE_PROGRESS set, the host
+ * reports the round and the active-point count on stderr at those reads, at most every 20 s. */
 DBIE_API int dbie_solve_lambda(dbie_ctx* ctx, double* lambda_inout, const dbie_solve_opts* opt,
                                double* B, double* fg, int32_t* status, int32_t* trials, void* stream);
 

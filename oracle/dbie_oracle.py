@@ -65,7 +65,7 @@ def pixel_centres(nx: int, ny: int, x0: float, y0: float, h: float):
 # ------------------------------------------------------------------------------------------------
 # Eq. (16) nodal sum + frozen-lambda derivatives (Eq. 13) + mu-tangents
 # ------------------------------------------------------------------------------------------------
-def field(B0, x0, y0, h, xyz, lam, tangents: bool = False, chunk: int = 64):
+def field(B0, x0, y0, h, xyz, lam, tangents: bool = False, chunk: int = 64, absolute: bool = False):
     """Field, frozen-lambda gradient and (optionally) mu-tangents at every point.
 
     B0: [3, ny, nx]; xyz: [3, N]; lam: [3, N] (lambda_p for p = x, y, z).
@@ -78,6 +78,10 @@ def field(B0, x0, y0, h, xyz, lam, tangents: bool = False, chunk: int = 64):
       dB_p/dx  = (z h^2 / 2pi) sum_k F'(r) (x_i - x_k)/r B0_pk      (and likewise y)
       dB_p/dz  = (h^2 / 2pi)   sum_k [F + z^2 F'(r)/r] B0_pk
     and dF/dmu = cos(t)/(2r), d(F'/r)/dmu = -N/(2 r^3).
+
+    absolute=True also returns, after the others, the same rows summed over the absolute values of
+    their terms (sum_k |term_k|, with the same prefactors): the scale that bounds the rounding error
+    of any summation order of each row.
     """
     B0 = np.asarray(B0, np.float64)
     xyz = np.asarray(xyz, np.float64)
@@ -89,6 +93,9 @@ def field(B0, x0, y0, h, xyz, lam, tangents: bool = False, chunk: int = 64):
     B = np.zeros((3, npts))
     dB = np.zeros((9, npts))
     tan = np.zeros((12, npts)) if tangents else None
+    if absolute:
+        aB, adB = np.zeros((3, npts)), np.zeros((9, npts))
+        atan = np.zeros((12, npts)) if tangents else None
     w = h * h / TWO_PI
     for s in range(0, npts, chunk):
         e = min(npts, s + chunk)
@@ -111,6 +118,11 @@ def field(B0, x0, y0, h, xyz, lam, tangents: bool = False, chunk: int = 64):
             dB[3 * p + 0, s:e] = -w * z * np.sum(G * dx * b, axis=1)
             dB[3 * p + 1, s:e] = -w * z * np.sum(G * dy * b, axis=1)
             dB[3 * p + 2, s:e] = w * np.sum((F + z[:, None] ** 2 * G) * b, axis=1)
+            if absolute:
+                aB[p, s:e] = w * z * np.sum(np.abs(F * b), axis=1)
+                adB[3 * p + 0, s:e] = w * z * np.sum(np.abs(G * dx * b), axis=1)
+                adB[3 * p + 1, s:e] = w * z * np.sum(np.abs(G * dy * b), axis=1)
+                adB[3 * p + 2, s:e] = w * np.sum(np.abs((F + z[:, None] ** 2 * G) * b), axis=1)
             if tangents:
                 dF = cs / (2.0 * r)                       # dF/dmu
                 dG = -N / (2.0 * r2 * r)                  # d(F'/r)/dmu
@@ -118,9 +130,15 @@ def field(B0, x0, y0, h, xyz, lam, tangents: bool = False, chunk: int = 64):
                 tan[3 + 3 * p + 0, s:e] = -w * z * np.sum(dG * dx * b, axis=1)
                 tan[3 + 3 * p + 1, s:e] = -w * z * np.sum(dG * dy * b, axis=1)
                 tan[3 + 3 * p + 2, s:e] = w * np.sum((dF + z[:, None] ** 2 * dG) * b, axis=1)
-    if tangents:
-        return B, dB, tan
-    return B, dB
+                if absolute:
+                    atan[p, s:e] = w * z * np.sum(np.abs(dF * b), axis=1)
+                    atan[3 + 3 * p + 0, s:e] = w * z * np.sum(np.abs(dG * dx * b), axis=1)
+                    atan[3 + 3 * p + 1, s:e] = w * z * np.sum(np.abs(dG * dy * b), axis=1)
+                    atan[3 + 3 * p + 2, s:e] = w * np.sum(np.abs((dF + z[:, None] ** 2 * dG) * b), axis=1)
+    out = (B, dB, tan) if tangents else (B, dB)
+    if absolute:
+        out = out + ((aB, adB, atan) if tangents else (aB, adB))
+    return out
 
 
 def field_only(B0, x0, y0, h, xyz, lam, chunk: int = 64):

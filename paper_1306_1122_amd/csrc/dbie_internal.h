@@ -164,6 +164,50 @@ __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const
     }
 }
 
+// FP64 pairs of the near-field window (shared by the finalize pass and the FP64 recompute of
+// high-phase points) (the bits set in dbie_init's classification).
+template <bool TAN, bool WIDE>
+__device__ __forceinline__ void add_near(const BoundaryDev& bd, const double* B0, uint32_t mask,
+                                         int32_t wa, int32_t wb, double u, double v, double w2,
+                                         const double lm[3], double* a) {
+    while (mask) {
+        const int bit = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const int ii = bit % kNearSide - kNearWin, jj = bit / kNearSide - kNearWin;
+        const int32_t pa = wa + ii, pb = wb + jj;
+        const int64_t k = (int64_t)pb * bd.nx + pa;
+        pair_fp64<TAN, WIDE>((double)pa - u, (double)pb - v, w2, lm, B0[k], B0[bd.npix + k],
+                       B0[2 * (int64_t)bd.npix + k], a);
+    }
+}
+
+// 9-node elements: every Gauss point of each element flagged near, at its FP64 position, with the
+// FP64 weighted field of the quadrature grid.
+template <bool TAN, bool WIDE>
+__device__ __forceinline__ void add_near_grid(const BoundaryDev& bd, const double* __restrict__ gpos,
+                                              const double* __restrict__ gB, uint32_t mask, int32_t wa,
+                                              int32_t wb, double u, double v, double w2, const double lm[3],
+                                              double* a) {
+    const double* cpos = gpos + bd.gpos_off;
+    const double* rpos = cpos + bd.gcols;
+    const int64_t ng = (int64_t)bd.gcols * bd.grows;
+    const double* W = gB + bd.gpl_off;
+    while (mask) {
+        const int bit = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const int32_t m = wa + bit % kNearSideQ - kNearWinQ, n = wb + bit / kNearSideQ - kNearWinQ;
+        for (int q = 0; q < bd.G; ++q) {
+            const int32_t r = bd.G * n + q;
+            const double dy = rpos[r] - v;
+            for (int g = 0; g < bd.G; ++g) {
+                const int32_t c = bd.G * m + g;
+                const int64_t k = (int64_t)r * bd.gcols + c;
+                pair_fp64<TAN, WIDE>(cpos[c] - u, dy, w2, lm, W[k], W[ng + k], W[2 * ng + k], a);
+            }
+        }
+    }
+}
+
 // ---- residuals (Eqs. 8, 9, 14) in FP64 -------------------------------------------------------
 enum : int32_t { kStConverged = 0, kStBudget = 1, kStDegenerate = 2, kStJZero = 3, kStNonfinite = 4 };
 
@@ -260,6 +304,17 @@ hipError_t launch_expand_scalar(const double* lam, int32_t L, int64_t N, double*
 hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
                           const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
                           int32_t L, int32_t S, const int32_t* idx, bool tan, double* acc, hipStream_t s);
+// FP32C contexts, after the FP32 bulk pass: recompute in FP64 (and overwrite) the partial sums of the
+// points whose largest phase max_p |lambda_p| r_max exceeds phase_max radians (see k_field64.hip).
+hipError_t launch_field64_override(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
+                                   const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
+                                   int32_t L, int32_t S, const int32_t* idx, bool tan, double phase_max, double* acc,
+                                   hipStream_t s);
+// Largest phase max_p |lambda_p| r_max (radians) up to which the FP32C bulk pass keeps its error
+// below its 1e-5 relative bar: without and with the mu-tangents (the tangent rows' weights decay
+// only as 1/r, so the far pixels, whose phases carry the most FP32 rounding, dominate them).
+constexpr double kFp32cPhaseMax = 2.0 * 3.14159265358979323846 * 512.0;
+constexpr double kFp32cPhaseMaxTan = 2.0 * 3.14159265358979323846 * 128.0;
 
 // The weighted field of the 9-node element quadrature grid: gB = w_g w_q sum L_a(xi_g) L_b(xi_q) B0
 // (lw[3 * g + a] = w_g L_a(xi_g), G points per element side).

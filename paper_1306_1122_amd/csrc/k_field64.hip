@@ -10,23 +10,31 @@
 // each writing its own partial ([S][L][kAcc][N], added in order by the finalize pass). sin and cos
 // come from the branch-free reduced form unless some pair of the workgroup's points can exceed its
 // argument bound (then, and for NaN lambda, from the device library).
+//
+// OVR (FP32C contexts, after the FP32 bulk pass): the same sums in FP64 for the points whose phase
+// can exceed the FP32 accuracy bound, max_p |lambda_p| r_max > phase_max with r_max the largest
+// distance from the point to its magnetogram's quadrature grid. Only those points' partial sums are
+// overwritten (every slice); their near-field pairs, which the finalize pass adds in FP64 as for every
+// FP32C point, are subtracted here, so that each pair is counted once. A workgroup without such a
+// point returns at once.
 #include "dbie_internal.h"
 
 namespace dbie {
 
 constexpr int kTP64 = 128;
 
-template <bool TAN>
+template <bool TAN, bool OVR>
 __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
                                                  const BoundaryDev* __restrict__ bnd,
                                                  const double* __restrict__ gpos,
                                                  const double* __restrict__ gB, Geo geo,
                                                  const double* __restrict__ lam, int64_t N,
                                                  const int32_t* __restrict__ idx,
-                                                 double* __restrict__ acc) {
+                                                 double* __restrict__ acc, const double* __restrict__ B0d,
+                                                 double phase_max) {
     constexpr int NA = TAN ? kAcc : kAccField;
     __shared__ double sa[kTP64], sb[kTP64], sx[kTP64], sy[kTP64], sz[kTP64];
-    __shared__ int s_wide;
+    __shared__ int s_wide, s_any;
     const Tile t = tiles[blockIdx.x];
     const int trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
@@ -47,18 +55,22 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
         // the largest |lambda r| of the workgroup's pairs (grid positions lie in [0, nx - 1] x
         // [0, ny - 1]) selects the sin/cos: the branch-free reduced form, or the library's for
         // arguments beyond its range (and for NaN lambda)
+        bool mine = live;   // OVR: this lane's point is recomputed
         {
             const double dxm = fmax(fabs(u), fabs((double)(bd.nx - 1) - u));
             const double dym = fmax(fabs(v), fabs((double)(bd.ny - 1) - v));
             const double rmax = sqrt(dxm * dxm + dym * dym + w2);
             const double tmax = fmax(fabs(lm[0]), fmax(fabs(lm[1]), fabs(lm[2]))) * rmax;
+            if (OVR) mine = live && !(tmax <= phase_max);   // NaN lambda included
             __syncthreads();
-            if (threadIdx.x == 0) s_wide = 0;
+            if (threadIdx.x == 0) s_wide = s_any = 0;
             __syncthreads();
-            if (live && !(tmax < kSincosBound)) s_wide = 1;
+            if (mine && !(tmax < kSincosBound)) s_wide = 1;
+            if (OVR && mine) s_any = 1;
             __syncthreads();
         }
         const bool wide = s_wide != 0;
+        if (OVR && s_any == 0) continue;   // uniform over the workgroup
         double tot[NA];
 #pragma unroll
         for (int r = 0; r < NA; ++r) tot[r] = 0.0;
@@ -90,7 +102,26 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
 #pragma unroll
             for (int r = 0; r < NA; ++r) tot[r] += part[r];
         }
-        if (live) {
+        if (OVR && mine && blockIdx.z == 0) {
+            // the finalize pass adds this point's near pairs: take them out of the full sum
+            const uint32_t mask = geo.near_mask[i];
+            if (mask) {
+                double nr[NA];
+#pragma unroll
+                for (int r = 0; r < NA; ++r) nr[r] = 0.0;
+                const bool wn = !(fmax(fabs(lm[0]), fmax(fabs(lm[1]), fabs(lm[2]))) * 64.0 < kSincosBound);
+                if (bd.G > 0) {
+                    if (wn) add_near_grid<TAN, true>(bd, gpos, gB, mask, geo.win_a[i], geo.win_b[i], u, v, w2, lm, nr);
+                    else add_near_grid<TAN, false>(bd, gpos, gB, mask, geo.win_a[i], geo.win_b[i], u, v, w2, lm, nr);
+                } else {
+                    if (wn) add_near<TAN, true>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], u, v, w2, lm, nr);
+                    else add_near<TAN, false>(bd, B0d + bd.pix_off, mask, geo.win_a[i], geo.win_b[i], u, v, w2, lm, nr);
+                }
+#pragma unroll
+                for (int r = 0; r < NA; ++r) tot[r] -= nr[r];
+            }
+        }
+        if (OVR ? mine : live) {
 #pragma unroll
             for (int r = 0; r < NA; ++r)
                 acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + i] = tot[r];
@@ -104,9 +135,26 @@ hipError_t launch_field64(const Tile* tiles, int64_t n_tiles, const BoundaryDev*
     if (n_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)n_tiles, (unsigned)L, (unsigned)S);
     if (tan)
-        hipLaunchKernelGGL(k_field64<true>, grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx, acc);
+        hipLaunchKernelGGL((k_field64<true, false>), grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
+                           acc, nullptr, 0.0);
     else
-        hipLaunchKernelGGL(k_field64<false>, grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx, acc);
+        hipLaunchKernelGGL((k_field64<false, false>), grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
+                           acc, nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_field64_override(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const double* B0d,
+                                   const double* gpos, const double* gB, Geo geo, const double* lam, int64_t N,
+                                   int32_t L, int32_t S, const int32_t* idx, bool tan, double phase_max, double* acc,
+                                   hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    const dim3 grid((unsigned)n_tiles, (unsigned)L, (unsigned)S);
+    if (tan)
+        hipLaunchKernelGGL((k_field64<true, true>), grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
+                           acc, B0d, phase_max);
+    else
+        hipLaunchKernelGGL((k_field64<false, true>), grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
+                           acc, B0d, phase_max);
     return hipGetLastError();
 }
 

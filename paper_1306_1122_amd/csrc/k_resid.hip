@@ -30,49 +30,6 @@ __device__ __forceinline__ void scale_sums(const double* a, double w, double h, 
     }
 }
 
-// FP64 pairs of the near-field window (the bits set in dbie_init's classification).
-template <bool TAN, bool WIDE>
-__device__ __forceinline__ void add_near(const BoundaryDev& bd, const double* B0, uint32_t mask,
-                                         int32_t wa, int32_t wb, double u, double v, double w2,
-                                         const double lm[3], double* a) {
-    while (mask) {
-        const int bit = __builtin_ctz(mask);
-        mask &= mask - 1u;
-        const int ii = bit % kNearSide - kNearWin, jj = bit / kNearSide - kNearWin;
-        const int32_t pa = wa + ii, pb = wb + jj;
-        const int64_t k = (int64_t)pb * bd.nx + pa;
-        pair_fp64<TAN, WIDE>((double)pa - u, (double)pb - v, w2, lm, B0[k], B0[bd.npix + k],
-                       B0[2 * (int64_t)bd.npix + k], a);
-    }
-}
-
-// 9-node elements: every Gauss point of each element flagged near, at its FP64 position, with the
-// FP64 weighted field of the quadrature grid.
-template <bool TAN, bool WIDE>
-__device__ __forceinline__ void add_near_grid(const BoundaryDev& bd, const double* __restrict__ gpos,
-                                              const double* __restrict__ gB, uint32_t mask, int32_t wa,
-                                              int32_t wb, double u, double v, double w2, const double lm[3],
-                                              double* a) {
-    const double* cpos = gpos + bd.gpos_off;
-    const double* rpos = cpos + bd.gcols;
-    const int64_t ng = (int64_t)bd.gcols * bd.grows;
-    const double* W = gB + bd.gpl_off;
-    while (mask) {
-        const int bit = __builtin_ctz(mask);
-        mask &= mask - 1u;
-        const int32_t m = wa + bit % kNearSideQ - kNearWinQ, n = wb + bit / kNearSideQ - kNearWinQ;
-        for (int q = 0; q < bd.G; ++q) {
-            const int32_t r = bd.G * n + q;
-            const double dy = rpos[r] - v;
-            for (int g = 0; g < bd.G; ++g) {
-                const int32_t c = bd.G * m + g;
-                const int64_t k = (int64_t)r * bd.gcols + c;
-                pair_fp64<TAN, WIDE>(cpos[c] - u, dy, w2, lm, W[k], W[ng + k], W[2 * ng + k], a);
-            }
-        }
-    }
-}
-
 template <bool TAN, bool NEAR>
 __global__ __launch_bounds__(256) void k_finalize(const BoundaryDev* __restrict__ bnd,
                                                   const double* __restrict__ B0d,

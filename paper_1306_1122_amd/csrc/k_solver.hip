@@ -16,7 +16,10 @@
 //  * Levenberg-Marquardt in mu = lambda^2 >= 0 (the gradient form): the 4x3 Jacobian of the residual
 //    vector u = (J x B / (|J||B|), sign(div B) g) from the mu-tangents, Marquardt scaling, nu /= 10 on
 //    acceptance (Phi falls) and nu *= 10 on rejection, projection into [0, cap^2].
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -906,6 +909,10 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     };
     int32_t rounds = 0;
     const int32_t check_every = 4;
+    // with DBIE_PROGRESS set in the environment, long solves report their round and active count on
+    // stderr (at the host's reads of the count, at most every 20 s)
+    const bool progress = std::getenv("DBIE_PROGRESS") != nullptr;
+    auto last_print = std::chrono::steady_clock::now();
     std::vector<hipEvent_t>& trace = solver_trace_events(c);
     hipEvent_t& trace_end = solver_trace_end(c);
     const bool tracing = solver_tracing(c);
@@ -994,6 +1001,12 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         if (rounds < opt->max_trials) {
             SOLVE_HIP(hipMemcpyAsync(ctx_solver(c).count_h, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, rs));
             SOLVE_HIP(hipStreamSynchronize(rs));
+            if (progress && std::chrono::steady_clock::now() - last_print > std::chrono::seconds(20)) {
+                last_print = std::chrono::steady_clock::now();
+                std::fprintf(stderr, "dbie_solve_lambda: %d of %d rounds, %d points active\n", rounds,
+                             opt->max_trials, *ctx_solver(c).count_h);
+                std::fflush(stderr);
+            }
             if (*ctx_solver(c).count_h == 0) break;
         }
     }

@@ -24,6 +24,7 @@ constexpr int kVjpPts = 64;      // points per LDS tile
 constexpr int kVjpCoef = 15;     // Lambda[3], alpha[3], beta[3], gx[3], gy[3]
 constexpr double kInv2Pi_v = 0.15915494309189533577;
 constexpr int kVjpPix = 4;       // pixels per lane of the FP32C adjoint
+constexpr int kVjpPix64 = 2;     // pixels per lane of the FP64 adjoint
 
 struct PixTile {
     int32_t b;
@@ -50,6 +51,7 @@ __global__ void k_vjp_coef(int64_t N, const BoundaryDev* __restrict__ bnd, Geo g
     }
 }
 
+template <int PPX>
 __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptiles,
                                                const BoundaryDev* __restrict__ bnd,
                                                const int64_t* __restrict__ seg, Geo geo, int64_t N,
@@ -57,17 +59,22 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                                                const double* __restrict__ coef, double* __restrict__ gW,
                                                int64_t slice_stride) {
     // sc rows: Lambda[3], alpha[3], then -3 beta[3], -3 gx[3], -3 gy[3] and -Lambda^2/3 [3], so that
-    // H rho^-5 (beta + ...) is summed as (N - (Lambda^2/3) rho^2 cos t) rho^-5 (-3 beta + ...)
+    // H rho^-5 (beta + ...) is summed as (N - (Lambda^2/3) rho^2 cos t) rho^-5 (-3 beta + ...).
+    // Each lane owns PPX pixels (k, k + 256, ...): a point's 21 values read from LDS serve them all.
     __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef + 3][kVjpPts];
     __shared__ int s_wide;
     const PixTile pt = ptiles[blockIdx.x];
     const BoundaryDev bd = bnd[pt.b];
     const int32_t ngrid = bd.gcols * bd.grows;
-    const int32_t k = pt.start + (int32_t)threadIdx.x;
-    const bool live = k < ngrid;
-    const double a = live ? gpos[bd.gpos_off + k % bd.gcols] : 0.0;
-    const double bb = live ? gpos[bd.gpos_off + bd.gcols + k / bd.gcols] : 0.0;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double a[PPX], bb[PPX], acc[PPX][3];
+#pragma unroll
+    for (int j = 0; j < PPX; ++j) {
+        const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
+        const bool live = k < ngrid;
+        a[j] = live ? gpos[bd.gpos_off + k % bd.gcols] : 0.0;
+        bb[j] = live ? gpos[bd.gpos_off + bd.gcols + k / bd.gcols] : 0.0;
+        acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+    }
     const int64_t s0 = seg[pt.b], s1 = seg[pt.b + 1];
     const int64_t nch = (s1 - s0 + kVjpPts - 1) / kVjpPts;
     const int64_t p0 = s0 + (int64_t)blockIdx.y * nch / gridDim.y * kVjpPts;
@@ -101,45 +108,66 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
             }
         }
         __syncthreads();
-        double part[3] = {0.0, 0.0, 0.0};
+        double part[PPX][3];
+#pragma unroll
+        for (int j = 0; j < PPX; ++j) part[j][0] = part[j][1] = part[j][2] = 0.0;
         // the chunk's pairs, with the library's sin/cos (WIDE) or the branch-free reduced form
         auto chunk = [&](auto wide_tag) {
             constexpr bool WIDE = decltype(wide_tag)::value;
             for (int e = 0; e < n; ++e) {
-                const double dx = a - su[e], dy = bb - sv[e];
-                const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, sw2[e]));
-                const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
-                const double r = r2 * ri;
-                const double ri2 = ri * ri;
-                const double ri3 = ri2 * ri;
-                const double ri5 = ri3 * ri2;
+                const double ue = su[e], ve = sv[e], w2 = sw2[e];
+                double L[3], al[3], be[3], gx[3], gy[3], l3[3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
-                    const double t = sc[p][e] * r;
-                    double s, c;
-                    if (WIDE) {
-                        sincos(t, &s, &c);
-                    } else {
-                        const uint64_t sg = sincos_halfturn(t, &s, &c);   // t = k pi + r: (-1)^k
-                        s = flip_sign(s, sg);
-                        c = flip_sign(c, sg);
+                    L[p] = sc[p][e];
+                    al[p] = sc[3 + p][e];
+                    be[p] = sc[6 + p][e];
+                    gx[p] = sc[9 + p][e];
+                    gy[p] = sc[12 + p][e];
+                    l3[p] = sc[kVjpCoef + p][e];
+                }
+#pragma unroll
+                for (int j = 0; j < PPX; ++j) {
+                    const double dx = a[j] - ue, dy = bb[j] - ve;
+                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
+                    const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
+                    const double r = r2 * ri;
+                    const double ri2 = ri * ri;
+                    const double ri3 = ri2 * ri;
+                    const double ri5 = ri3 * ri2;
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        const double t = L[p] * r;
+                        double sn, cs;
+                        if (WIDE) {
+                            sincos(t, &sn, &cs);
+                        } else {
+                            const uint64_t sg = sincos_halfturn(t, &sn, &cs);   // t = k pi + r: (-1)^k
+                            sn = flip_sign(sn, sg);
+                            cs = flip_sign(cs, sg);
+                        }
+                        const double nn = __builtin_fma(t, sn, cs);
+                        const double q = __builtin_fma(l3[p] * r2, cs, nn);   // -H / 3
+                        const double lin = __builtin_fma(gx[p], dx, __builtin_fma(gy[p], dy, be[p]));
+                        part[j][p] = __builtin_fma(nn * ri3, al[p], __builtin_fma(q * ri5, lin, part[j][p]));
                     }
-                    const double nn = __builtin_fma(t, s, c);
-                    const double q = __builtin_fma(sc[kVjpCoef + p][e] * r2, c, nn);   // -H / 3
-                    const double lin =
-                        __builtin_fma(sc[9 + p][e], dx, __builtin_fma(sc[12 + p][e], dy, sc[6 + p][e]));
-                    part[p] = __builtin_fma(nn * ri3, sc[3 + p][e], __builtin_fma(q * ri5, lin, part[p]));
                 }
             }
         };
         if (s_wide != 0) chunk(std::true_type{});
         else chunk(std::false_type{});
-        for (int p = 0; p < 3; ++p) acc[p] += part[p];
+#pragma unroll
+        for (int j = 0; j < PPX; ++j)
+            for (int p = 0; p < 3; ++p) acc[j][p] += part[j][p];
     }
-    if (live) {
-        const int64_t o = bd.gpl_off + k;
-        double* out = gW + (int64_t)blockIdx.y * slice_stride;
-        for (int p = 0; p < 3; ++p) out[o + (int64_t)p * ngrid] = acc[p];
+    double* out = gW + (int64_t)blockIdx.y * slice_stride;
+#pragma unroll
+    for (int j = 0; j < PPX; ++j) {
+        const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
+        if (k < ngrid) {
+            const int64_t o = bd.gpl_off + k;
+            for (int p = 0; p < 3; ++p) out[o + (int64_t)p * ngrid] = acc[j][p];
+        }
     }
 }
 
@@ -396,17 +424,17 @@ using namespace dbie;
 
 namespace dbie {
 // Pixel tiles of the two adjoint kernels and the workspace sizes of dbie_grad's gB0 part.
-// Pixel tiles of every boundary's grid: 256 grid points each (FP64 kernel) and 256 * kVjpPix
-// (FP32C kernel), uploaded once with the point segments.
+// Pixel tiles of every boundary's grid: 256 * kVjpPix64 grid points each (FP64 kernel) and
+// 256 * kVjpPix (FP32C kernel), uploaded once with the point segments.
 hipError_t vjp_tables_init(const dbie_ctx* c, void** dev, VjpTables* t) {
     std::vector<PixTile> pt;
     const int32_t nb = ctx_nb(c);
-    for (int per : {256, 256 * kVjpPix}) {
+    for (int per : {256 * kVjpPix64, 256 * kVjpPix}) {
         for (int32_t b = 0; b < nb; ++b) {
             const BoundaryDev& bd = ctx_bnd_host(c, b);
             for (int32_t k = 0; k < bd.gcols * bd.grows; k += per) pt.push_back(PixTile{b, k});
         }
-        if (per == 256) t->n64 = (int64_t)pt.size();
+        if (per == 256 * kVjpPix64) t->n64 = (int64_t)pt.size();
     }
     t->n32 = (int64_t)pt.size() - t->n64;
     t->seg_off = (pt.size() * sizeof(PixTile) + 255) / 256 * 256;
@@ -497,7 +525,8 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
             hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
         const dim3 g64((unsigned)vt.n64, (unsigned)gp.S), g32((unsigned)vt.n32, (unsigned)gp.S);
         if (ctx_precision(c) == DBIE_FP64) {
-            hipLaunchKernelGGL(k_vjp64, g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos, coef, parts, T3);
+            hipLaunchKernelGGL(k_vjp64<kVjpPix64>, g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos, coef, parts,
+                               T3);
         } else {
             if (grid.G)
                 hipLaunchKernelGGL((k_vjp32c<kVjpPix, true>), g32, dim3(256), 0, s, ptd32, bnd, segd, ctx_perm(c),

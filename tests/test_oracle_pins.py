@@ -420,3 +420,27 @@ def test_vjp_lambda_gradient_matches_differences():
         lp[p] += step
         lmn[p] -= step
         np.testing.assert_allclose(glam[p], (L(lp) - L(lmn)) / (2 * step), atol=1e-6 * np.abs(glam).max())
+
+
+def test_absolute_term_sums():
+    """field(..., absolute=True): with one pixel every row is a single term, so each absolute sum is
+    the row's own magnitude (pins each row's terms and prefactors); with B0 >= 0 at lambda = 0 the
+    terms of B and of the mu-tangent rows tan[p] are all positive, so those sums equal the rows; and
+    in general every absolute sum bounds its row."""
+    rng = np.random.default_rng(41)
+    xyz = np.stack([rng.uniform(-3, 3, 9), rng.uniform(-3, 3, 9), rng.uniform(0.2, 4, 9)])
+    lam = rng.uniform(-1.5, 1.5, size=(3, 9))
+    one = rng.normal(size=(3, 1, 1))
+    B, dB, tan, aB, adB, atan = oracle.field(one, 0.3, -0.2, 0.7, xyz, lam, tangents=True, absolute=True)
+    for a, r in ((aB, B), (adB, dB), (atan, tan)):
+        np.testing.assert_allclose(a, np.abs(r), rtol=1e-13, atol=0)
+    B0 = np.abs(rng.normal(size=(3, 6, 7)))
+    B, dB, tan, aB, adB, atan = oracle.field(B0, 0.0, 0.0, 0.5, xyz, np.zeros((3, 9)), tangents=True, absolute=True)
+    np.testing.assert_allclose(aB, B, rtol=1e-13)
+    np.testing.assert_allclose(atan[:3], tan[:3], rtol=1e-13)
+    B, dB, tan, aB, adB, atan = oracle.field(rng.normal(size=(3, 6, 7)), 0.0, 0.0, 0.5, xyz, lam, tangents=True,
+                                             absolute=True)
+    for a, r in ((aB, B), (adB, dB), (atan, tan)):
+        assert np.all(a >= np.abs(r) * (1 - 1e-13))
+    two = oracle.field(B0, 0.0, 0.0, 0.5, xyz, lam, absolute=True)
+    assert len(two) == 4
