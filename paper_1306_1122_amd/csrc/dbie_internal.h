@@ -126,32 +126,80 @@ __device__ __forceinline__ double flip_sign(double x, uint64_t sign) {
     return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) ^ sign);
 }
 
+// sin and cos of t for |t| < kSincosBound from a table of (sin, cos)(j pi/16), j = 0..31: t =
+// k pi/16 + r with k = rint(16 t / pi) from one FMA that adds 1.5 2^52 (as in sincos_halfturn: the
+// low word of the sum holds k, so k mod 32 is its low five bits), r from a two-constant Cody-Waite
+// reduction with FMA (|r| <= pi/32 up to rounding), sin r and cos r from their Taylor series to r^9
+// and r^10 (coefficients +-1/n! rounded to double; the first terms left out are below 4e-19 and
+// 3e-21 on |r| <= 0.1), and the addition theorems sin t = S cos r + C sin r, cos t = C cos r - S sin r
+// with (S, C) = tab[k mod 32]. About one ulp of 1 absolute. `tab` is kSinCos16 copied to LDS by the
+// calling kernel; the constants come from csrc/sincos_fit.py (`table`).
+static __constant__ double kSinCos16[64] = {
+    0.0, 1.0, 0.19509032201612828, 0.9807852804032304,
+    0.3826834323650898, 0.9238795325112867, 0.5555702330196022, 0.8314696123025452,
+    0.7071067811865476, 0.7071067811865476, 0.8314696123025452, 0.5555702330196022,
+    0.9238795325112867, 0.3826834323650898, 0.9807852804032304, 0.19509032201612828,
+    1.0, 0.0, 0.9807852804032304, -0.19509032201612828,
+    0.9238795325112867, -0.3826834323650898, 0.8314696123025452, -0.5555702330196022,
+    0.7071067811865476, -0.7071067811865476, 0.5555702330196022, -0.8314696123025452,
+    0.3826834323650898, -0.9238795325112867, 0.19509032201612828, -0.9807852804032304,
+    0.0, -1.0, -0.19509032201612828, -0.9807852804032304,
+    -0.3826834323650898, -0.9238795325112867, -0.5555702330196022, -0.8314696123025452,
+    -0.7071067811865476, -0.7071067811865476, -0.8314696123025452, -0.5555702330196022,
+    -0.9238795325112867, -0.3826834323650898, -0.9807852804032304, -0.19509032201612828,
+    -1.0, 0.0, -0.9807852804032304, 0.19509032201612828,
+    -0.9238795325112867, 0.3826834323650898, -0.8314696123025452, 0.5555702330196022,
+    -0.7071067811865476, 0.7071067811865476, -0.5555702330196022, 0.8314696123025452,
+    -0.3826834323650898, 0.9238795325112867, -0.19509032201612828, 0.9807852804032304,
+};
+__device__ __forceinline__ void sincos_table16(double t, const double2* __restrict__ tab, double* s, double* c) {
+    const double kb = __builtin_fma(t, 5.092958178940651, kRoundMagic);
+    const double k = kb - kRoundMagic;
+    double r = __builtin_fma(-k, 0.19634954084936207, t);
+    r = __builtin_fma(-k, 7.654042494670958e-18, r);
+    const double z = r * r;
+    double p = __builtin_fma(z, 2.7557319223985893e-06, -0.0001984126984126984);
+    p = __builtin_fma(z, p, 0.008333333333333333);
+    p = __builtin_fma(z, p, -0.16666666666666666);
+    const double sr = __builtin_fma(r * z, p, r);
+    double q = __builtin_fma(z, -2.755731922398589e-07, 2.48015873015873e-05);
+    q = __builtin_fma(z, q, -0.001388888888888889);
+    q = __builtin_fma(z, q, 0.041666666666666664);
+    const double cr = __builtin_fma(z * z, q, __builtin_fma(z, -0.5, 1.0));
+    const double2 e = tab[(uint32_t)__builtin_bit_cast(uint64_t, kb) & 31u];
+    *s = __builtin_fma(e.y, sr, e.x * cr);
+    *c = __builtin_fma(-e.x, sr, e.y * cr);
+}
+
 // One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
 // dx = a_k - u, dy = b_k - v, w2 = w^2, all in pixels. Shared by the FP64 bulk kernel and the
 // FP64 near-field pass of the FP32C path. WIDE: the device library's sincos (any argument);
-// otherwise every |lambda r| must stay below kSincosBound. H = t^2 cos t - 3 N is summed as
-// (-3 / r^5)(N - (lambda^2 / 3) r^2 cos t): one multiply and one FMA per component, the factor
-// -3 once per pair.
-template <bool TAN, bool WIDE>
+// otherwise every |lambda r| must stay below kSincosBound, and TAB takes sincos_table16 (its table
+// in the caller's LDS) instead of sincos_halfturn. With t^2 = lambda^2 r^2, the gradient term
+// H B0 / r^5 (H = t^2 cos t - 3 N) is formed as (B0 / r^3)((-3 / r^2) N + lambda^2 cos t), sharing
+// B0 / r^3 with the field row: two multiplies and one FMA per component, -3 / r^2 once per pair.
+template <bool TAN, bool WIDE, bool TAB = false>
 __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const double lam[3],
-                                          double b0x, double b0y, double b0z, double* acc) {
+                                          double b0x, double b0y, double b0z, double* acc,
+                                          const double2* __restrict__ tab = nullptr) {
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
     const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
     const double r = r2 * ri;
     const double ri2 = ri * ri;
     const double ri3 = ri2 * ri;
-    const double ri5n3 = ri3 * (-3.0 * ri2);
+    const double ri2n3 = -3.0 * ri2;
     const double b0[3] = {b0x, b0y, b0z};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const double t = lam[p] * r;
         double s, c, bp = b0[p];
         if (WIDE) sincos(t, &s, &c);
+        else if (TAB) sincos_table16(t, tab, &s, &c);
         else bp = flip_sign(bp, sincos_halfturn(t, &s, &c));   // (-1)^k carried by B0
         const double n = __builtin_fma(t, s, c);
-        const double q = __builtin_fma(lam[p] * lam[p] * (-1.0 / 3.0) * r2, c, n);   // -H / 3
-        const double nb = n * (ri3 * bp);
-        const double hb = q * (ri5n3 * bp);
+        const double b3 = ri3 * bp;
+        const double nb = n * b3;
+        const double hb = b3 * __builtin_fma(ri2n3, n, lam[p] * lam[p] * c);   // H B0 / r^5
         acc[4 * p + 0] += nb;
         acc[4 * p + 1] = __builtin_fma(hb, dx, acc[4 * p + 1]);
         acc[4 * p + 2] = __builtin_fma(hb, dy, acc[4 * p + 2]);

@@ -34,7 +34,9 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
                                                  double phase_max) {
     constexpr int NA = TAN ? kAcc : kAccField;
     __shared__ double sa[kTP64], sb[kTP64], sx[kTP64], sy[kTP64], sz[kTP64];
+    __shared__ double2 stab[32];   // (sin, cos)(j pi / 16) for sincos_table16
     __shared__ int s_wide, s_any;
+    if (threadIdx.x < 32) stab[threadIdx.x] = make_double2(kSinCos16[2 * threadIdx.x], kSinCos16[2 * threadIdx.x + 1]);
     const Tile t = tiles[blockIdx.x];
     const int trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
                     pair_fp64<TAN, true>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
             else
                 for (int k = 0; k < kn; ++k)
-                    pair_fp64<TAN, false>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
+                    pair_fp64<TAN, false, true>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part, stab);
 #pragma unroll
             for (int r = 0; r < NA; ++r) tot[r] += part[r];
         }

@@ -1,4 +1,6 @@
-"""Provenance of the polynomial coefficients of sincos_halfturn (dbie_internal.h).
+"""Provenance of the constants of the FP64 sin/cos in dbie_internal.h: the polynomial coefficients of
+sincos_halfturn, and (`python sincos_fit.py table`) the table and reduction constants of
+sincos_table16, whose polynomials are the Taylor series with coefficients +-1/n! rounded to double.
 
 Discrete least squares on 500 Chebyshev nodes of z = r^2 in [0, (pi/2)^2], in 50-digit arithmetic:
     sin r = r + r^3 P(z),  weight z   (P of degree 7)
@@ -40,5 +42,21 @@ def main():
     print("pi =", repr(hi), "+", repr(float(mp.pi - hi)), "; 1/pi =", repr(float(1 / mp.pi)))
 
 
-if __name__ == "__main__":
+if __name__ == "__main__" and len(__import__("sys").argv) == 1:
     main()
+
+
+def table16():
+    """The table of sincos_table16 (dbie_internal.h): (sin, cos)(j pi / 16), j = 0..31, each rounded
+    to the nearest double from 50-digit values, and the two-part pi / 16 and 16 / pi of its
+    reduction. Run: python sincos_fit.py table"""
+    mp.mp.dps = 50
+    for j in range(32):
+        a = mp.mpf(j) / 16   # sinpi and cospi are exact at the multiples of 1/2
+        print("    {%s, %s}," % (repr(float(mp.sinpi(a))), repr(float(mp.cospi(a)))))
+    hi = float(mp.pi / 16)
+    print("pi/16 =", repr(hi), "+", repr(float(mp.pi / 16 - hi)), "; 16/pi =", repr(float(16 / mp.pi)))
+
+
+if __name__ == "__main__" and len(__import__("sys").argv) > 1 and __import__("sys").argv[1] == "table":
+    table16()

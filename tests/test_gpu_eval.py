@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import oracle
+from _parity import check_sampled, max_phase
 import paper_1306_1122_amd as D
 from workloads import config1, config2, z_stratified_subsample
 
@@ -33,69 +34,12 @@ def ctx_for(boundaries, xyz, precision, seg=None, **kw):
     return D.dbie_init(bl, T(xyz), seg=seg, precision=precision, **kw)
 
 
-# Pointwise bound of each output against the oracle, |x_gpu - x_ref| <= c u S, where S is the row's
-# sum of absolute terms (oracle.field(..., absolute=True)) and u the path's unit roundoff, with
-# c = c0 + 4 t^2 and t the point's largest phase max_p |lambda_p| r_max in radians: c0 = 512 for FP64
-# (recursive sums of 128-term tiles and of the tile partials, sin/cos and 1/sqrt to a few ulp, the
-# oracle's own rounding), c0 = 1024 for FP32C (block sums of 256 FP32 terms, each term to ~10 u);
-# 4 t^2 covers the rounding of the distance r (relative u, so a phase error t u) times the kernel's
-# sensitivity to the phase (~t), in both the path and the oracle.
-UNIT = {"fp64": 2.0 ** -53, "fp32c": 2.0 ** -24}
-
-
-def max_phase(bd, xyz, lam):
-    ny, nx = bd.B0.shape[1:]
-    u = (xyz[0] - bd.x0) / bd.h
-    v = (xyz[1] - bd.y0) / bd.h
-    dx = np.maximum(np.abs(u), np.abs(nx - 1 - u))
-    dy = np.maximum(np.abs(v), np.abs(ny - 1 - v))
-    rmax = bd.h * np.sqrt(dx * dx + dy * dy + (xyz[2] / bd.h) ** 2)
-    return np.max(np.abs(lam), axis=0) * rmax
-
-
-def check_pointwise(out, ref, absref, precision, tmax, label):
-    c = (512.0 if precision == "fp64" else 1024.0) + 4.0 * tmax ** 2
-    worst = 0.0
-    for k in ref:
-        err = np.abs(np.asarray(out[k], np.float64) - ref[k])
-        scale = UNIT[precision] * absref[k]
-        ratio = err / (scale * c[None, :])
-        bad = ~(ratio <= 1.0)
-        worst = max(worst, float(np.max(err / np.maximum(scale, 1e-300))))
-        assert not np.any(bad), (label, k, int(np.count_nonzero(bad)))
-    return worst
-
-
 def check_against_oracle(ctx, bd, xyz, lam, tol, tangents=True, fg=True, label=""):
     out = D.dbie_eval_field(ctx, T(lam), want_tan=tangents)
     torch.cuda.synchronize()
-    B, dB, tan, aB, adB, atan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, xyz, lam, tangents=True, absolute=True)
-    errs = dict(B=rel(out["B"].cpu(), B), dB=rel(out["dB"].cpu(), dB))
-    if tangents:
-        errs["tan"] = rel(out["tan"].cpu(), tan)
     prec = "fp64" if tol <= 1e-10 else "fp32c"
-    ref, absref = dict(B=B, dB=dB), dict(B=aB, dB=adB)
-    if tangents:
-        ref["tan"], absref["tan"] = tan, atan
-    got = {k: out[k].cpu().numpy() for k in ref}
-    errs["pointwise"] = check_pointwise(got, ref, absref, prec, max_phase(bd, xyz, lam), label)
-    if fg:
-        # f and g gated at the path's bar where they are well conditioned: |J| and |div B| not lost
-        # to cancellation (>= 1e-2 of the gradient's norm) and f >= 1e-2
-        res = oracle.residuals(B, dB, bd.h)
-        fgo = out["fg"].cpu().numpy()
-        J = np.stack([dB[7] - dB[5], dB[2] - dB[6], dB[3] - dB[1]])
-        nJ, nG = np.linalg.norm(J, axis=0), np.linalg.norm(dB, axis=0)
-        D_ = np.abs(dB[0] + dB[4] + dB[8])
-        okf = np.isfinite(res["f"]) & (nJ >= 1e-2 * nG) & (res["f"] >= 1e-2)
-        okg = np.isfinite(res["g"]) & (D_ >= 1e-2 * nG)
-        errs["f"] = rel(fgo[0][okf], res["f"][okf]) if okf.any() else 0.0
-        errs["g"] = rel(fgo[1][okg], res["g"][okg]) if okg.any() else 0.0
-    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k in ("B", "dB", "tan", "f", "g"):
-        if k in errs:
-            assert errs[k] <= tol, (label, k, errs[k])
-    return errs
+    got = {k: out[k].cpu().numpy() for k in (("B", "dB", "tan") if tangents else ("B", "dB"))}
+    return check_sampled(got, bd, xyz, lam, prec, label, fg=out["fg"].cpu().numpy() if fg else None, tol=tol)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
@@ -116,12 +60,9 @@ def test_bipoles_full_size_sampled(precision):
     out = D.dbie_eval_field(ctx, T(w.lam), want_tan=True)
     torch.cuda.synchronize()
     idx = z_stratified_subsample(w.xyz, 512, seed=5)
-    B, dB, tan = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, idx], w.lam[:, idx], tangents=True)
-    e = dict(B=rel(out["B"][:, idx].cpu(), B), dB=rel(out["dB"][:, idx].cpu(), dB),
-             tan=rel(out["tan"][:, idx].cpu(), tan))
-    print("bipoles", precision, e, flush=True)
-    for k, v in e.items():
-        assert v <= TOL[precision], (k, v)
+    got = {k: out[k][:, idx].cpu().numpy() for k in ("B", "dB", "tan")}
+    check_sampled(got, bd, w.xyz[:, idx], w.lam[:, idx], precision, f"bipoles {precision}",
+                  fg=out["fg"][:, idx].cpu().numpy())
     assert torch.isfinite(out["B"]).all() and torch.isfinite(out["dB"]).all()
 
 

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+from _parity import well_conditioned_fg
 from _ties import Recording, has_near_tie
 import paper_1306_1122_amd as D
 
@@ -231,4 +232,8 @@ def test_full_size_elements_sampled(G):
         assert v <= TOLS["fp32c"], (k, v)
     res = oracle.residuals(B, dB, 1.0)
     fg = out["fg"][:, idx].cpu().numpy()
-    assert rel(fg[0], res["f"]) <= 1e-4 and rel(fg[1], res["g"]) <= 1e-4
+    # f and g at the path's bar where they are well conditioned (tests/_parity.py)
+    okf, okg = well_conditioned_fg(B, dB, res)
+    ef, eg = rel(fg[0][okf], res["f"][okf]), rel(fg[1][okg], res["g"][okg])
+    print("quad9 full size", G, "f %.1e g %.1e over %d / %d points" % (ef, eg, okf.sum(), okg.sum()), flush=True)
+    assert ef <= TOLS["fp32c"] and eg <= TOLS["fp32c"]

@@ -91,3 +91,83 @@ def test_within_one_ulp_of_40_digit_values(seed):
         worst = max(worst, es, ec)
         assert es <= 2.3e-16 and ec <= 2.3e-16, (t, es, ec)
     print("largest absolute error %.2e" % worst)
+
+
+# ------------------------------------------------------------------------------------------------
+# sincos_table16: the table-driven form of the FP64 bulk kernel
+# ------------------------------------------------------------------------------------------------
+def _table16():
+    src = open(SRC).read()
+    tab = re.search(r"kSinCos16\[64\] = \{(.*?)\};", src, re.S).group(1)
+    vals = [float(x) for x in re.findall(r"-?[0-9.]+(?:e-?[0-9]+)?", tab)]
+    body = re.search(r"void sincos_table16\(double t, const double2\* __restrict__ tab, double\* s, double\* c\) "
+                     r"\{(.*?)\n\}", src, re.S).group(1)
+    num = r"(-?[0-9.]+(?:e-?[0-9]+)?)"
+    k16 = float(re.search(r"double kb = __builtin_fma\(t, " + num + r", kRoundMagic\)", body).group(1))
+    parts = [float(x) for x in re.findall(r"__builtin_fma\(-k, " + num + r", ", body)]
+    p = re.findall(r"double p = __builtin_fma\(z, " + num + r", " + num + r"\)", body)[0]
+    ps = [float(x) for x in re.findall(r"p = __builtin_fma\(z, p, " + num + r"\)", body)]
+    q = re.findall(r"double q = __builtin_fma\(z, " + num + r", " + num + r"\)", body)[0]
+    qs = [float(x) for x in re.findall(r"q = __builtin_fma\(z, q, " + num + r"\)", body)]
+    assert re.search(r"tab\[\(uint32_t\)__builtin_bit_cast\(uint64_t, kb\) & 31u\]", body)
+    assert re.search(r"\*s = __builtin_fma\(e\.y, sr, e\.x \* cr\);", body)
+    assert re.search(r"\*c = __builtin_fma\(-e\.x, sr, e\.y \* cr\);", body)
+    return vals, k16, parts, [float(p[0]), float(p[1])] + ps, [float(q[0]), float(q[1])] + qs
+
+
+TAB16, K16, PARTS16, PS16, QS16 = _table16()
+
+
+def sincos_table16(t):
+    """(sin t, cos t) from the device steps of sincos_table16."""
+    kb = _fma(t, K16, MAGIC)
+    k = kb - MAGIC
+    j = struct.unpack("<Q", struct.pack("<d", kb))[0] & 31
+    assert k == int(k) and j == int(k) % 32
+    r = _fma(-k, PARTS16[0], t)
+    r = _fma(-k, PARTS16[1], r)
+    z = r * r
+    p = _fma(z, PS16[0], PS16[1])
+    for cf in PS16[2:]:
+        p = _fma(z, p, cf)
+    sr = _fma(r * z, p, r)
+    q = _fma(z, QS16[0], QS16[1])
+    for cf in QS16[2:]:
+        q = _fma(z, q, cf)
+    cr = _fma(z * z, q, _fma(z, -0.5, 1.0))
+    S, C = TAB16[2 * j], TAB16[2 * j + 1]
+    return _fma(C, sr, S * cr), _fma(-S, sr, C * cr)
+
+
+def test_table16_constants():
+    """The table holds (sin, cos)(j pi/16) correctly rounded; the reduction constants split pi/16 to
+    ~1e-33 and 16/pi is rounded to nearest; the polynomial coefficients are +-1/n! rounded."""
+    import math
+    from fractions import Fraction
+    mp.mp.dps = 40
+    assert len(TAB16) == 64
+    for j in range(32):
+        assert TAB16[2 * j] == float(mp.sinpi(mp.mpf(j) / 16)) and TAB16[2 * j + 1] == float(mp.cospi(mp.mpf(j) / 16))
+    assert abs(mp.mpf(PARTS16[0]) + mp.mpf(PARTS16[1]) - mp.pi / 16) < 1e-33
+    assert K16 == float(16 / mp.pi)
+    assert PS16 == [float(Fraction((-1) ** (n // 2), math.factorial(n))) for n in (9, 7, 5, 3)]
+    assert QS16 == [float(Fraction((-1) ** (n // 2), math.factorial(n))) for n in (10, 8, 6, 4)]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_table16_within_one_and_a_half_ulp_of_40_digit_values(seed):
+    mp.mp.dps = 40
+    rng = random.Random(seed)
+    ts = [rng.uniform(-BOUND, BOUND) for _ in range(700)] + [rng.uniform(-8.0, 8.0) for _ in range(500)]
+    # near the reduction points k pi/32 (both sides of a rounding of k) and near zeros of sin, cos
+    ts += [float(mp.pi * (2 * k + 1) / 32) + d for k in range(-600000, 600001, 59999) for d in (0.0, 1e-12, -1e-12)]
+    ts += [float(mp.pi * k / 2) + d for k in range(-300000, 300001, 29989) for d in (0.0, 3e-13, -2e-9)]
+    ts += [0.0, -0.0, 1e-300, -5e-324, 0.09817477042468103, -0.09817477042468103, BOUND * 0.999999,
+           -BOUND * 0.999999]
+    worst = 0.0
+    for t in ts:
+        s, c = sincos_table16(t)
+        es, ec = abs(s - float(mp.sin(t))), abs(c - float(mp.cos(t)))
+        worst = max(worst, es, ec)
+        assert es <= 3.4e-16 and ec <= 3.4e-16, (t, es, ec)
+    print("largest absolute error %.2e" % worst)
