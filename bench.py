@@ -452,9 +452,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="", help="comma-separated names of the extras to run (default: all)")
-    ap.add_argument("--tts-full", action="store_true",
-                    help="instead of the benchmark: time to solution over all 8,388,608 points of the 256x256 "
-                         "workload (plain FP64 Nelder-Mead, 200 trials, against the fast form; ~8 minutes)")
+    ap.add_argument("--tts-full", default="",
+                    help="instead of the benchmark: time to solution over all points of the named workloads "
+                         "(comma-separated: config3 = the 256x256 headline workload, ~8 minutes; config5 = the "
+                         "active region, ~2 minutes): plain FP64 Nelder-Mead, 200 trials, against the fast form")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB once (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--shape", default="", help="FP32C tile shape ppl,waves,tile_pixels")
@@ -482,9 +483,11 @@ def main():
     _lib.load()   # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     if args.tts_full:
-        print("time to solution over all points of the 256x256 workload", flush=True)
-        r = time_to_solution(D, dev, n_sample=None, forms=("fast", "plain"))
-        print(json.dumps({"time_to_solution_full": r}), flush=True)
+        out = {}
+        for name in args.tts_full.split(","):
+            print(f"time to solution over all points of {name}", file=sys.stderr, flush=True)
+            out[name] = time_to_solution(D, dev, n_sample=None, workload=name, forms=("fast", "plain"))
+        print(json.dumps({"time_to_solution_full": out}), flush=True)
         return
     bd = w.boundaries[0]
     N = w.n_points

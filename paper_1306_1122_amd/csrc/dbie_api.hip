@@ -332,10 +332,12 @@ static int eval_core(dbie_ctx* c, const double* lam, int32_t L, bool fp64, bool 
         DBIE_HIP(c, hipEventRecord(e1, s));
         c->ev.emplace_back(e0, e1);
     }
-    if (!fp64)   // points beyond the FP32 phase bound: their sums again in FP64
-        DBIE_HIP(c, launch_field64_override(set ? set->tiles64 : c->tiles64, set ? set->n_tiles64 : c->n_tiles64,
-                                            c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, c->N, L, S, idx, tan,
-                                            tan ? kFp32cPhaseMaxTan : kFp32cPhaseMax, acc, s));
+    // points beyond the FP32 phase bound: their sums again in FP64, in every evaluation whose results
+    // the library returns; a solve's rounds (an active set) only steer its search, which the FP64
+    // acceptance and the final evaluation check, and skip it
+    if (!fp64 && !set)
+        DBIE_HIP(c, launch_field64_override(c->tiles64, c->n_tiles64, c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam,
+                                            c->N, L, S, idx, tan, tan ? kFp32cPhaseMaxTan : kFp32cPhaseMax, acc, s));
     const bool near = !fp64 && c->opt.nearfield_radius_h > 0.0;
     DBIE_HIP(c, launch_finalize(c->bnd_d, c->B0d, c->gpos, c->gB, c->geo, lam, idx, c->N,
                                 set ? set->n_dev : nullptr, c->N,

@@ -15,8 +15,8 @@
 // can exceed the FP32 accuracy bound, max_p |lambda_p| r_max > phase_max with r_max the largest
 // distance from the point to its magnetogram's quadrature grid. Only those points' partial sums are
 // overwritten (every slice); their near-field pairs, which the finalize pass adds in FP64 as for every
-// FP32C point, are subtracted here, so that each pair is counted once. A workgroup without such a
-// point returns at once.
+// FP32C point, are subtracted here, so that each pair is counted once. It runs with one wavefront per
+// workgroup, and a run of 64 points without such a point skips the pair loop.
 #include "dbie_internal.h"
 
 namespace dbie {
@@ -150,12 +150,14 @@ hipError_t launch_field64_override(const Tile* tiles, int64_t n_tiles, const Bou
                                    int32_t L, int32_t S, const int32_t* idx, bool tan, double phase_max, double* acc,
                                    hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
+    // one wavefront per workgroup: the tile's points are taken 64 at a time, and a run of 64 without a
+    // point beyond the bound costs only its test (points beyond it are few and scattered)
     const dim3 grid((unsigned)n_tiles, (unsigned)L, (unsigned)S);
     if (tan)
-        hipLaunchKernelGGL((k_field64<true, true>), grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
+        hipLaunchKernelGGL((k_field64<true, true>), grid, dim3(64), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
                            acc, B0d, phase_max);
     else
-        hipLaunchKernelGGL((k_field64<false, true>), grid, dim3(256), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
+        hipLaunchKernelGGL((k_field64<false, true>), grid, dim3(64), 0, s, tiles, bnd, gpos, gB, geo, lam, N, idx,
                            acc, B0d, phase_max);
     return hipGetLastError();
 }
