@@ -265,16 +265,17 @@ def test_large_lambda_needs_range_reduction_and_nan_lambda_stays_local(precision
         assert rel(sc[k][0].cpu(), r) <= TOL[precision], k
 
 
-def test_fp32c_phase_bound_recomputes_those_points_in_fp64():
+@pytest.mark.parametrize("G", [0, 2])
+def test_fp32c_phase_bound_recomputes_those_points_in_fp64(G):
     """The FP32C accuracy envelope: a point whose largest phase max_p |lambda_p| r_max exceeds 2 pi 128
     radians (with the mu-tangents) or 2 pi 512 (without) has its sums recomputed in FP64 after the
-    FP32 pass, near-field pairs counted once. On the 600 x 40 magnetogram half of the points sit near
-    the cap (phases of ~1500-1750 radians) and half at |lambda| < 0.4 (< 250 radians): with tangents
-    the first half equals the FP64 context's result to FP64 regrouping and the second half keeps its
-    FP32 rounding; without tangents every point keeps the FP32 pass (range-reduced beyond 256
-    revolutions), within the 1e-5 bar of the oracle."""
+    FP32 pass, near-field pairs (elements, with G = 2) counted once. On a 601 x 41 magnetogram half of
+    the points sit near the cap (phases of ~850-1900 radians) and half at |lambda| < 0.4 (< 250
+    radians): with tangents the first half equals the FP64 context's result to FP64 regrouping and the
+    second half keeps its FP32 rounding; without tangents every point keeps the FP32 pass
+    (range-reduced beyond 256 revolutions), within the 1e-5 bar of the oracle."""
     rng = np.random.default_rng(81)
-    nx, ny, n = 600, 40, 260
+    nx, ny, n = 601, 41, 260
     B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
     xyz = np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0.4, 20, n)])
     big = np.arange(n) % 2 == 0
@@ -291,8 +292,8 @@ def test_fp32c_phase_bound_recomputes_those_points_in_fp64():
     tmax = max_phase(bd, xyz, lam)
     hi_tan, hi_field = tmax > 2 * np.pi * 128, tmax > 2 * np.pi * 512
     assert np.array_equal(hi_tan, big) and not hi_field.any()
-    c32 = ctx_for([bd], xyz, "fp32c")
-    c64 = ctx_for([bd], xyz, "fp64")
+    c32 = ctx_for([bd], xyz, "fp32c", quad_points=G)
+    c64 = ctx_for([bd], xyz, "fp64", quad_points=G)
     a = D.dbie_eval_field(c32, T(lam), want_tan=True)
     b = D.dbie_eval_field(c64, T(lam), want_tan=True)
     p = D.dbie_eval_field(c32, T(lam), want_tan=False)
@@ -300,14 +301,23 @@ def test_fp32c_phase_bound_recomputes_those_points_in_fp64():
     for k in ("B", "dB", "tan"):
         x, y = a[k].cpu().numpy(), b[k].cpu().numpy()
         e_hi, e_lo = rel(x[:, big], y[:, big]), rel(x[:, ~big], y[:, ~big])
-        print("phase bound, with tangents", k, "beyond %.2e, below %.2e" % (e_hi, e_lo), flush=True)
+        print(f"phase bound G={G}, with tangents", k, "beyond %.2e, below %.2e" % (e_hi, e_lo), flush=True)
         assert e_hi <= 1e-12 and 1e-10 < e_lo <= 1e-5, k
     for k in ("B", "dB"):
         x, y = p[k].cpu().numpy(), b[k].cpu().numpy()
         e = rel(x, y)
-        print("phase bound, without tangents", k, "%.2e" % e, flush=True)
+        print(f"phase bound G={G}, without tangents", k, "%.2e" % e, flush=True)
         assert 1e-10 < e <= 1e-5, k
-    check_against_oracle(c32, bd, xyz, lam, TOL["fp32c"], label="phase bound fp32c")
+    if G == 0:
+        check_against_oracle(c32, bd, xyz, lam, TOL["fp32c"], label="phase bound fp32c")
+    else:
+        # the element sum of the oracle at a sample (it is slow at this size)
+        idx = np.arange(0, n, 13)
+        Bq, dBq, tq = oracle.field_quad9(B0, 0.0, 0.0, 1.0, xyz[:, idx], lam[:, idx], G=G, tangents=True)
+        for k, r in (("B", Bq), ("dB", dBq), ("tan", tq)):
+            e = rel(a[k][:, idx].cpu(), r)
+            print(f"phase bound G={G} against the oracle", k, "%.2e" % e, flush=True)
+            assert e <= TOL["fp32c"], k
 
 
 @pytest.mark.parametrize("G", [0, 2])
