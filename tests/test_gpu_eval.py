@@ -320,6 +320,33 @@ def test_fp32c_phase_bound_recomputes_those_points_in_fp64(G):
             assert e <= TOL["fp32c"], k
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fp32c_just_below_the_phase_bound_stays_within_the_bar(seed):
+    """The bounds that decide the FP64 recompute, checked where the FP32 pass is kept: points whose
+    largest phase lies at 0.8-1.0 of the bound (2 pi 128 rad with tangents, 2 pi 512 without) on a
+    long magnetogram (701 to 1001 pixels) stay within the FP32C bar of the oracle (relative L2)."""
+    rng = np.random.default_rng(500 + seed)
+    nx, ny, n = int(rng.integers(701, 1002)), int(rng.integers(15, 45)), 96
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    xyz = np.stack([rng.uniform(-5, nx + 5, n), rng.uniform(-3, ny + 3, n), rng.uniform(0.4, 30, n)])
+
+    class Bd:
+        pass
+
+    bd = Bd()
+    bd.B0, bd.x0, bd.y0, bd.h = B0, 0.0, 0.0, 1.0
+    unit = max_phase(bd, xyz, np.ones((3, n)))   # r_max of each point
+    for tan, bound in ((True, 2 * np.pi * 128), (False, 2 * np.pi * 512)):
+        t = bound * rng.uniform(0.8, 1.0, size=n)
+        f = rng.uniform(0.5, 1.0, size=(3, n))
+        f[int(rng.integers(3))] = 1.0
+        lam = (t / unit)[None, :] * f * rng.choice([-1.0, 1.0], size=(3, n))
+        assert np.all(max_phase(bd, xyz, lam) <= bound)
+        ctx = ctx_for([bd], xyz, "fp32c")
+        check_against_oracle(ctx, bd, xyz, lam, TOL["fp32c"], tangents=tan, fg=False,
+                             label=f"below the phase bound, {nx}x{ny}, tangents {tan}")
+
+
 @pytest.mark.parametrize("G", [0, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_magnetograms_without_points(precision, G):
