@@ -126,22 +126,25 @@ def test_autograd_function():
     assert rel(lamt.grad.cpu(), glam_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("shape", [(600, 40, 2.5, 2.7), (1001, 31, 2.9, 3.14)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5)])
-def test_grad_at_large_lambda_matches_oracle(precision, tol):
-    """|lambda| h up to 2.7 over a 600 x 40 magnetogram (beyond the hardware sin/cos range, so the
-    FP32C adjoint reduces the phase first) against the oracle's transpose."""
-    rng = np.random.default_rng(36)
-    nx, ny, n = 600, 40, 160
+def test_grad_at_large_lambda_matches_oracle(precision, tol, shape):
+    """|lambda| h up to 2.7 over a 600 x 40 magnetogram, and up to the cap pi / h over a 1001 x 31 one
+    (phases up to ~3100 radians: beyond the hardware sin/cos range, so the FP32C adjoint reduces the
+    phase first) against the oracle's transpose."""
+    nx, ny, lo, hi = shape
+    rng = np.random.default_rng(36 + nx)
+    n = 160
     B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
     xyz = np.stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0.5, 20, n)])
-    lam = rng.uniform(2.5, 2.7, size=(3, n)) * rng.choice([-1.0, 1.0], size=(3, n))
+    lam = rng.uniform(lo, hi, size=(3, n)) * rng.choice([-1.0, 1.0], size=(3, n))
     gB, gdB = rng.normal(size=(3, n)), rng.normal(size=(9, n))
     ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision=precision)
     r = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB))
     torch.cuda.synchronize()
     gB0_ref, glam_ref, _ = oracle.vjp(B0, 0.0, 0.0, 1.0, xyz, lam, gB, gdB)
     e = rel(r["gB0"].cpu().numpy().reshape(3, ny, nx), gB0_ref)
-    print("large-lambda adjoint", precision, "%.2e" % e, flush=True)
+    print("large-lambda adjoint", precision, nx, ny, "%.2e" % e, flush=True)
     assert e <= tol
 
 
