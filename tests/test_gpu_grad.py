@@ -126,7 +126,7 @@ def test_autograd_function():
     assert rel(lamt.grad.cpu(), glam_ref) <= 1e-10
 
 
-@pytest.mark.parametrize("shape", [(600, 40, 2.5, 2.7), (1001, 31, 2.9, 3.14)])
+@pytest.mark.parametrize("shape", [(600, 40, 2.5, 2.7), (1001, 31, 2.9, 3.14), (2001, 16, 3.0, 3.14), (4001, 8, 3.0, 3.14)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5)])
 def test_grad_at_large_lambda_matches_oracle(precision, tol, shape):
     """|lambda| h up to 2.7 over a 600 x 40 magnetogram, and up to the cap pi / h over a 1001 x 31 one
