@@ -14,12 +14,15 @@
 // are kept in registers; for each row dy = (b0 + r - floor(v)) - frac(v) and q = dy^2 + w^2; then
 //   rho^2 = dx_c^2 + q, rho^-1 = rsq(rho^2), and per component t = Lambda rho, sin/cos in
 //   revolutions (minus the nearest integer, only when a wavefront's |Lambda| rho / 2pi can exceed the
-//   hardware's accurate range of 256 revolutions), N = t sin t + cos t and, in place of
-//   H = t^2 cos t - 3 N, the two-operation form Q = -H / 3 = N - (Lambda^2 / 3) rho^2 cos t;
+//   hardware's accurate range of 256 revolutions). t is never formed: since t / rho = Lambda,
+//   N rho^-3 = (t sin t + cos t) rho^-3 = rho^-2 (Lambda sin t + cos t rho^-1), and in place of
+//   H = t^2 cos t - 3 N the form Q = -H / 3 = N - (Lambda^2 / 3) rho^2 cos t gives
+//   Q rho^-3 = N rho^-3 + (-Lambda^2 / 3) cos t rho^-1;
 //   A0 += N rho^-3 B0,  A1 += Q rho^-3 B0 * dx rho^-2,  A2 likewise with dy,  A3 += Q rho^-3 B0 rho^-2
 //   (the totals of A1..A3 are multiplied by -3 when written), and with tangents
-//   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy; there Q rho^-3 B0 is formed
-//   as N rho^-3 B0 + (-Lambda^2 / 3) (cos t rho^-1 B0), sharing the T0 term.
+//   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy; there the T0 term
+//   cos t rho^-1 B0 is shared by N rho^-3 B0 = rho^-2 (Lambda sin t B0 + cos t rho^-1 B0) and by
+//   Q rho^-3 B0.
 // SCALAR: the three components share one lambda, so t, sin, cos, N and Q are computed once per pair.
 // Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
 // FP64 totals, so the error does not grow with the magnetogram size.
@@ -39,11 +42,10 @@ struct PointState {
     float xn[PPL], xf[PPL], yn[PPL], yf[PPL], w2[PPL];
     float l3[PPL][3];   // -Lambda^2 / 3 (per pixel^2)
     float lr[PPL][3];   // Lambda / 2pi (revolutions per pixel)
+    float lm[PPL][3];   // Lambda (radians per pixel)
     float fa[PPL], fb[PPL];   // near-window centre as floats
     uint32_t msk[PPL];
 };
-
-constexpr float kTwoPiF = 6.28318530717958647692f;
 
 // Phase in revolutions (hi = lr r as rounded), reduced to about [-1/2, 1/2] when FRACT: with
 // k = rint(hi), one FMA forms lr r - k from the exact product with a single rounding (the product's
@@ -58,13 +60,11 @@ __device__ __forceinline__ float phase_rev(float lr, float r, float hi) {
 // One pair given dx, dy (pixels), q = dy^2 + w^2 and the field of the pixel.
 template <bool TAN, bool FRACT>
 __device__ __forceinline__ void pair32(float dx, float dy, float q, const float nl3[3], const float lr[3],
-                                       float bx, float by, float bz, float* acc) {
+                                       const float lm[3], float bx, float by, float bz, float* acc) {
     const float r2 = fmaf(dx, dx, q);
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float ri2 = ri * ri;
-    // with tangents B0 / r is needed anyway, so B0 / r^3 is formed from it (one multiply less)
-    const float ri3 = TAN ? 0.0f : ri2 * ri;
     const float dxr = dx * ri2;
     const float dyr = dy * ri2;
     const float b0[3] = {bx, by, bz};
@@ -75,24 +75,23 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
         const float tr = phase_rev<FRACT>(lr[p], r, hi);
         const float sn = __builtin_amdgcn_sinf(tr);
         const float cs = __builtin_amdgcn_cosf(tr);
-        const float t = hi * kTwoPiF;
-        const float n = fmaf(t, sn, cs);
         float hb;
         if (TAN) {
-            // -H/3 B0 / r^3 = N B0 / r^3 + (-Lambda^2 / 3) cos t B0 / r, since r^2 B0 / r^3 = B0 / r:
-            // cos t B0 / r is the T0 term, so -H/3 costs one FMA
-            const float rb = ri * b0[p];
-            const float nb = n * (rb * ri2);
-            const float crb = cs * rb;
+            // N B0 / r^3 = (Lambda sin t B0 + cos t B0 / r) / r^2 and -H/3 B0 / r^3 = N B0 / r^3 +
+            // (-Lambda^2 / 3) cos t B0 / r: both share the T0 term cos t B0 / r
+            const float crb = cs * (ri * b0[p]);
+            const float nb = fmaf(lm[p] * sn, b0[p], crb) * ri2;
             hb = fmaf(nl3[p], crb, nb);
             acc[4 * p + 0] += nb;
             acc[12 + 3 * p + 0] += crb;
             acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
             acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
         } else {
-            const float b3 = ri3 * b0[p];
-            hb = fmaf(nl3[p] * r2, cs, n) * b3;   // -H / 3 times B0 / r^3
-            acc[4 * p + 0] = fmaf(n, b3, acc[4 * p + 0]);
+            // N / r^3 = (Lambda sin t + cos t / r) / r^2, -H/3 / r^3 = N / r^3 + (-Lambda^2 / 3) cos t / r
+            const float cri = cs * ri;
+            const float nr3 = fmaf(lm[p], sn, cri) * ri2;
+            hb = fmaf(nl3[p], cri, nr3) * b0[p];
+            acc[4 * p + 0] = fmaf(nr3, b0[p], acc[4 * p + 0]);
         }
         acc[4 * p + 1] = fmaf(hb, dxr, acc[4 * p + 1]);
         acc[4 * p + 2] = fmaf(hb, dyr, acc[4 * p + 2]);
@@ -102,24 +101,21 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
 
 // One pair when the three components share one lambda: the sin/cos, N and H are computed once.
 template <bool TAN, bool FRACT>
-__device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float nl3, float lr, float bx, float by,
-                                              float bz, float* acc) {
+__device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float nl3, float lr, float lm, float bx,
+                                              float by, float bz, float* acc) {
     const float r2 = fmaf(dx, dx, q);
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float ri2 = ri * ri;
-    const float ri3 = ri2 * ri;
     const float dxr = dx * ri2;
     const float dyr = dy * ri2;
     const float hi = lr * r;
     const float tr = phase_rev<FRACT>(lr, r, hi);
     const float sn = __builtin_amdgcn_sinf(tr);
     const float cs = __builtin_amdgcn_cosf(tr);
-    const float t = hi * kTwoPiF;
-    const float n = fmaf(t, sn, cs);
-    const float hh = fmaf(nl3 * r2, cs, n);   // -H / 3
-    const float nr3 = n * ri3, hr3 = hh * ri3;
     const float cri = cs * ri;
+    const float nr3 = fmaf(lm, sn, cri) * ri2;   // N / r^3
+    const float hr3 = fmaf(nl3, cri, nr3);       // -H / 3 / r^3
     const float b0[3] = {bx, by, bz};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -190,9 +186,10 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
                     if (in && ((S.msk[j] >> bit) & 1u)) bx = by = bz = 0.0f;
                 }
                 if (SCALAR)
-                    pair32_scalar<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j][0], S.lr[j][0], bx, by, bz, part[j]);
+                    pair32_scalar<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j][0], S.lr[j][0], S.lm[j][0], bx, by, bz,
+                                              part[j]);
                 else
-                    pair32<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j], S.lr[j], bx, by, bz, part[j]);
+                    pair32<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j], S.lr[j], S.lm[j], bx, by, bz, part[j]);
             }
         }
     }
@@ -238,6 +235,7 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
             const double L = lam[(trial * 3 + p) * N + i] * bd.h;
             S.l3[j][p] = (float)(L * L * (-1.0 / 3.0));
             S.lr[j][p] = (float)(L * 0.15915494309189533577);
+            S.lm[j][p] = (float)L;
         }
         const int32_t wa = geo.win_a[i], wb = geo.win_b[i];
         S.fa[j] = (float)wa;

@@ -178,10 +178,9 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
 // FP32 partials per point tile cascaded into FP64. Pairs classified near in dbie_init are skipped
 // here (point tiles holding such points take a masked loop) and added in FP64 by k_vjp_near.
 constexpr int kVjp32Pts = 64;
-constexpr int kVjp32F = 26;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^2, -Lambda^2/3 [3],
+constexpr int kVjp32F = 29;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^2, -Lambda^2/3 [3],
                               // Lambda/2pi [3], alpha[3], -3 beta[3], -3 gx[3], -3 gy[3], window a,
-                              // window b, mask (as bits)
-constexpr float kTwoPiF = 6.28318530717958647692f;
+                              // window b, mask (as bits), Lambda [3]
 
 // GRID (9-node elements): output j sits at (a + af, b + bf) (integer part + fraction) and belongs to
 // element (ea, eb); the near mask is per element of the 3x3 window.
@@ -209,9 +208,7 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, w2));
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * ri;
-        const float ri2 = ri * ri;
-        const float ri3 = ri2 * ri * keep;
-        const float ri5 = ri3 * ri2;
+        const float ri2 = ri * ri * keep;   // a skipped pair zeroes both terms through 1 / r^2
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             // phase in revolutions; FRACT (a chunk beyond the sin/cos range): minus its nearest
@@ -220,12 +217,14 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
             const float tr = FRACT ? fmaf(sp[8 + p][e], r, -__builtin_rintf(th)) : th;
             const float sn = __builtin_amdgcn_sinf(tr);
             const float cs = __builtin_amdgcn_cosf(tr);
-            const float t = th * kTwoPiF;
-            const float n = fmaf(t, sn, cs);
-            // -H / 3 = N - (Lambda^2 / 3) r^2 cos t; the -3 sits in the staged coefficients of lin
-            const float hh = fmaf(sp[5 + p][e] * r2, cs, n);
+            // t = Lambda r is never formed: N / r^3 = (Lambda sin t + cos t / r) / r^2, and
+            // -H / 3 / r^5 = (N / r^3 + (-Lambda^2 / 3) cos t / r) / r^2; the -3 sits in the staged
+            // coefficients of lin
+            const float cri = cs * ri;
+            const float nr3 = fmaf(sp[26 + p][e], sn, cri) * ri2;
+            const float hr5 = fmaf(sp[5 + p][e], cri, nr3) * ri2;
             const float lin = fmaf(sp[17 + p][e], dx, fmaf(sp[20 + p][e], dy, sp[14 + p][e]));
-            acc[j][p] = fmaf(n * ri3, sp[11 + p][e], fmaf(hh * ri5, lin, acc[j][p]));
+            acc[j][p] = fmaf(nr3, sp[11 + p][e], fmaf(hr5, lin, acc[j][p]));
         }
     }
 }
@@ -296,6 +295,7 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
                 const double L = coef[(0 + p) * N + i];
                 sp[5 + p][e] = (float)(L * L * (-1.0 / 3.0));
                 sp[8 + p][e] = (float)(L * 0.15915494309189533577);
+                sp[26 + p][e] = (float)L;
                 sp[11 + p][e] = (float)coef[(3 + p) * N + i];
                 sp[14 + p][e] = (float)(-3.0 * coef[(6 + p) * N + i]);
                 sp[17 + p][e] = (float)(-3.0 * coef[(9 + p) * N + i]);
