@@ -138,10 +138,15 @@ typedef struct {
                              0 means the simplex edge (init_step, or 1 / the longer side); +inf means no
                              trust region (proposals only clipped to [0, cap^2]); negative or NaN is
                              DBIE_E_INVAL. Not used by Nelder-Mead. */
+    double lm_damping;    /* Levenberg-Marquardt initial damping nu0: each step solves
+                             (J^T J + nu diag(J^T J)) d = -J^T u, nu is divided by 10 on acceptance and
+                             multiplied by 10 on rejection. 0 means 1; negative, NaN or infinite is
+                             DBIE_E_INVAL. Not used by Nelder-Mead. */
 } dbie_solve_opts;
 
 /* Fill defaults: FP32C, radius 2, dV/dSigma = 1/6, no tuning, nodal sum / Nelder-Mead, 50 trials, eps 1e-4,
- * default step and cap, FP64 acceptance on, graph replay on, LM trust radius = the simplex edge. Return
+ * default step and cap, FP64 acceptance on, graph replay on, LM trust radius = the simplex edge, LM
+ * initial damping 1. Return
  * DBIE_OK, or DBIE_E_INVAL for NULL. */
 DBIE_API int dbie_default_options(dbie_options* opt);
 DBIE_API int dbie_default_solve_opts(dbie_solve_opts* opt);

@@ -449,13 +449,14 @@ def lm_direction(Jac, u, nu):
     return np.linalg.solve(A + nu * np.diag(dg), -gvec)
 
 
-def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu0: float = 1e-3,
+def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu0: float = 1.0,
                         radius0: float = math.inf):
     """Projected Levenberg-Marquardt on Phi(mu) = |u(mu)|^2, mu in [0, mu_cap]^3, with a trust region
     in lambda = sqrt(mu).
 
     evalfun(mu) -> (u [4], Jac [4, 3] = du/dmu, Phi, rho, status); one call is one trial.
-    Start at mu0; each iteration solves the damped normal equations for a step d, and the proposal
+    Start at mu0 with damping nu0; each iteration solves the damped normal equations
+    (J^T J + nu diag(J^T J)) d = -J^T u (`lm_direction`) for a step d, and the proposal
     mu + d is clipped, per component, into the box where sqrt(mu) lies within the radius Delta of the
     accepted point's sqrt(mu) and inside [0, sqrt(mu_cap)]. The proposal is evaluated and accepted if
     Phi falls (nu /= 10, Delta doubled up to sqrt(mu_cap)) or rejected (nu *= 10, Delta halved).
@@ -497,7 +498,7 @@ def levenberg_marquardt(evalfun, mu0, budget: int, eps: float, mu_cap: float, nu
     return mu, ST_BUDGET, trials, rho, Phi
 
 
-def solve_point_lm(prob, lam0, budget: int, eps: float, lam_cap: float, nu0: float = 1e-3,
+def solve_point_lm(prob, lam0, budget: int, eps: float, lam_cap: float, nu0: float = 1.0,
                    radius0: float = math.inf) -> Tuple[np.ndarray, int, int, float]:
     """Gradient form for one point: LM in mu = lambda^2 >= 0 (`levenberg_marquardt`, box [0, cap^2],
     trust radius radius0 in lambda); one trial = one call of prob.lm_eval(mu), which for a DBIE point

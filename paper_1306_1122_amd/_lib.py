@@ -32,7 +32,7 @@ class dbie_options(ctypes.Structure):
 class dbie_solve_opts(ctypes.Structure):
     _fields_ = [("method", c_int32), ("max_trials", c_int32), ("eps", c_double), ("init_step", c_double),
                 ("lambda_cap", c_double), ("fp64_accept", c_int32), ("use_graph", c_int32),
-                ("lm_radius", c_double)]
+                ("lm_radius", c_double), ("lm_damping", c_double)]
 
 
 class dbie_lambda_grid(ctypes.Structure):

@@ -458,6 +458,7 @@ int dbie_default_solve_opts(dbie_solve_opts* o) {
     o->fp64_accept = 1;
     o->use_graph = 1;
     o->lm_radius = 0.0;
+    o->lm_damping = 0.0;
     return DBIE_OK;
 }
 

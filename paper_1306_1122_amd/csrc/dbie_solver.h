@@ -12,7 +12,7 @@ namespace dbie {
 // What a captured solver graph depends on (compared bytewise before a replay).
 struct GraphKey {
     int32_t method, max_trials, fp64, per32;
-    double eps, step, cap, radius;
+    double eps, step, cap, radius, damping;
     void* block;
     hipStream_t stream;
     const int32_t* perm;

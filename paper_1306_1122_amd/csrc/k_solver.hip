@@ -854,6 +854,8 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     if (!std::isfinite(opt->init_step) || !std::isfinite(opt->lambda_cap))
         return ctx_fail(c, DBIE_E_INVAL, "init_step and lambda_cap must be finite");
     if (!(opt->lm_radius >= 0.0)) return ctx_fail(c, DBIE_E_INVAL, "lm_radius must be >= 0 (or +inf)");
+    if (!(opt->lm_damping >= 0.0) || !std::isfinite(opt->lm_damping))
+        return ctx_fail(c, DBIE_E_INVAL, "lm_damping must be finite and >= 0");
     const int64_t N = ctx_n(c);
     if (int rc = ctx_check_device(c)) return rc;
     if (N > 0 && (!lam || !status || !trials))
@@ -871,8 +873,8 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
     const bool fp64 = ctx_precision(c) == DBIE_FP64;
     const F32Shape sh = get_shape(c, lmm);
     const int32_t per32 = sh.ppl * sh.waves * 64;
-    SolveCfg cfg{opt->method, opt->max_trials, opt->eps, opt->init_step, opt->lambda_cap, ctx_dvds(c), 1e-3,
-                 opt->lm_radius};
+    SolveCfg cfg{opt->method, opt->max_trials, opt->eps, opt->init_step, opt->lambda_cap, ctx_dvds(c),
+                 opt->lm_damping > 0.0 ? opt->lm_damping : 1.0, opt->lm_radius};
     const unsigned gN = (unsigned)((N + 255) / 256);
 #define SOLVE_HIP(call)                                                           \
     do {                                                                          \
@@ -949,6 +951,7 @@ extern "C" int dbie_solve_lambda(dbie_ctx* c, double* lam, const dbie_solve_opts
         key.step = opt->init_step;
         key.cap = opt->lambda_cap;
         key.radius = opt->lm_radius;
+        key.damping = opt->lm_damping;
         key.block = ctx_solver(c).block;
         key.stream = rs;
         key.per32 = per32;

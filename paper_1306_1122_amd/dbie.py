@@ -224,10 +224,11 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
                       eps: float = 1e-4, init_step: float = 0.0, lambda_cap: float = 0.0,
                       fp64_accept: bool = True, B=None, fg=None, status=None, trials=None,
                       want_B: bool = True, want_fg: bool = True, use_graph: bool = True,
-                      lm_radius: float = 0.0, stream=None):
+                      lm_radius: float = 0.0, lm_damping: float = 0.0, stream=None):
     """Per-point lambda search (method "nm": Nelder-Mead, "lm": Levenberg-Marquardt in mu = lambda^2)
     from the start values in lambda_inout [3, N], which receives |lambda*|. lm_radius: LM's trust
-    radius in lambda at the start (0: the simplex edge; math.inf: none). Returns dict(lam, B, fg,
+    radius in lambda at the start (0: the simplex edge; math.inf: none); lm_damping: its initial
+    damping nu0 (0: 1). Returns dict(lam, B, fg,
     status, trials): status per point (_lib.DBIE_ST_*), trials = evaluations used."""
     N = ctx.n_points
     _need(lambda_inout, "lambda_inout", (3, N), device=ctx.device)
@@ -251,6 +252,7 @@ def dbie_solve_lambda(ctx: Context, lambda_inout: torch.Tensor, method: str = "n
     o.fp64_accept = int(bool(fp64_accept))
     o.use_graph = int(bool(use_graph))
     o.lm_radius = float(lm_radius)
+    o.lm_damping = float(lm_damping)
     with _on(ctx.device):
         rc = _lib().dbie_solve_lambda(ctx.handle, _ptr(lambda_inout), ctypes.byref(o), _ptr(B), _ptr(fg),
                                       _ptr(status), _ptr(trials), _stream(stream))

@@ -68,6 +68,7 @@ def test_defaults(lib):
     s = L.dbie_solve_opts()
     assert lib.dbie_default_solve_opts(ctypes.byref(s)) == 0
     assert s.max_trials == 50 and s.eps == 1e-4 and s.method == L.DBIE_NELDER_MEAD
+    assert s.lm_radius == 0.0 and s.lm_damping == 0.0   # the simplex edge, nu0 = 1
     assert lib.dbie_default_options(None) == L.DBIE_E_INVAL
 
 

@@ -35,9 +35,10 @@ def lowlou_ctx(precision):
     return w, bd, D.dbie_init([dict(B0=T(bd.B0), x0=bd.x0, y0=bd.y0, h=bd.h)], T(w.xyz), precision=precision)
 
 
-def oracle_solve(bd, xyz, method, budget, eps, idx, radius0=None):
-    """The oracle's search at the points idx (LM trust radius radius0; None = the library's default,
-    the simplex edge). Returns {i: ((lambda, status, trials, rho), recorded trial values)}."""
+def oracle_solve(bd, xyz, method, budget, eps, idx, radius0=None, nu0=None):
+    """The oracle's search at the points idx (LM trust radius radius0 and initial damping nu0; None =
+    the library's defaults, the simplex edge and 1). Returns {i: ((lambda, status, trials, rho),
+    recorded trial values)}."""
     cap = math.pi / bd.h
     delta = oracle.default_nm_step(bd.nx, bd.ny, bd.h)
     out = {}
@@ -47,7 +48,8 @@ def oracle_solve(bd, xyz, method, budget, eps, idx, radius0=None):
             r = oracle.solve_point_nm(prob, np.zeros(3), budget, eps, delta, cap)
         else:
             r = oracle.solve_point_lm(prob, np.zeros(3), budget, eps, cap,
-                                      radius0=delta if radius0 is None else radius0)
+                                      radius0=delta if radius0 is None else radius0,
+                                      nu0=1.0 if nu0 is None else nu0)
         out[i] = (r, prob.vals)
     return out
 
@@ -67,14 +69,18 @@ def check_trajectories(lg, st, tr, ref, eps, what):
     assert not bad, f"{what}: trajectories differ without a near-tie at points {bad}"
 
 
-@pytest.mark.parametrize("method,budget,radius", [("nm", 50, None), ("lm", 20, None), ("lm", 20, math.inf)])
-def test_fp64_solve_matches_oracle_trajectories(method, budget, radius):
+@pytest.mark.parametrize("method,budget,radius,damping", [("nm", 50, None, None), ("lm", 20, None, None),
+                                                          ("lm", 20, math.inf, None), ("lm", 20, None, 1e-3)])
+def test_fp64_solve_matches_oracle_trajectories(method, budget, radius, damping):
     """FP64 searches on the Low & Lou workload: Nelder-Mead, LM with the default trust region (the
-    simplex edge) and LM without one, every trajectory identical to the oracle's but for near-ties."""
+    simplex edge) and damping (1), LM without a trust region, and LM damped by 1e-3 at the start,
+    every trajectory identical to the oracle's but for near-ties."""
     w, bd, ctx = lowlou_ctx("fp64")
     N = w.n_points
     lam = torch.zeros(3, N, dtype=torch.float64, device="cuda:0")
     kw = {} if radius is None else dict(lm_radius=radius)
+    if damping is not None:
+        kw["lm_damping"] = damping
     r = D.dbie_solve_lambda(ctx, lam, method=method, max_trials=budget, eps=1e-4, **kw)
     torch.cuda.synchronize()
     lg = r["lam"].cpu().numpy()
@@ -82,8 +88,8 @@ def test_fp64_solve_matches_oracle_trajectories(method, budget, radius):
     tr = r["trials"].cpu().numpy()
     assert np.all(tr >= 1) and np.all(tr <= budget)
     idx = list(range(0, N, 4))
-    ref = oracle_solve(bd, w.xyz, method, budget, 1e-4, idx, radius0=radius)
-    check_trajectories(lg, st, tr, ref, 1e-4, f"{method} radius {radius}")
+    ref = oracle_solve(bd, w.xyz, method, budget, 1e-4, idx, radius0=radius, nu0=damping)
+    check_trajectories(lg, st, tr, ref, 1e-4, f"{method} radius {radius} damping {damping}")
     # field and residuals at lambda*: the GPU's outputs equal the oracle's re-evaluation
     Bo, dBo = oracle.field(bd.B0, bd.x0, bd.y0, bd.h, w.xyz, lg)
     res = oracle.residuals(Bo, dBo, bd.h)
@@ -196,6 +202,12 @@ def test_solver_edge_cases():
         assert torch.all(r0["status"] == D._lib.DBIE_ST_DEGENERATE), m
     with pytest.raises(D.DbieError, match="max_trials"):
         D.dbie_solve_lambda(ctx, T(np.zeros((3, 6))), method="nm", max_trials=0)
+    for bad in (-1.0, math.nan):
+        with pytest.raises(D.DbieError, match="lm_radius"):
+            D.dbie_solve_lambda(ctx, T(np.zeros((3, 6))), method="lm", lm_radius=bad)
+    for bad in (-1.0, math.nan, math.inf):
+        with pytest.raises(D.DbieError, match="lm_damping"):
+            D.dbie_solve_lambda(ctx, T(np.zeros((3, 6))), method="lm", lm_damping=bad)
 
 
 @pytest.mark.parametrize("method,prec", [("nm", "fp64"), ("lm", "fp32c")])

@@ -145,16 +145,21 @@ def test_solve_point_lm_trust_radius_is_in_lambda():
     """From lambda = 0 with a full Gauss-Newton step beyond the radius Delta0 in every component, the
     first proposal is sqrt(mu) = Delta0 in each (a radius applied to mu would give sqrt(Delta0));
     after that acceptance the radius doubles, so the second proposal moves sqrt(mu) by at most
-    2 Delta0; with radius0 = inf the first proposal is the damped step itself."""
+    2 Delta0; with radius0 = inf the first proposal is the damped step itself, damped by nu0 (1 by
+    default)."""
     prob = _LinearMuProblem([0.25, 0.9, 0.5])
     oracle.solve_point_lm(prob, np.zeros(3), 3, 0.0, 1.2, radius0=0.1)
     np.testing.assert_allclose(np.sqrt(prob.seen[1]), [0.1, 0.1, 0.1], rtol=1e-15)
     step2 = np.sqrt(prob.seen[2]) - np.sqrt(prob.seen[1])
     assert np.all(step2 <= 0.2 * (1 + 1e-12)) and np.any(step2 >= 0.2 * (1 - 1e-12))
-    free = _LinearMuProblem([0.25, 0.9, 0.5])
-    oracle.solve_point_lm(free, np.zeros(3), 2, 0.0, 1.2)
-    d = oracle.lm_direction(free.A, -free.b, 1e-3)
-    np.testing.assert_allclose(free.seen[1], np.clip(d, 0.0, 1.44), rtol=1e-15)
+    for nu0 in (None, 1e-3):
+        free = _LinearMuProblem([0.25, 0.9, 0.5])
+        kw = {} if nu0 is None else dict(nu0=nu0)
+        oracle.solve_point_lm(free, np.zeros(3), 2, 0.0, 1.2, **kw)
+        d = oracle.lm_direction(free.A, -free.b, 1.0 if nu0 is None else nu0)
+        np.testing.assert_allclose(free.seen[1], np.clip(d, 0.0, 1.44), rtol=1e-15)
+    # the two dampings give different first steps (the pin would not see a swapped default otherwise)
+    assert not np.allclose(oracle.lm_direction(free.A, -free.b, 1.0), oracle.lm_direction(free.A, -free.b, 1e-3))
 
 
 class _ScriptedLM:
@@ -177,15 +182,16 @@ class _ScriptedLM:
 def test_solve_point_lm_infinite_radius_never_shrinks():
     """radius0 = inf is no trust region at all: after an acceptance and a rejection the next proposal
     still reaches the damped step's far target (a radius that became the cap on acceptance and was
-    halved on rejection would stop it at cap / 2); a finite radius0 does stop it."""
+    halved on rejection would stop it at cap / 2); a finite radius0 does stop it. A small initial
+    damping (1e-3) keeps the damped steps close to the Gauss-Newton ones, so the target is reached."""
     cap = 1.2
     target = [0.81 * cap * cap, 0.01, 0.01]
     free = _ScriptedLM(target, cap)
-    oracle.solve_point_lm(free, np.zeros(3), 4, 0.0, cap)
+    oracle.solve_point_lm(free, np.zeros(3), 4, 0.0, cap, nu0=1e-3)
     assert np.array_equal(free.seen[1], np.zeros(3))            # u = 0: no step
     assert math.sqrt(free.seen[3][0]) > 0.85 * cap               # not limited after the rejection
     boxed = _ScriptedLM(target, cap)
-    oracle.solve_point_lm(boxed, np.zeros(3), 4, 0.0, cap, radius0=0.25)
+    oracle.solve_point_lm(boxed, np.zeros(3), 4, 0.0, cap, nu0=1e-3, radius0=0.25)
     # 0.25 doubled on acceptance (0.5), halved on rejection (0.25): the fourth proposal moves 0.25
     np.testing.assert_allclose(math.sqrt(boxed.seen[2][0]), 0.5, rtol=1e-15)
     np.testing.assert_allclose(math.sqrt(boxed.seen[3][0]), 0.25, rtol=1e-15)
