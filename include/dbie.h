@@ -98,7 +98,8 @@ typedef struct {
     double nearfield_radius_h;   /* FP32C only: pairs with r < this * h are summed in FP64; in [0, 2] */
     double dv_over_dsigma_h;     /* dV / dSigma of Eq. 9 in units of h (1/6: cube of side h) */
     int32_t tune;                /* 1: choose the FP32C tile shapes (points per lane, waves per
-                                  * workgroup, grid or persistent form) and, when the point tiles alone
+                                  * workgroup, rows of the LDS pixel block, grid or persistent form)
+                                  * and, when the point tiles alone
                                   * cannot fill the device, the pixel split, by timing the bulk kernel at
                                   * init on the largest tiles at lambda spread over |lambda| < 4 pi / L.
                                   * Choices are reused within the process for contexts of the same
@@ -227,10 +228,11 @@ DBIE_API int dbie_grad(dbie_ctx* ctx, const double* lambda, const double* gB, co
 DBIE_API int dbie_timing(dbie_ctx* ctx, int32_t enable);
 DBIE_API int dbie_timing_read(dbie_ctx* ctx, double* total_ms, int64_t* launches);
 
-/* Choose the FP32C tile shape (points per lane, waves per workgroup, pixels per LDS block, and
- * persistent != 0 for a persistent grid that pulls tiles from a device counter) for both the plain
- * pass and the pass with tangents. Only the shapes the library was built with are accepted
- * (DBIE_E_UNSUPPORTED otherwise; DBIE_E_UNSUPPORTED for an FP64 context). */
+/* Choose the FP32C tile shape (points per lane, waves per workgroup, pixels per LDS block = 8
+ * columns x 16, 32 or 64 rows, and persistent != 0 for a persistent grid that pulls tiles from a
+ * device counter) for both the plain pass and the pass with tangents. Only the shapes the library
+ * was built with are accepted: (1, 2, 256), (1, 4, 256), (1, 8, 256), (2, 4, 256), (1, 4, 128),
+ * (1, 4, 512) (DBIE_E_UNSUPPORTED otherwise; DBIE_E_UNSUPPORTED for an FP64 context). */
 DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int32_t tile_pixels,
                                  int32_t persistent);
 

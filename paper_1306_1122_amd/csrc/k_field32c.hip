@@ -6,8 +6,10 @@
 // partial, and the finalize pass adds the slices in order); static schedules are ordered by
 // decreasing cost. Lane l of the workgroup owns points l, l + NT, ...
 // of the tile, so a wavefront holds 64 consecutive points (the library orders points so that these
-// are spatially coherent). The magnetogram streams through LDS in blocks of kRows x kCols pixels
-// (three planes Bx, By, Bz, tile-major in HBM); every lane reads the same LDS address (broadcast).
+// are spatially coherent). The magnetogram streams through LDS in blocks of RB x kCols pixels (three
+// planes Bx, By, Bz; RB = 16, 32 or 64 rows, a tuning parameter; HBM holds kRows x kCols blocks,
+// tile-major, so a 64-row block stages two consecutive HBM blocks of one column strip and a 16-row
+// block half of one); every lane reads the same LDS address (broadcast).
 //
 // Arithmetic per pair, all FP32. For each block and point the kCols column offsets
 //   dx_c = (a0 + c - floor(u)) - frac(u)           (exact integer difference, one rounding)
@@ -135,12 +137,12 @@ __device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float
     }
 }
 
-// One block of kRows x kCols pixels with origin (a0, b0) and `rows` valid rows, for all PPL points.
+// One block of RB x kCols pixels with origin (a0, b0) and `rows` valid rows, for all PPL points.
 // GRID (9-node elements): the block's columns and rows sit at the positions sC, sR ({integer part,
 // fraction, element index}) instead of at a0 + c, b0 + r, and the near mask is per element.
-template <int PPL, bool TAN, bool SLOW, bool FRACT, bool SCALAR, bool GRID>
+template <int PPL, int RB, bool TAN, bool SLOW, bool FRACT, bool SCALAR, bool GRID>
 __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
-                                           const float4 (*sB)[kRows][kCols / 4], const float4* sC,
+                                           const float4 (*sB)[RB][kCols / 4], const float4* sC,
                                            const float4* sR, float a0, float b0, int rows,
                                            float (&part)[PPL][TAN ? kAcc : kAccField]) {
     static_assert(kCols == 8, "the row body reads two float4 per plane");
@@ -196,15 +198,17 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
 }
 
 // One schedule tile: the sums of its points over every pixel block of their magnetogram.
-template <int PPL, int WAVES, bool TAN, bool SCALAR, bool GRID>
+template <int PPL, int WAVES, int RB, bool TAN, bool SCALAR, bool GRID>
 __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* __restrict__ bnd,
                                               const float* __restrict__ pixf, const float4* __restrict__ gposf,
                                               const Geo& geo, const double* __restrict__ lam, int64_t N,
                                               const int32_t* __restrict__ idx, double* __restrict__ acc,
-                                              float4 (*sB)[kRows][kCols / 4], float4* sC, float4* sR) {
+                                              float4 (*sB)[RB][kCols / 4], float4* sC, float4* sR) {
     constexpr int NT = 64 * WAVES;
     constexpr int NA = TAN ? kAcc : kAccField;
-    constexpr int BQ = kRows * kCols / 4;   // float4 per plane of a block
+    constexpr int BQ = kRows * kCols / 4;   // float4 per plane of an HBM block
+    constexpr int RQ = kCols / 4;           // float4 per row of a plane
+    static_assert(NT >= kCols + RB, "the row positions of a GRID block are staged one per thread");
     if (t.count == 0) return;
     const int64_t trial = blockIdx.y;
     const BoundaryDev bd = bnd[t.b];
@@ -280,23 +284,40 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
         for (int r = 0; r < NA; ++r) tot[j][r] = 0.0;
 
     const float4* P = reinterpret_cast<const float4*>(pixf + bd.pixf_off);
-    // pixel split: slice blockIdx.z of gridDim.z takes an even share of the blocks
-    const int nblk_all = bd.ntx * bd.nty;
+    // LDS blocks of RB rows over the grid's rows (every block holds at least one row); pixel split:
+    // slice blockIdx.z of gridDim.z takes an even share of them
+    const int nrows = GRID ? bd.grows : bd.ny;
+    const int nrb = (nrows + RB - 1) / RB;
+    const int nblk_all = bd.ntx * nrb;
     const int kb0 = (int)((int64_t)blockIdx.z * nblk_all / gridDim.z);
     const int nblk = (int)((int64_t)(blockIdx.z + 1) * nblk_all / gridDim.z);
     for (int k = kb0; k < nblk; ++k) {
         const int ty = k / bd.ntx, tx = k - ty * bd.ntx;
-        const int a0 = tx * kCols, b0 = ty * kRows;
-        const int rows = min(kRows, (GRID ? bd.grows : bd.ny) - b0);
+        const int a0 = tx * kCols, b0 = ty * RB;
+        const int rows = min(RB, nrows - b0);
         __syncthreads();
-        for (int q = tid; q < 3 * BQ; q += NT) {
-            const int pl = q / BQ, o = q - pl * BQ;
-            sB[pl][o / (kCols / 4)][o % (kCols / 4)] = P[(int64_t)k * 3 * BQ + q];
+        if (RB == kRows) {
+            // one HBM block, contiguous
+            for (int q = tid; q < 3 * BQ; q += NT) {
+                const int pl = q / BQ, o = q - pl * BQ;
+                sB[pl][o / RQ][o % RQ] = P[(int64_t)k * 3 * BQ + q];
+            }
+        } else {
+            // the block's rows from the HBM blocks of column strip tx that hold them (rows b0 .. b0 +
+            // rows - 1 < nrows <= nty * kRows: every read lies inside the padded magnetogram)
+            for (int q = tid; q < 3 * RB * RQ; q += NT) {
+                const int pl = q / (RB * RQ), o = q - pl * (RB * RQ);
+                const int r = o / RQ, h = o - r * RQ;
+                if (r < rows) {
+                    const int b = b0 + r, hb = b / kRows;
+                    sB[pl][r][h] = P[((int64_t)(hb * bd.ntx + tx) * 3 + pl) * BQ + (b - hb * kRows) * RQ + h];
+                }
+            }
         }
         if (GRID) {
             const float4* gp = gposf + bd.gposf_off;
             if (tid < kCols) sC[tid] = gp[a0 + tid];
-            else if (tid < kCols + kRows) sR[tid - kCols] = gp[(int64_t)bd.ntx * kCols + b0 + tid - kCols];
+            else if (tid < kCols + rows) sR[tid - kCols] = gp[(int64_t)bd.ntx * kCols + b0 + tid - kCols];
         }
         __syncthreads();
         bool slow = false;
@@ -316,11 +337,11 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
             for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
         const float fa0 = (float)a0, fb0 = (float)b0;
         if (!slow) {
-            if (need_fract) block_loop<PPL, TAN, false, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
-            else block_loop<PPL, TAN, false, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+            if (need_fract) block_loop<PPL, RB, TAN, false, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+            else block_loop<PPL, RB, TAN, false, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
         } else {
-            if (need_fract) block_loop<PPL, TAN, true, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
-            else block_loop<PPL, TAN, true, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+            if (need_fract) block_loop<PPL, RB, TAN, true, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+            else block_loop<PPL, RB, TAN, true, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
         }
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
@@ -342,7 +363,7 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 // Either one workgroup per tile (work == NULL), or persistent: a grid sized to the resident
 // workgroups pulls tile indices from the device counter `work` (cleared by a kernel before the
 // launch) until the schedule is exhausted; every workgroup reaches the exit test after each tile.
-template <int PPL, int WAVES, bool TAN, bool SCALAR, bool GRID>
+template <int PPL, int WAVES, int RB, bool TAN, bool SCALAR, bool GRID>
 __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ? 4 : 1) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
                                                          const BoundaryDev* __restrict__ bnd,
@@ -352,11 +373,11 @@ __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ?
                                                          const int32_t* __restrict__ idx,
                                                          int32_t* __restrict__ work,
                                                          double* __restrict__ acc) {
-    __shared__ float4 sB[3][kRows][kCols / 4];
-    __shared__ float4 sC[GRID ? kCols : 1], sR[GRID ? kRows : 1];
+    __shared__ float4 sB[3][RB][kCols / 4];
+    __shared__ float4 sC[GRID ? kCols : 1], sR[GRID ? RB : 1];
     if (!work) {
-        field32c_tile<PPL, WAVES, TAN, SCALAR, GRID>(tiles[blockIdx.x], bnd, pixf, gposf, geo, lam, N, idx, acc, sB,
-                                                     sC, sR);
+        field32c_tile<PPL, WAVES, RB, TAN, SCALAR, GRID>(tiles[blockIdx.x], bnd, pixf, gposf, geo, lam, N, idx, acc,
+                                                         sB, sC, sR);
         return;
     }
     __shared__ int next;
@@ -366,24 +387,26 @@ __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ?
         const int64_t ti = next;
         __syncthreads();
         if (ti >= n_tiles) break;
-        field32c_tile<PPL, WAVES, TAN, SCALAR, GRID>(tiles[ti], bnd, pixf, gposf, geo, lam, N, idx, acc, sB, sC,
-                                                     sR);
+        field32c_tile<PPL, WAVES, RB, TAN, SCALAR, GRID>(tiles[ti], bnd, pixf, gposf, geo, lam, N, idx, acc, sB,
+                                                         sC, sR);
     }
 }
 
-// The instantiated shapes (points per lane, waves per workgroup); the pixel block is kRows x kCols.
-// (shapes whose tangent variant would spill registers to scratch are left out)
+// The instantiated shapes (points per lane, waves per workgroup, rows of the LDS pixel block of
+// kCols columns); shapes whose tangent variant would spill registers to scratch are left out.
 #define DBIE_F32_SHAPES(X) \
-    X(1, 2)                \
-    X(1, 4)                \
-    X(1, 8)                \
-    X(2, 4)
+    X(1, 2, 32)            \
+    X(1, 4, 32)            \
+    X(1, 8, 32)            \
+    X(2, 4, 32)            \
+    X(1, 4, 16)            \
+    X(1, 4, 64)
 
 int field32c_shapes(F32Shape* out, int max) {
     int n = 0;
     for (int persist = 0; persist < 2; ++persist) {
-#define DBIE_LIST(P, W)                                           \
-        if (n < max) out[n] = F32Shape{P, W, kRows * kCols, persist}; \
+#define DBIE_LIST(P, W, R)                                        \
+        if (n < max) out[n] = F32Shape{P, W, R * kCols, persist}; \
         ++n;
         DBIE_F32_SHAPES(DBIE_LIST)
 #undef DBIE_LIST
@@ -393,8 +416,8 @@ int field32c_shapes(F32Shape* out, int max) {
 
 bool field32c_shape_supported(F32Shape s) {
     if (s.persist != 0 && s.persist != 1) return false;
-#define DBIE_CHK(P, W) \
-    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) return true;
+#define DBIE_CHK(P, W, R) \
+    if (s.ppl == P && s.waves == W && s.tp == R * kCols) return true;
     DBIE_F32_SHAPES(DBIE_CHK)
 #undef DBIE_CHK
     return false;
@@ -404,7 +427,7 @@ __global__ void k_clear_work(int32_t* __restrict__ w) { *w = 0; }
 
 constexpr int kMaxDevices = 64;
 
-template <int P, int W, bool T, bool SC, bool GR>
+template <int P, int W, int R, bool T, bool SC, bool GR>
 static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
                              const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L, int32_t S,
                              const int32_t* idx, int32_t* work, double* acc, hipStream_t st) {
@@ -419,28 +442,28 @@ static hipError_t launch_one(const Tile* tiles, int64_t n_tiles, const BoundaryD
         if (r == 0) {
             int cus = 0, nb = 0;
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field32c<P, W, T, SC, GR>, 64 * W, 0);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field32c<P, W, R, T, SC, GR>, 64 * W, 0);
             r = std::max(nb, 1) * std::max(cus, 1);
             if (dev >= 0 && dev < kMaxDevices) resident[dev].store(r, std::memory_order_relaxed);
         }
         gx = (unsigned)std::min<int64_t>(n_tiles, (int64_t)r);
         hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(1), 0, st, work);
     }
-    hipLaunchKernelGGL((k_field32c<P, W, T, SC, GR>), dim3(gx, (unsigned)L, (unsigned)S), dim3(64 * W), 0, st,
+    hipLaunchKernelGGL((k_field32c<P, W, R, T, SC, GR>), dim3(gx, (unsigned)L, (unsigned)S), dim3(64 * W), 0, st,
                        tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, idx, work, acc);
     return hipGetLastError();
 }
 
-template <int P, int W, bool GR>
+template <int P, int W, int R, bool GR>
 static hipError_t launch_variant(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd, const float* pixf,
                                  const float4* gposf, Geo geo, const double* lam, int64_t N, int32_t L, int32_t S,
                                  const int32_t* idx, int32_t* w, bool tan, bool scalar, double* acc, hipStream_t st) {
     if (tan) {
-        if (scalar) return launch_one<P, W, true, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
-        return launch_one<P, W, true, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
+        if (scalar) return launch_one<P, W, R, true, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
+        return launch_one<P, W, R, true, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
     }
-    if (scalar) return launch_one<P, W, false, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
-    return launch_one<P, W, false, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
+    if (scalar) return launch_one<P, W, R, false, true, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
+    return launch_one<P, W, R, false, false, GR>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, acc, st);
 }
 
 hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev* bnd,
@@ -451,10 +474,10 @@ hipError_t launch_field32c(const Tile* tiles, int64_t n_tiles, const BoundaryDev
     if (S < 1) return hipErrorInvalidValue;
     // a persistent launch with L trials or S slices would share one counter between the grid rows
     int32_t* w = (s.persist && L == 1 && S == 1) ? work : nullptr;
-#define DBIE_LAUNCH(P, W)                                                                                  \
-    if (s.ppl == P && s.waves == W && s.tp == kRows * kCols) {                                             \
-        if (gposf) return launch_variant<P, W, true>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, tan, scalar, acc, st); \
-        return launch_variant<P, W, false>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, tan, scalar, acc, st);         \
+#define DBIE_LAUNCH(P, W, R)                                                                               \
+    if (s.ppl == P && s.waves == W && s.tp == R * kCols) {                                                 \
+        if (gposf) return launch_variant<P, W, R, true>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, tan, scalar, acc, st); \
+        return launch_variant<P, W, R, false>(tiles, n_tiles, bnd, pixf, gposf, geo, lam, N, L, S, idx, w, tan, scalar, acc, st);         \
     }
     DBIE_F32_SHAPES(DBIE_LAUNCH)
 #undef DBIE_LAUNCH

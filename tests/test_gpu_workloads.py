@@ -115,9 +115,11 @@ def test_tuner_picks_an_instantiated_shape_and_results_do_not_change():
         assert D.dbie_query_split(ctx2) == D.dbie_query_split(ctx)
     r1 = D.dbie_eval_field(ctx, lam, want_tan=True)
     torch.cuda.synchronize()
-    # a different tile shape changes only the order of the FP32 partial sums
+    # a different tile shape changes only the FP32 rounding: the lane that sums a point and, with
+    # another LDS block height, which pixels share an FP32 block partial; each run is within ~1e-6 of
+    # the FP64 sums here, so the two agree to a few 1e-6
     for k in ("B", "dB", "tan"):
-        assert rel(r1[k].cpu(), r0[k].cpu()) <= 1e-6, k
+        assert rel(r1[k].cpu(), r0[k].cpu()) <= 5e-6, k
     # an explicit shape is honoured, an unknown one is rejected
     D.dbie_set_tile_shape(ctx, 1, 8, 256)
     assert D.dbie_query(ctx)["ppl"] == 1 and D.dbie_query(ctx)["waves"] == 8
@@ -128,7 +130,8 @@ def test_tuner_picks_an_instantiated_shape_and_results_do_not_change():
 def test_tuner_reuses_its_choice_within_a_size_bucket():
     """A context whose key (architecture, quadrature, pass, floor(log2) of the point count and of the
     pixels per magnetogram) matches an earlier one reuses that choice without timing; its results
-    agree with an untuned context's (the shape changes only which lane sums a point)."""
+    agree with an untuned context's set to the same tile shape (grid or persistent form, split: FP64
+    regrouping at most)."""
     w4, w6 = config2(nz=4), config2(nz=6)     # 65,536 and 98,304 points: both 2^16 <= N < 2^17
     B0 = T(w4.boundaries[0].B0)
     a = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], T(w4.xyz), precision="fp32c", tune=True)
@@ -141,6 +144,8 @@ def test_tuner_reuses_its_choice_within_a_size_bucket():
     assert D.dbie_query_split(b) == D.dbie_query_split(a)
     ref = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], T(w6.xyz), precision="fp32c")
     assert D.dbie_query_tuned(ref) == 0
+    qt = D.dbie_query_tan(b)
+    D.dbie_set_tile_shape(ref, qt["ppl"], qt["waves"], qt["tile_pixels"])
     lam = T(w6.lam)
     r0 = D.dbie_eval_field(ref, lam, want_tan=True)
     r1 = D.dbie_eval_field(b, lam, want_tan=True)
@@ -151,7 +156,8 @@ def test_tuner_reuses_its_choice_within_a_size_bucket():
 
 def test_tuner_with_few_points_picks_a_split():
     """With few points (a 2,000-point evaluation over the 256x256 magnetogram: 8 point tiles) the tuner
-    also times the pixel split; the result agrees with an untuned context's to FP64 regrouping."""
+    also times the pixel split; the result agrees to FP64 regrouping with an untuned one-slice
+    context's set to the same tile shape."""
     w = config3(nz=1)
     bd = w.boundaries[0]
     idx = np.random.default_rng(3).choice(w.n_points, 2000, replace=False)
@@ -159,6 +165,8 @@ def test_tuner_with_few_points_picks_a_split():
     B0 = T(bd.B0)
     ctx = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", tune=True)
     ref = D.dbie_init([dict(B0=B0, x0=0.0, y0=0.0, h=1.0)], xyz, precision="fp32c", pixel_split=1)
+    qt = D.dbie_query_tan(ctx)
+    D.dbie_set_tile_shape(ref, qt["ppl"], qt["waves"], qt["tile_pixels"])
     S = D.dbie_query_split(ctx)
     print("tuned split for 2000 points:", S, "shape", D.dbie_query(ctx), flush=True)
     assert 1 <= S <= 32 and D.dbie_query_tuned(ctx) in (1, 2)
@@ -221,6 +229,46 @@ def test_pixel_slices_match_one_slice_and_the_oracle(G, precision):
         B, dB, tan = oracle.field_quad9(B0, 0.0, 0.0, 1.0, xyz, lam, G=G, tangents=True)
     for k, ref in (("B", B), ("dB", dB), ("tan", tan)):
         assert rel(outs[0][k].cpu(), ref) <= (1e-5 if precision == "fp32c" else 1e-10), k
+
+
+@pytest.mark.parametrize("G", [0, 2])
+@pytest.mark.parametrize("tile_pixels", [128, 256, 512])
+def test_every_pixel_block_height_matches_the_oracle(tile_pixels, G):
+    """LDS pixel blocks of 16, 32 and 64 rows x 8 columns (the 64-row block stages two HBM blocks, the
+    16-row block half of one) on a 77 x 45 magnetogram, whose 45 rows (44 grid rows with elements)
+    leave a ragged last block for every height; points below 2 pixels (masked near field) and beyond
+    the magnetogram; one and three pixel slices and the persistent form. Every run equals the oracle
+    (nodal rule: relative L2 and the pointwise bound at every point; elements: relative L2) and the
+    32-row blocks up to the FP32 rounding of the regrouped block sums."""
+    from workloads import Boundary
+    rng = np.random.default_rng(53)
+    nx, ny = 77, 45
+    B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+    n = 1500
+    xyz = np.stack([rng.uniform(-2, nx + 1, n), rng.uniform(-2, ny + 1, n), rng.uniform(0.4, 30, n)])
+    lam = rng.uniform(-0.5, 0.5, size=(3, n))
+    if G == 0:
+        B, dB, tan = oracle.field(B0, 0.0, 0.0, 1.0, xyz, lam, tangents=True)
+    else:
+        B, dB, tan = oracle.field_quad9(B0, 0.0, 0.0, 1.0, xyz, lam, G=G, tangents=True)
+    base = None
+    for S, persistent in ((1, False), (3, False), (1, True)):
+        ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision="fp32c", pixel_split=S,
+                          quad_points=G)
+        if base is None:
+            base = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+        D.dbie_set_tile_shape(ctx, 1, 4, tile_pixels, persistent)
+        assert D.dbie_query(ctx)["tile_pixels"] == tile_pixels and D.dbie_query_tan(ctx)["tile_pixels"] == tile_pixels
+        out = D.dbie_eval_field(ctx, T(lam), want_tan=True)
+        torch.cuda.synchronize()
+        label = f"{tile_pixels // 8} rows, G {G}, {S} slices, persistent {persistent}"
+        for k, ref in (("B", B), ("dB", dB), ("tan", tan)):
+            assert rel(out[k].cpu(), ref) <= 1e-5, (label, k)
+            assert rel(out[k].cpu(), base[k].cpu()) <= 5e-6, (label, k)
+        if G == 0:
+            got = {k: out[k].cpu().numpy() for k in ("B", "dB", "tan")}
+            check_sampled(got, Boundary(B0), xyz, lam, "fp32c", label, fg=out["fg"].cpu().numpy())
+        ctx.close()
 
 
 def test_captured_solve_survives_a_reallocated_accumulator():
