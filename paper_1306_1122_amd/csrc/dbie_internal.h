@@ -129,9 +129,10 @@ __device__ __forceinline__ double flip_sign(double x, uint64_t sign) {
 // sin and cos of t for |t| < kSincosBound from a table of (sin, cos)(j pi/16), j = 0..31: t =
 // k pi/16 + r with k = rint(16 t / pi) from one FMA that adds 1.5 2^52 (as in sincos_halfturn: the
 // low word of the sum holds k, so k mod 32 is its low five bits), r from a two-constant Cody-Waite
-// reduction with FMA (|r| <= pi/32 up to rounding), sin r and cos r from their Taylor series to r^9
-// and r^10 (coefficients +-1/n! rounded to double; the first terms left out are below 4e-19 and
-// 3e-21 on |r| <= 0.1), and the addition theorems sin t = S cos r + C sin r, cos t = C cos r - S sin r
+// reduction with FMA (|r| <= pi/32 up to rounding), sin r = r + r^3 P(r^2) with P of degree 2 fitted
+// on [0, pi/32] (largest absolute error 1.4e-17), cos r from its Taylor series to r^8 (coefficients
+// +-1/n! rounded to double; the first term left out is below 2.3e-17 there), and the addition
+// theorems sin t = S cos r + C sin r, cos t = C cos r - S sin r
 // with (S, C) = tab[k mod 32]. About one ulp of 1 absolute. `tab` is kSinCos16 copied to LDS by the
 // calling kernel; the constants come from csrc/sincos_fit.py (`table`).
 static __constant__ double kSinCos16[64] = {
@@ -158,12 +159,10 @@ __device__ __forceinline__ void sincos_table16(double t, const double2* __restri
     double r = __builtin_fma(-k, 0.19634954084936207, t);
     r = __builtin_fma(-k, 7.654042494670958e-18, r);
     const double z = r * r;
-    double p = __builtin_fma(z, 2.7557319223985893e-06, -0.0001984126984126984);
-    p = __builtin_fma(z, p, 0.008333333333333333);
-    p = __builtin_fma(z, p, -0.16666666666666666);
+    double p = __builtin_fma(z, -0.00019835792424992082, 0.00833333299396471);
+    p = __builtin_fma(z, p, -0.16666666666603067);
     const double sr = __builtin_fma(r * z, p, r);
-    double q = __builtin_fma(z, -2.755731922398589e-07, 2.48015873015873e-05);
-    q = __builtin_fma(z, q, -0.001388888888888889);
+    double q = __builtin_fma(z, 2.48015873015873e-05, -0.001388888888888889);
     q = __builtin_fma(z, q, 0.041666666666666664);
     const double cr = __builtin_fma(z * z, q, __builtin_fma(z, -0.5, 1.0));
     const double2 e = tab[(uint32_t)__builtin_bit_cast(uint64_t, kb) & 31u];
