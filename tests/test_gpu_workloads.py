@@ -237,9 +237,10 @@ def test_every_pixel_block_height_matches_the_oracle(tile_pixels, G):
     """LDS pixel blocks of 16, 32 and 64 rows x 8 columns (the 64-row block stages two HBM blocks, the
     16-row block half of one) on a 77 x 45 magnetogram, whose 45 rows (44 grid rows with elements)
     leave a ragged last block for every height; points below 2 pixels (masked near field) and beyond
-    the magnetogram; one and three pixel slices and the persistent form. Every run equals the oracle
-    (nodal rule: relative L2 and the pointwise bound at every point; elements: relative L2) and the
-    32-row blocks up to the FP32 rounding of the regrouped block sums."""
+    the magnetogram; one and three pixel slices and the persistent form; the passes with and without
+    tangents and the single-lambda pass. Every run equals the oracle (nodal rule: relative L2 and the
+    pointwise bound at every point; elements: relative L2) and the 32-row blocks up to the FP32
+    rounding of the regrouped block sums."""
     from workloads import Boundary
     rng = np.random.default_rng(53)
     nx, ny = 77, 45
@@ -247,10 +248,11 @@ def test_every_pixel_block_height_matches_the_oracle(tile_pixels, G):
     n = 1500
     xyz = np.stack([rng.uniform(-2, nx + 1, n), rng.uniform(-2, ny + 1, n), rng.uniform(0.4, 30, n)])
     lam = rng.uniform(-0.5, 0.5, size=(3, n))
-    if G == 0:
-        B, dB, tan = oracle.field(B0, 0.0, 0.0, 1.0, xyz, lam, tangents=True)
-    else:
-        B, dB, tan = oracle.field_quad9(B0, 0.0, 0.0, 1.0, xyz, lam, G=G, tangents=True)
+    lam1 = lam[0]
+    field = (lambda l: oracle.field(B0, 0.0, 0.0, 1.0, xyz, l, tangents=True)) if G == 0 else \
+        (lambda l: oracle.field_quad9(B0, 0.0, 0.0, 1.0, xyz, l, G=G, tangents=True))
+    B, dB, tan = field(lam)
+    B1, dB1, _ = field(np.stack([lam1] * 3))
     base = None
     for S, persistent in ((1, False), (3, False), (1, True)):
         ctx = D.dbie_init([dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0)], T(xyz), precision="fp32c", pixel_split=S,
@@ -268,6 +270,13 @@ def test_every_pixel_block_height_matches_the_oracle(tile_pixels, G):
         if G == 0:
             got = {k: out[k].cpu().numpy() for k in ("B", "dB", "tan")}
             check_sampled(got, Boundary(B0), xyz, lam, "fp32c", label, fg=out["fg"].cpu().numpy())
+        plain = D.dbie_eval_field(ctx, T(lam))                 # the pass without tangents
+        one = D.dbie_eval_field_scalar(ctx, T(lam1))           # one lambda for the three components
+        torch.cuda.synchronize()
+        for k, ref in (("B", B), ("dB", dB)):
+            assert rel(plain[k].cpu(), ref) <= 1e-5, (label, "plain", k)
+        for k, ref in (("B", B1), ("dB", dB1)):
+            assert rel(one[k].cpu(), ref) <= 1e-5, (label, "single lambda", k)
         ctx.close()
 
 
