@@ -25,6 +25,9 @@
 //   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy; there the T0 term
 //   cos t rho^-1 B0 is shared by N rho^-3 B0 = rho^-2 (Lambda sin t B0 + cos t rho^-1 B0) and by
 //   Q rho^-3 B0.
+// Rows: dy is the same for the kCols pairs of a block row, so the row's A3 terms (and, with tangents,
+// its A0 terms) are summed apart, and A2 += dy (row sum of A3 terms), T2 += dy (row sum of A0 terms)
+// once per row: no per-pair products with dy.
 // SCALAR: the three components share one lambda, so t, sin, cos, N and Q are computed once per pair.
 // Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
 // FP64 totals, so the error does not grow with the magnetogram size.
@@ -59,16 +62,23 @@ __device__ __forceinline__ float phase_rev(float lr, float r, float hi) {
     return fmaf(lr, r, -__builtin_rintf(hi));
 }
 
-// One pair given dx, dy (pixels), q = dy^2 + w^2 and the field of the pixel.
-template <bool TAN, bool FRACT>
-__device__ __forceinline__ void pair32(float dx, float dy, float q, const float nl3[3], const float lr[3],
-                                       const float lm[3], float bx, float by, float bz, float* acc) {
+// Sum of the row's terms: the first pair of a row sets it, the others add to it.
+template <bool FIRST>
+__device__ __forceinline__ void row_add(float& s, float x) {
+    if (FIRST) s = x;
+    else s += x;
+}
+
+// One pair given dx (pixels), q = dy^2 + w^2 and the field of the pixel. rs: the row sums of the A3
+// terms [3] and, with tangents, of the A0 terms [3] (FIRST: the row's first pair).
+template <bool TAN, bool FRACT, bool FIRST>
+__device__ __forceinline__ void pair32(float dx, float q, const float nl3[3], const float lr[3],
+                                       const float lm[3], float bx, float by, float bz, float* acc, float* rs) {
     const float r2 = fmaf(dx, dx, q);
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float ri2 = ri * ri;
     const float dxr = dx * ri2;
-    const float dyr = dy * ri2;
     const float b0[3] = {bx, by, bz};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -84,10 +94,9 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
             const float crb = cs * (ri * b0[p]);
             const float nb = fmaf(lm[p] * sn, b0[p], crb) * ri2;
             hb = fmaf(nl3[p], crb, nb);
-            acc[4 * p + 0] += nb;
+            row_add<FIRST>(rs[3 + p], nb);
             acc[12 + 3 * p + 0] += crb;
             acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
-            acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
         } else {
             // N / r^3 = (Lambda sin t + cos t / r) / r^2, -H/3 / r^3 = N / r^3 + (-Lambda^2 / 3) cos t / r
             const float cri = cs * ri;
@@ -96,21 +105,20 @@ __device__ __forceinline__ void pair32(float dx, float dy, float q, const float 
             acc[4 * p + 0] = fmaf(nr3, b0[p], acc[4 * p + 0]);
         }
         acc[4 * p + 1] = fmaf(hb, dxr, acc[4 * p + 1]);
-        acc[4 * p + 2] = fmaf(hb, dyr, acc[4 * p + 2]);
-        acc[4 * p + 3] = fmaf(hb, ri2, acc[4 * p + 3]);
+        if (FIRST) rs[p] = hb * ri2;
+        else rs[p] = fmaf(hb, ri2, rs[p]);
     }
 }
 
 // One pair when the three components share one lambda: the sin/cos, N and H are computed once.
-template <bool TAN, bool FRACT>
-__device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float nl3, float lr, float lm, float bx,
-                                              float by, float bz, float* acc) {
+template <bool TAN, bool FRACT, bool FIRST>
+__device__ __forceinline__ void pair32_scalar(float dx, float q, float nl3, float lr, float lm, float bx,
+                                              float by, float bz, float* acc, float* rs) {
     const float r2 = fmaf(dx, dx, q);
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float ri2 = ri * ri;
     const float dxr = dx * ri2;
-    const float dyr = dy * ri2;
     const float hi = lr * r;
     const float tr = phase_rev<FRACT>(lr, r, hi);
     const float sn = __builtin_amdgcn_sinf(tr);
@@ -124,16 +132,15 @@ __device__ __forceinline__ void pair32_scalar(float dx, float dy, float q, float
         const float hb = hr3 * b0[p];
         if (TAN) {
             const float nb = nr3 * b0[p];
-            acc[4 * p + 0] += nb;
+            row_add<FIRST>(rs[3 + p], nb);
             acc[12 + 3 * p + 0] = fmaf(cri, b0[p], acc[12 + 3 * p + 0]);
             acc[12 + 3 * p + 1] = fmaf(nb, dx, acc[12 + 3 * p + 1]);
-            acc[12 + 3 * p + 2] = fmaf(nb, dy, acc[12 + 3 * p + 2]);
         } else {
             acc[4 * p + 0] = fmaf(nr3, b0[p], acc[4 * p + 0]);
         }
         acc[4 * p + 1] = fmaf(hb, dxr, acc[4 * p + 1]);
-        acc[4 * p + 2] = fmaf(hb, dyr, acc[4 * p + 2]);
-        acc[4 * p + 3] = fmaf(hb, ri2, acc[4 * p + 3]);
+        if (FIRST) rs[p] = hb * ri2;
+        else rs[p] = fmaf(hb, ri2, rs[p]);
     }
 }
 
@@ -171,6 +178,7 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
         for (int j = 0; j < PPL; ++j) {
             const float dy = GRID ? (rp.x + S.yn[j]) + (rp.y - S.yf[j]) : (brow + S.yn[j]) - S.yf[j];
             const float q = fmaf(dy, dy, S.w2[j]);
+            float rs[TAN ? 6 : 3];   // the row sums of the A3 terms and, with tangents, of the A0 terms
 #pragma unroll
             for (int c = 0; c < kCols; ++c) {
                 float bx = bxs[c], by = bys[c], bz = bzs[c];
@@ -187,11 +195,29 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
                         in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
                     if (in && ((S.msk[j] >> bit) & 1u)) bx = by = bz = 0.0f;
                 }
-                if (SCALAR)
-                    pair32_scalar<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j][0], S.lr[j][0], S.lm[j][0], bx, by, bz,
-                                              part[j]);
-                else
-                    pair32<TAN, FRACT>(dxc[j][c], dy, q, S.l3[j], S.lr[j], S.lm[j], bx, by, bz, part[j]);
+                if (SCALAR) {
+                    if (c == 0)
+                        pair32_scalar<TAN, FRACT, true>(dxc[j][c], q, S.l3[j][0], S.lr[j][0], S.lm[j][0], bx, by,
+                                                        bz, part[j], rs);
+                    else
+                        pair32_scalar<TAN, FRACT, false>(dxc[j][c], q, S.l3[j][0], S.lr[j][0], S.lm[j][0], bx, by,
+                                                         bz, part[j], rs);
+                } else {
+                    if (c == 0)
+                        pair32<TAN, FRACT, true>(dxc[j][c], q, S.l3[j], S.lr[j], S.lm[j], bx, by, bz, part[j], rs);
+                    else
+                        pair32<TAN, FRACT, false>(dxc[j][c], q, S.l3[j], S.lr[j], S.lm[j], bx, by, bz, part[j], rs);
+                }
+            }
+            // the row's y-moments: A2 += dy (sum of A3 terms), T2 += dy (sum of A0 terms)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                part[j][4 * p + 3] += rs[p];
+                part[j][4 * p + 2] = fmaf(dy, rs[p], part[j][4 * p + 2]);
+                if (TAN) {
+                    part[j][4 * p + 0] += rs[3 + p];
+                    part[j][12 + 3 * p + 2] = fmaf(dy, rs[3 + p], part[j][12 + 3 * p + 2]);
+                }
             }
         }
     }
