@@ -170,18 +170,13 @@ __device__ __forceinline__ void sincos_table16(double t, const double2* __restri
     *c = __builtin_fma(-e.x, sr, e.y * cr);
 }
 
-// One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
-// dx = a_k - u, dy = b_k - v, w2 = w^2, all in pixels. Shared by the FP64 bulk kernel and the
-// FP64 near-field pass of the FP32C path. WIDE: the device library's sincos (any argument);
-// otherwise every |lambda r| must stay below kSincosBound, and TAB takes sincos_table16 (its table
-// in the caller's LDS) instead of sincos_halfturn. With t^2 = lambda^2 r^2, the gradient term
-// H B0 / r^5 (H = t^2 cos t - 3 N) is formed as (B0 / r^3)((-3 / r^2) N + lambda^2 cos t), sharing
-// B0 / r^3 with the field row: two multiplies and one FMA per component, -3 / r^2 once per pair.
-template <bool TAN, bool WIDE, bool TAB = false>
-__device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const double lam[3],
-                                          double b0x, double b0y, double b0z, double* acc,
-                                          const double2* __restrict__ tab = nullptr) {
-    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
+// The FP64 pair: shared arithmetic of pair_fp64 (every row accumulated per pair) and pair_fp64_row
+// (the y-moment rows through per-row sums).
+template <bool TAN, bool WIDE, bool TAB, bool ROW>
+__device__ __forceinline__ void pair_fp64_core(double dx, double dy, double w2q, const double lam[3],
+                                               double b0x, double b0y, double b0z, double* acc, double* rs,
+                                               const double2* __restrict__ tab) {
+    const double r2 = ROW ? __builtin_fma(dx, dx, w2q) : __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2q));
     const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
     const double r = r2 * ri;
     const double ri2 = ri * ri;
@@ -199,16 +194,48 @@ __device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const
         const double b3 = ri3 * bp;
         const double nb = n * b3;
         const double hb = b3 * __builtin_fma(ri2n3, n, lam[p] * lam[p] * c);   // H B0 / r^5
-        acc[4 * p + 0] += nb;
         acc[4 * p + 1] = __builtin_fma(hb, dx, acc[4 * p + 1]);
-        acc[4 * p + 2] = __builtin_fma(hb, dy, acc[4 * p + 2]);
-        acc[4 * p + 3] += hb;
+        if (ROW) {
+            // the row's y-moments come from these row sums, times dy, once per row
+            rs[p] += hb;
+            if (TAN) rs[3 + p] += nb;
+        } else {
+            acc[4 * p + 0] += nb;
+            acc[4 * p + 2] = __builtin_fma(hb, dy, acc[4 * p + 2]);
+            acc[4 * p + 3] += hb;
+        }
         if (TAN) {
             acc[12 + 3 * p + 0] = __builtin_fma(c * ri, bp, acc[12 + 3 * p + 0]);
             acc[12 + 3 * p + 1] = __builtin_fma(nb, dx, acc[12 + 3 * p + 1]);
-            acc[12 + 3 * p + 2] = __builtin_fma(nb, dy, acc[12 + 3 * p + 2]);
+            if (!ROW) acc[12 + 3 * p + 2] = __builtin_fma(nb, dy, acc[12 + 3 * p + 2]);
         }
+        if (ROW && !TAN) acc[4 * p + 0] += nb;
     }
+}
+
+// One pair (point, pixel) in FP64, added to the 12 (+9) accumulators of the three components.
+// dx = a_k - u, dy = b_k - v, w2 = w^2, all in pixels. Used by the FP64 near-field pass of the
+// FP32C path (and the near pairs the FP64 recompute takes out again). WIDE: the device library's
+// sincos (any argument); otherwise every |lambda r| must stay below kSincosBound, and TAB takes
+// sincos_table16 (its table in the caller's LDS) instead of sincos_halfturn. With t^2 = lambda^2 r^2,
+// the gradient term H B0 / r^5 (H = t^2 cos t - 3 N) is formed as (B0 / r^3)((-3 / r^2) N +
+// lambda^2 cos t), sharing B0 / r^3 with the field row: two multiplies and one FMA per component,
+// -3 / r^2 once per pair.
+template <bool TAN, bool WIDE, bool TAB = false>
+__device__ __forceinline__ void pair_fp64(double dx, double dy, double w2, const double lam[3],
+                                          double b0x, double b0y, double b0z, double* acc,
+                                          const double2* __restrict__ tab = nullptr) {
+    pair_fp64_core<TAN, WIDE, TAB, false>(dx, dy, w2, lam, b0x, b0y, b0z, acc, nullptr, tab);
+}
+
+// The same pair within a row of the grid: q = dy^2 + w^2 of the row; the A3 terms H B0 / r^5 and,
+// with tangents, the A0 terms N B0 / r^3 go to the row sums rs[3] (+3), from which the caller adds
+// A0, A3, A2 += dy (sum of A3 terms) and T2 += dy (sum of A0 terms) once per row.
+template <bool TAN, bool WIDE, bool TAB = false>
+__device__ __forceinline__ void pair_fp64_row(double dx, double q, const double lam[3], double b0x, double b0y,
+                                              double b0z, double* acc, double* rs,
+                                              const double2* __restrict__ tab = nullptr) {
+    pair_fp64_core<TAN, WIDE, TAB, true>(dx, 0.0, q, lam, b0x, b0y, b0z, acc, rs, tab);
 }
 
 // FP64 pairs of the near-field window (shared by the finalize pass and the FP64 recompute of

@@ -95,12 +95,30 @@ __global__ __launch_bounds__(256) void k_field64(const Tile* __restrict__ tiles,
             double part[NA];
 #pragma unroll
             for (int r = 0; r < NA; ++r) part[r] = 0.0;
-            if (wide)
-                for (int k = 0; k < kn; ++k)
-                    pair_fp64<TAN, true>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part);
-            else
-                for (int k = 0; k < kn; ++k)
-                    pair_fp64<TAN, false, true>(sa[k] - u, sb[k] - v, w2, lm, sx[k], sy[k], sz[k], part, stab);
+            // the tile's pixels row by row: dy is the same along a row, so the y-moment rows come
+            // from per-row sums (A2 += dy (sum of A3 terms), T2 += dy (sum of A0 terms))
+            for (int k = 0; k < kn;) {
+                const int kend = min(kn, ((k0 + k) / bd.gcols + 1) * bd.gcols - k0);   // uniform
+                const double dy = sb[k] - v;
+                const double q = __builtin_fma(dy, dy, w2);
+                double rs[TAN ? 6 : 3];
+#pragma unroll
+                for (int r = 0; r < (TAN ? 6 : 3); ++r) rs[r] = 0.0;
+                if (wide)
+                    for (; k < kend; ++k) pair_fp64_row<TAN, true>(sa[k] - u, q, lm, sx[k], sy[k], sz[k], part, rs);
+                else
+                    for (; k < kend; ++k)
+                        pair_fp64_row<TAN, false, true>(sa[k] - u, q, lm, sx[k], sy[k], sz[k], part, rs, stab);
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    part[4 * p + 3] += rs[p];
+                    part[4 * p + 2] = __builtin_fma(dy, rs[p], part[4 * p + 2]);
+                    if (TAN) {
+                        part[4 * p + 0] += rs[3 + p];
+                        part[12 + 3 * p + 2] = __builtin_fma(dy, rs[3 + p], part[12 + 3 * p + 2]);
+                    }
+                }
+            }
 #pragma unroll
             for (int r = 0; r < NA; ++r) tot[r] += part[r];
         }
