@@ -183,16 +183,25 @@ constexpr int kVjp32F = 29;   // per point: xi_int, xi_frac, yi_int, yi_frac, w^
                               // window b, mask (as bits), Lambda [3]
 
 // GRID (9-node elements): output j sits at (a + af, b + bf) (integer part + fraction) and belongs to
-// element (ea, eb); the near mask is per element of the 3x3 window.
-template <int PPX, bool SLOW, bool GRID, bool FRACT>
+// element (ea, eb); the near mask is per element of the 3x3 window. ROWQ: the lane's PPX outputs are
+// consecutive points of one grid row, so dy, dy^2 + w^2 and -3 (beta + gy dy) are formed once per
+// point for all of them.
+template <int PPX, bool SLOW, bool GRID, bool FRACT, bool ROWQ>
 __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e, const float a[PPX],
                                             const float b[PPX], const float af[PPX], const float bf[PPX],
                                             const float ea[PPX], const float eb[PPX], float (&acc)[PPX][3]) {
     const float X = sp[0][e], xf = sp[1][e], Y = sp[2][e], yf = sp[3][e], w2 = sp[4][e];
+    float dyq = 0.0f, qq = 0.0f, cq[3] = {0.0f, 0.0f, 0.0f};
+    if (ROWQ) {
+        dyq = GRID ? (b[0] - Y) + (bf[0] - yf) : (b[0] - Y) - yf;
+        qq = fmaf(dyq, dyq, w2);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) cq[p] = fmaf(sp[20 + p][e], dyq, sp[14 + p][e]);
+    }
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
         const float dx = GRID ? (a[j] - X) + (af[j] - xf) : (a[j] - X) - xf;
-        const float dy = GRID ? (b[j] - Y) + (bf[j] - yf) : (b[j] - Y) - yf;
+        const float dy = ROWQ ? dyq : (GRID ? (b[j] - Y) + (bf[j] - yf) : (b[j] - Y) - yf);
         float keep = 1.0f;
         if (SLOW && GRID) {
             const float da = ea[j] - sp[23][e], db = eb[j] - sp[24][e];
@@ -205,7 +214,7 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
             const int bit = in ? (int)(da + (float)kNearWin) + kNearSide * (int)(db + (float)kNearWin) : 0;
             if (in && ((__float_as_uint(sp[25][e]) >> bit) & 1u)) keep = 0.0f;
         }
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, w2));
+        const float r2 = fmaf(dx, dx, ROWQ ? qq : fmaf(dy, dy, w2));
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * ri;
         const float ri2 = ri * ri * keep;   // a skipped pair zeroes both terms through 1 / r^2
@@ -223,15 +232,16 @@ __device__ __forceinline__ void vjp32_point(const float (*sp)[kVjp32Pts], int e,
             const float cri = cs * ri;
             const float nr3 = fmaf(sp[26 + p][e], sn, cri) * ri2;
             const float hr5 = fmaf(sp[5 + p][e], cri, nr3) * ri2;
-            const float lin = fmaf(sp[17 + p][e], dx, fmaf(sp[20 + p][e], dy, sp[14 + p][e]));
+            const float lin = fmaf(sp[17 + p][e], dx, ROWQ ? cq[p] : fmaf(sp[20 + p][e], dy, sp[14 + p][e]));
             acc[j][p] = fmaf(nr3, sp[11 + p][e], fmaf(hr5, lin, acc[j][p]));
         }
     }
 }
 
 // Outputs are the quadrature grid points (the pixels for the nodal rule), written to gW at the
-// grid's plane offsets.
-template <int PPX, bool GRID>
+// grid's plane offsets. Lane t owns the tile's points t, t + 256, ... or, ROWQ (every grid row a
+// multiple of PPX long), the PPX consecutive points PPX t .. PPX t + PPX - 1, which share a row.
+template <int PPX, bool GRID, bool ROWQ>
 __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptiles,
                                                 const BoundaryDev* __restrict__ bnd,
                                                 const int64_t* __restrict__ seg, const int32_t* __restrict__ perm,
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
     bool live[PPX];
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
-        const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
+        const int32_t k = pt.start + (ROWQ ? PPX * (int32_t)threadIdx.x + j : (int32_t)threadIdx.x + j * 256);
         live[j] = k < ngrid;
         const int32_t kc = live[j] ? k % bd.gcols : 0, kr = live[j] ? k / bd.gcols : 0;
         if (GRID) {
@@ -323,14 +333,14 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
             for (int p = 0; p < 3; ++p) part[j][p] = 0.0f;
         if (any_far) {
             if (any_near)
-                for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID, true>(sp, e, a, b, af, bf, ea, eb, part);
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID, true, ROWQ>(sp, e, a, b, af, bf, ea, eb, part);
             else
-                for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID, true>(sp, e, a, b, af, bf, ea, eb, part);
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID, true, ROWQ>(sp, e, a, b, af, bf, ea, eb, part);
         } else {
             if (any_near)
-                for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID, false>(sp, e, a, b, af, bf, ea, eb, part);
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, true, GRID, false, ROWQ>(sp, e, a, b, af, bf, ea, eb, part);
             else
-                for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID, false>(sp, e, a, b, af, bf, ea, eb, part);
+                for (int e = 0; e < n; ++e) vjp32_point<PPX, false, GRID, false, ROWQ>(sp, e, a, b, af, bf, ea, eb, part);
         }
 #pragma unroll
         for (int j = 0; j < PPX; ++j)
@@ -339,7 +349,7 @@ __global__ __launch_bounds__(256) void k_vjp32c(const PixTile* __restrict__ ptil
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
         if (!live[j]) continue;
-        const int64_t o = bd.gpl_off + pt.start + (int64_t)threadIdx.x + j * 256;
+        const int64_t o = bd.gpl_off + pt.start + (ROWQ ? PPX * (int64_t)threadIdx.x + j : (int64_t)threadIdx.x + j * 256);
         double* out = gW + (int64_t)blockIdx.y * slice_stride;
         for (int p = 0; p < 3; ++p) out[o + (int64_t)p * ngrid] = tot[j][p];
     }
@@ -530,12 +540,22 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
             hipLaunchKernelGGL(k_vjp64<kVjpPix64>, g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos, coef, parts,
                                T3);
         } else {
-            if (grid.G)
-                hipLaunchKernelGGL((k_vjp32c<kVjpPix, true>), g32, dim3(256), 0, s, ptd32, bnd, segd, ctx_perm(c),
-                                   grid.posf, geo, N, coef, parts, T3);
+            // rows of a multiple of kVjpPix points (and tiles starting at multiples of it): each lane's
+            // outputs share one row
+            bool rowq = true;
+            for (int32_t b = 0; b < ctx_nb(c); ++b) rowq = rowq && ctx_bnd_host(c, b).gcols % kVjpPix == 0;
+            if (grid.G && rowq)
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, true, true>), g32, dim3(256), 0, s, ptd32, bnd, segd,
+                                   ctx_perm(c), grid.posf, geo, N, coef, parts, T3);
+            else if (grid.G)
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, true, false>), g32, dim3(256), 0, s, ptd32, bnd, segd,
+                                   ctx_perm(c), grid.posf, geo, N, coef, parts, T3);
+            else if (rowq)
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, false, true>), g32, dim3(256), 0, s, ptd32, bnd, segd,
+                                   ctx_perm(c), grid.posf, geo, N, coef, parts, T3);
             else
-                hipLaunchKernelGGL((k_vjp32c<kVjpPix, false>), g32, dim3(256), 0, s, ptd32, bnd, segd, ctx_perm(c),
-                                   grid.posf, geo, N, coef, parts, T3);
+                hipLaunchKernelGGL((k_vjp32c<kVjpPix, false, false>), g32, dim3(256), 0, s, ptd32, bnd, segd,
+                                   ctx_perm(c), grid.posf, geo, N, coef, parts, T3);
         }
         if (gp.S > 1)
             hipLaunchKernelGGL(k_vjp_reduce, dim3((unsigned)((T3 + 255) / 256)), dim3(256), 0, s, T3, gp.S, parts, gW);
