@@ -45,6 +45,37 @@ def test_grad_matches_oracle(precision, tol):
     assert rel(r["resid_jac"].cpu(), jac) <= 10 * tol
 
 
+@pytest.mark.parametrize("sizes", [((24, 17), (40, 9)), ((24, 17), (21, 9))])
+def test_fp32c_adjoint_row_quads_and_strided_outputs_match_the_oracle(sizes):
+    """When every magnetogram row is a multiple of four pixels long (24 and 40), each lane of the FP32C
+    transpose owns four consecutive pixels of one row and forms the point's dy terms once for them;
+    with a 21-pixel row in the batch the outputs are 256 apart. Both match the oracle's transpose,
+    with points down to z = 0.4 (near-field pairs) and over the magnetogram edges."""
+    rng = np.random.default_rng(37)
+    bds, xyzs, seg, B0s = [], [], [0], []
+    for nx, ny in sizes:
+        n = 450
+        B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
+        B0s.append(B0)
+        bds.append(dict(B0=T(B0), x0=0.0, y0=0.0, h=1.0))
+        xyzs.append(np.stack([rng.uniform(-1, nx, n), rng.uniform(-1, ny, n), rng.uniform(0.4, 8.0, n)]))
+        seg.append(seg[-1] + n)
+    xyz = np.concatenate(xyzs, axis=1)
+    n = xyz.shape[1]
+    lam = rng.uniform(-0.6, 0.6, size=(3, n))
+    gB, gdB = rng.normal(size=(3, n)), rng.normal(size=(9, n))
+    ctx = D.dbie_init(bds, T(xyz), seg=seg, precision="fp32c")
+    r = D.dbie_grad(ctx, T(lam), gB=T(gB), gdB=T(gdB))
+    torch.cuda.synchronize()
+    parts = D.split_gB0(ctx, r["gB0"])
+    for b in range(2):
+        s0, s1 = seg[b], seg[b + 1]
+        ref, _, _ = oracle.vjp(B0s[b], 0.0, 0.0, 1.0, xyz[:, s0:s1], lam[:, s0:s1], gB[:, s0:s1], gdB[:, s0:s1])
+        e = rel(parts[b].cpu(), ref)
+        print("adjoint", sizes, b, "%.2e" % e, flush=True)
+        assert e <= 1e-5, (sizes, b)
+
+
 def test_fp32c_adjoint_on_batched_boundaries_and_determinism():
     rng = np.random.default_rng(35)
     bds, xyzs, seg, B0s = [], [], [0], []
