@@ -51,7 +51,7 @@ __global__ void k_vjp_coef(int64_t N, const BoundaryDev* __restrict__ bnd, Geo g
     }
 }
 
-template <int PPX>
+template <int PPX, bool ROWQ>
 __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptiles,
                                                const BoundaryDev* __restrict__ bnd,
                                                const int64_t* __restrict__ seg, Geo geo, int64_t N,
@@ -60,7 +60,9 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                                                int64_t slice_stride) {
     // sc rows: Lambda[3], alpha[3], then -3 beta[3], -3 gx[3], -3 gy[3] and -Lambda^2/3 [3], so that
     // H rho^-5 (beta + ...) is summed as (N - (Lambda^2/3) rho^2 cos t) rho^-5 (-3 beta + ...).
-    // Each lane owns PPX pixels (k, k + 256, ...): a point's 21 values read from LDS serve them all.
+    // Each lane owns PPX pixels (k, k + 256, ...; ROWQ, every grid row a multiple of PPX long: PPX
+    // consecutive pixels of one row, whose dy terms are formed once per point): a point's 21 values
+    // read from LDS serve them all.
     __shared__ double su[kVjpPts], sv[kVjpPts], sw2[kVjpPts], sc[kVjpCoef + 3][kVjpPts];
     __shared__ int s_wide;
     const PixTile pt = ptiles[blockIdx.x];
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
     double a[PPX], bb[PPX], acc[PPX][3];
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
-        const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
+        const int32_t k = pt.start + (ROWQ ? PPX * (int32_t)threadIdx.x + j : (int32_t)threadIdx.x + j * 256);
         const bool live = k < ngrid;
         a[j] = live ? gpos[bd.gpos_off + k % bd.gcols] : 0.0;
         bb[j] = live ? gpos[bd.gpos_off + bd.gcols + k / bd.gcols] : 0.0;
@@ -126,10 +128,19 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                     gy[p] = sc[12 + p][e];
                     l3[p] = sc[kVjpCoef + p][e];
                 }
+                // ROWQ: the lane's pixels share dy, dy^2 + w^2 and -3 (beta + gy dy), the same values the
+                // per-pixel form computes
+                double dyq = 0.0, qq = 0.0, cq[3] = {0.0, 0.0, 0.0};
+                if (ROWQ) {
+                    dyq = bb[0] - ve;
+                    qq = __builtin_fma(dyq, dyq, w2);
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) cq[p] = __builtin_fma(gy[p], dyq, be[p]);
+                }
 #pragma unroll
                 for (int j = 0; j < PPX; ++j) {
-                    const double dx = a[j] - ue, dy = bb[j] - ve;
-                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, w2));
+                    const double dx = a[j] - ue, dy = ROWQ ? dyq : bb[j] - ve;
+                    const double r2 = __builtin_fma(dx, dx, ROWQ ? qq : __builtin_fma(dy, dy, w2));
                     const double ri = WIDE ? rsqrt(r2) : rsqrt_pos(r2);
                     const double r = r2 * ri;
                     const double ri2 = ri * ri;
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
                         }
                         const double nn = __builtin_fma(t, sn, cs);
                         const double q = __builtin_fma(l3[p] * r2, cs, nn);   // -H / 3
-                        const double lin = __builtin_fma(gx[p], dx, __builtin_fma(gy[p], dy, be[p]));
+                        const double lin = __builtin_fma(gx[p], dx, ROWQ ? cq[p] : __builtin_fma(gy[p], dy, be[p]));
                         part[j][p] = __builtin_fma(nn * ri3, al[p], __builtin_fma(q * ri5, lin, part[j][p]));
                     }
                 }
@@ -165,7 +176,7 @@ __global__ __launch_bounds__(256) void k_vjp64(const PixTile* __restrict__ ptile
     double* out = gW + (int64_t)blockIdx.y * slice_stride;
 #pragma unroll
     for (int j = 0; j < PPX; ++j) {
-        const int32_t k = pt.start + (int32_t)threadIdx.x + j * 256;
+        const int32_t k = pt.start + (ROWQ ? PPX * (int32_t)threadIdx.x + j : (int32_t)threadIdx.x + j * 256);
         if (k < ngrid) {
             const int64_t o = bd.gpl_off + k;
             for (int p = 0; p < 3; ++p) out[o + (int64_t)p * ngrid] = acc[j][p];
@@ -537,8 +548,16 @@ extern "C" int dbie_grad(dbie_ctx* c, const double* lam, const double* gB, const
             hipLaunchKernelGGL(k_vjp_coef, dim3(gN), dim3(256), 0, s, N, bnd, geo, lam, gB, gdB, coef);
         const dim3 g64((unsigned)vt.n64, (unsigned)gp.S), g32((unsigned)vt.n32, (unsigned)gp.S);
         if (ctx_precision(c) == DBIE_FP64) {
-            hipLaunchKernelGGL(k_vjp64<kVjpPix64>, g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos, coef, parts,
-                               T3);
+            // rows of a multiple of kVjpPix64 points (tiles start at multiples of it): each lane's
+            // outputs share one row
+            bool rowq = true;
+            for (int32_t b = 0; b < ctx_nb(c); ++b) rowq = rowq && ctx_bnd_host(c, b).gcols % kVjpPix64 == 0;
+            if (rowq)
+                hipLaunchKernelGGL((k_vjp64<kVjpPix64, true>), g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos,
+                                   coef, parts, T3);
+            else
+                hipLaunchKernelGGL((k_vjp64<kVjpPix64, false>), g64, dim3(256), 0, s, ptd, bnd, segd, geo, N, grid.pos,
+                                   coef, parts, T3);
         } else {
             // rows of a multiple of kVjpPix points (and tiles starting at multiples of it): each lane's
             // outputs share one row
