@@ -228,9 +228,10 @@ DBIE_API int dbie_grad(dbie_ctx* ctx, const double* lambda, const double* gB, co
 DBIE_API int dbie_timing(dbie_ctx* ctx, int32_t enable);
 DBIE_API int dbie_timing_read(dbie_ctx* ctx, double* total_ms, int64_t* launches);
 
-/* Choose the FP32C tile shape (points per lane, waves per workgroup, pixels per LDS block = 8
- * columns x 16, 32 or 64 rows, and persistent != 0 for a persistent grid that pulls tiles from a
- * device counter) for both the plain pass and the pass with tangents. Only the shapes the library
+/* Choose the FP32C tile shape (points per lane, waves per workgroup, tile_pixels = 8 x the rows of the
+ * LDS pixel block, 16, 32 or 64 (a block spans 16 columns of a nodal magnetogram, 8 of an element
+ * grid), and persistent != 0 for a persistent grid that pulls tiles from a device counter) for both
+ * the plain pass and the pass with tangents. Only the shapes the library
  * was built with are accepted: (1, 2, 256), (1, 4, 256), (1, 8, 256), (2, 4, 256), (1, 4, 128),
  * (1, 4, 512) (DBIE_E_UNSUPPORTED otherwise; DBIE_E_UNSUPPORTED for an FP64 context). */
 DBIE_API int dbie_set_tile_shape(dbie_ctx* ctx, int32_t ppl, int32_t waves, int32_t tile_pixels,
@@ -248,8 +249,8 @@ DBIE_API int dbie_solve_trace_read(dbie_ctx* ctx, double* t_ms, int32_t* converg
                                    int32_t* n_rounds, double* t_end_ms);
 
 /* Sizes the context was built with: n_points, total pixels, FP32C tile shape (points per lane,
- * waves per workgroup, pixels per LDS tile) as chosen by defaults or the tuner. Any pointer may be
- * NULL. */
+ * waves per workgroup, tile_pixels as in dbie_set_tile_shape) as chosen by defaults or the tuner.
+ * Any pointer may be NULL. */
 DBIE_API int dbie_query(const dbie_ctx* ctx, int64_t* n_points, int64_t* n_pixels, int32_t* ppl,
                         int32_t* waves, int32_t* tile_pixels);
 /* The tile shape of the FP32C pass with mu-tangents (the LM solver's pass), and whether each pass

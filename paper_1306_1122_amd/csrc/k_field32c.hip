@@ -6,12 +6,12 @@
 // partial, and the finalize pass adds the slices in order); static schedules are ordered by
 // decreasing cost. Lane l of the workgroup owns points l, l + NT, ...
 // of the tile, so a wavefront holds 64 consecutive points (the library orders points so that these
-// are spatially coherent). The magnetogram streams through LDS in blocks of RB x kCols pixels (three
-// planes Bx, By, Bz; RB = 16, 32 or 64 rows, a tuning parameter; HBM holds kRows x kCols blocks,
-// tile-major, so a 64-row block stages two consecutive HBM blocks of one column strip and a 16-row
-// block half of one); every lane reads the same LDS address (broadcast).
+// are spatially coherent). The magnetogram streams through LDS in blocks of RB rows (three planes Bx,
+// By, Bz; RB = 16, 32 or 64, a tuning parameter) by 16 columns, or 8 on an element grid; HBM holds
+// kRows x kCols blocks, tile-major, so a nodal block stages the rows it needs from two adjacent column
+// strips; every lane reads the same LDS address (broadcast).
 //
-// Arithmetic per pair, all FP32. For each block and point the kCols column offsets
+// Arithmetic per pair, all FP32. For each block and point the column offsets
 //   dx_c = (a0 + c - floor(u)) - frac(u)           (exact integer difference, one rounding)
 // are kept in registers; for each row dy = (b0 + r - floor(v)) - frac(v) and q = dy^2 + w^2; then
 //   rho^2 = dx_c^2 + q, rho^-1 = rsq(rho^2), and per component t = Lambda rho, sin/cos in
@@ -25,12 +25,13 @@
 //   T0 += cos t rho^-1 B0, T1 += N rho^-3 B0 dx, T2 += N rho^-3 B0 dy; there the T0 term
 //   cos t rho^-1 B0 is shared by N rho^-3 B0 = rho^-2 (Lambda sin t B0 + cos t rho^-1 B0) and by
 //   Q rho^-3 B0.
-// Rows: dy is the same for the kCols pairs of a block row, so the row's A3 terms (and, with tangents,
+// Rows: dy is the same for the pairs of a block row, so the row's A3 terms (and, with tangents,
 // its A0 terms) are summed apart, and A2 += dy (row sum of A3 terms), T2 += dy (row sum of A0 terms)
 // once per row: no per-pair products with dy.
 // SCALAR: the three components share one lambda, so t, sin, cos, N and Q are computed once per pair.
-// Compensation: each block is summed in FP32 (error ~ 256 u), and the block partials are added into
-// FP64 totals, so the error does not grow with the magnetogram size.
+// Compensation: at most kRows rows of a block (512 pairs per point, 256 on an element grid) are summed
+// in FP32, and these partials are added into FP64 totals, so the error does not grow with the
+// magnetogram size.
 // Near field: pairs whose (FP64-classified) distance is below the near radius are skipped here and
 // summed in FP64 by the finalize pass. Blocks that cannot contain such a pair for any point of the
 // wavefront take the unmasked loop; the test is uniform over the wavefront.
@@ -41,6 +42,13 @@
 #include "dbie_internal.h"
 
 namespace dbie {
+
+// Columns of an LDS pixel block: nodal blocks take two adjacent HBM column strips, so that the per-row
+// work (dy, q, the row fold) is shared by 16 pairs; element grids keep one strip (their column
+// positions are staged per block, eight of them).
+template <bool GRID>
+constexpr int block_cols() { return GRID ? kCols : 2 * kCols; }
+static_assert(block_cols<false>() % 4 == 0 && block_cols<true>() % 4 == 0, "rows are read as float4");
 
 template <int PPL, bool TAN>
 struct PointState {
@@ -144,32 +152,30 @@ __device__ __forceinline__ void pair32_scalar(float dx, float q, float nl3, floa
     }
 }
 
-// One block of RB x kCols pixels with origin (a0, b0) and `rows` valid rows, for all PPL points.
+// Rows r0 .. r1 - 1 of a block of RB x block_cols pixels with origin (a0, b0), for all PPL points.
 // GRID (9-node elements): the block's columns and rows sit at the positions sC, sR ({integer part,
 // fraction, element index}) instead of at a0 + c, b0 + r, and the near mask is per element.
 template <int PPL, int RB, bool TAN, bool SLOW, bool FRACT, bool SCALAR, bool GRID>
 __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
-                                           const float4 (*sB)[RB][kCols / 4], const float4* sC,
-                                           const float4* sR, float a0, float b0, int rows,
+                                           const float4 (*sB)[RB][block_cols<GRID>() / 4], const float4* sC,
+                                           const float4* sR, float a0, float b0, int r0, int r1,
                                            float (&part)[PPL][TAN ? kAcc : kAccField]) {
-    static_assert(kCols == 8, "the row body reads two float4 per plane");
-    float dxc[PPL][kCols];
+    constexpr int KC = block_cols<GRID>();
+    float dxc[PPL][KC];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         const float base = a0 + S.xn[j];   // exact: integers
 #pragma unroll
-        for (int c = 0; c < kCols; ++c) {
+        for (int c = 0; c < KC; ++c) {
             if (GRID) dxc[j][c] = (sC[c].x + S.xn[j]) + (sC[c].y - S.xf[j]);
             else dxc[j][c] = (base + (float)c) - S.xf[j];
         }
     }
-    for (int r = 0; r < rows; ++r) {
-        const float4 X0 = sB[0][r][0], X1 = sB[0][r][1];
-        const float4 Y0 = sB[1][r][0], Y1 = sB[1][r][1];
-        const float4 Z0 = sB[2][r][0], Z1 = sB[2][r][1];
-        const float bxs[kCols] = {X0.x, X0.y, X0.z, X0.w, X1.x, X1.y, X1.z, X1.w};
-        const float bys[kCols] = {Y0.x, Y0.y, Y0.z, Y0.w, Y1.x, Y1.y, Y1.z, Y1.w};
-        const float bzs[kCols] = {Z0.x, Z0.y, Z0.z, Z0.w, Z1.x, Z1.y, Z1.z, Z1.w};
+    for (int r = r0; r < r1; ++r) {
+        // the row's three planes (broadcast reads of KC / 4 float4 each)
+        const float* bxs = reinterpret_cast<const float*>(&sB[0][r][0]);
+        const float* bys = reinterpret_cast<const float*>(&sB[1][r][0]);
+        const float* bzs = reinterpret_cast<const float*>(&sB[2][r][0]);
         const float brow = b0 + (float)r;
         // GRID: the row's split position (the element index is read only by the masked loop)
         float2 rp = make_float2(0.0f, 0.0f);
@@ -180,7 +186,7 @@ __device__ __forceinline__ void block_loop(const PointState<PPL, TAN>& S,
             const float q = fmaf(dy, dy, S.w2[j]);
             float rs[TAN ? 6 : 3];   // the row sums of the A3 terms and, with tangents, of the A0 terms
 #pragma unroll
-            for (int c = 0; c < kCols; ++c) {
+            for (int c = 0; c < KC; ++c) {
                 float bx = bxs[c], by = bys[c], bz = bzs[c];
                 if (SLOW && GRID) {
                     const float da = sC[c].z - S.fa[j], db = sR[r].z - S.fb[j];
@@ -229,8 +235,10 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
                                               const float* __restrict__ pixf, const float4* __restrict__ gposf,
                                               const Geo& geo, const double* __restrict__ lam, int64_t N,
                                               const int32_t* __restrict__ idx, double* __restrict__ acc,
-                                              float4 (*sB)[RB][kCols / 4], float4* sC, float4* sR) {
+                                              float4 (*sB)[RB][block_cols<GRID>() / 4], float4* sC, float4* sR) {
     constexpr int NT = 64 * WAVES;
+    constexpr int KC = block_cols<GRID>();
+    constexpr int KQ = KC / 4;              // float4 per row of a plane of an LDS block
     constexpr int NA = TAN ? kAcc : kAccField;
     constexpr int BQ = kRows * kCols / 4;   // float4 per plane of an HBM block
     constexpr int RQ = kCols / 4;           // float4 per row of a plane
@@ -275,7 +283,7 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
             // farthest pixel centre of the (column-padded) magnetogram from this point
             const float uf = -S.xn[j] + S.xf[j], vf = -S.yn[j] + S.yf[j];
             // (grid positions, padding included, lie in [0, nx - 1] x [0, ny - 1])
-            const float xe = GRID ? (float)(bd.nx - 1) : (float)(bd.ntx * kCols - 1);
+            const float xe = GRID ? (float)(bd.nx - 1) : (float)((bd.ntx + 1) / 2 * KC - 1);
             const float dxm = fmaxf(fabsf(uf), fabsf(xe - uf)) + 1.0f;
             const float dym = fmaxf(fabsf(vf), fabsf((float)(bd.ny - 1) - vf)) + 1.0f;
             const float rmax = sqrtf(dxm * dxm + dym * dym + S.w2[j]);
@@ -310,19 +318,36 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
         for (int r = 0; r < NA; ++r) tot[j][r] = 0.0;
 
     const float4* P = reinterpret_cast<const float4*>(pixf + bd.pixf_off);
-    // LDS blocks of RB rows over the grid's rows (every block holds at least one row); pixel split:
-    // slice blockIdx.z of gridDim.z takes an even share of them
+    // LDS blocks of RB rows (every block holds at least one row) over strips of KC columns (the last
+    // nodal strip may hold one HBM strip and zeros); pixel split: slice blockIdx.z of gridDim.z takes
+    // an even share of them
     const int nrows = GRID ? bd.grows : bd.ny;
     const int nrb = (nrows + RB - 1) / RB;
-    const int nblk_all = bd.ntx * nrb;
+    const int nstrip = GRID ? bd.ntx : (bd.ntx + 1) / 2;
+    const int nblk_all = nstrip * nrb;
     const int kb0 = (int)((int64_t)blockIdx.z * nblk_all / gridDim.z);
     const int nblk = (int)((int64_t)(blockIdx.z + 1) * nblk_all / gridDim.z);
     for (int k = kb0; k < nblk; ++k) {
-        const int ty = k / bd.ntx, tx = k - ty * bd.ntx;
-        const int a0 = tx * kCols, b0 = ty * RB;
+        const int ty = k / nstrip, tx = k - ty * nstrip;
+        const int a0 = tx * KC, b0 = ty * RB;
         const int rows = min(RB, nrows - b0);
         __syncthreads();
-        if (RB == kRows) {
+        if (!GRID) {
+            // the block's rows from the HBM blocks of column strips 2 tx and 2 tx + 1 that hold them
+            // (rows b0 .. b0 + rows - 1 < nrows <= nty * kRows lie inside the padded magnetogram; a
+            // strip beyond the last, ntx odd, reads as zeros)
+            for (int q = tid; q < 3 * RB * KQ; q += NT) {
+                const int pl = q / (RB * KQ), o = q - pl * (RB * KQ);
+                const int r = o / KQ, h = o - r * KQ;
+                const int st = 2 * tx + h / RQ, hh = h - (h / RQ) * RQ;
+                if (r < rows) {
+                    const int b = b0 + r, hb = b / kRows;
+                    sB[pl][r][h] = st < bd.ntx
+                                       ? P[((int64_t)(hb * bd.ntx + st) * 3 + pl) * BQ + (b - hb * kRows) * RQ + hh]
+                                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+            }
+        } else if (RB == kRows) {
             // one HBM block, contiguous
             for (int q = tid; q < 3 * BQ; q += NT) {
                 const int pl = q / BQ, o = q - pl * BQ;
@@ -354,25 +379,30 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
                 const int eb0 = b0 / bd.G, eb1 = (b0 + rows - 1) / bd.G;
                 slow = !(eb1 < bmin || eb0 > bmax || ea1 < amin || ea0 > amax);
             } else {
-                slow = !(b0 + rows - 1 < bmin || b0 > bmax || a0 + kCols - 1 < amin || a0 > amax);
+                slow = !(b0 + rows - 1 < bmin || b0 > bmax || a0 + KC - 1 < amin || a0 > amax);
             }
         }
-#pragma unroll
-        for (int j = 0; j < PPL; ++j)
-#pragma unroll
-            for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
         const float fa0 = (float)a0, fb0 = (float)b0;
-        if (!slow) {
-            if (need_fract) block_loop<PPL, RB, TAN, false, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
-            else block_loop<PPL, RB, TAN, false, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
-        } else {
-            if (need_fract) block_loop<PPL, RB, TAN, true, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
-            else block_loop<PPL, RB, TAN, true, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, rows, part);
+        // FP32 partials over at most kRows rows of the block (kRows x block_cols pairs per point), each
+        // then added into the FP64 totals
+        for (int h0 = 0; h0 < rows; h0 += kRows) {
+            const int h1 = min(rows, h0 + kRows);
+#pragma unroll
+            for (int j = 0; j < PPL; ++j)
+#pragma unroll
+                for (int r = 0; r < NA; ++r) part[j][r] = 0.0f;
+            if (!slow) {
+                if (need_fract) block_loop<PPL, RB, TAN, false, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, h0, h1, part);
+                else block_loop<PPL, RB, TAN, false, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, h0, h1, part);
+            } else {
+                if (need_fract) block_loop<PPL, RB, TAN, true, true, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, h0, h1, part);
+                else block_loop<PPL, RB, TAN, true, false, SCALAR, GRID>(S, sB, sC, sR, fa0, fb0, h0, h1, part);
+            }
+#pragma unroll
+            for (int j = 0; j < PPL; ++j)
+#pragma unroll
+                for (int r = 0; r < NA; ++r) tot[j][r] += (double)part[j][r];
         }
-#pragma unroll
-        for (int j = 0; j < PPL; ++j)
-#pragma unroll
-            for (int r = 0; r < NA; ++r) tot[j][r] += (double)part[j][r];
     }
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
@@ -389,8 +419,12 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 // Either one workgroup per tile (work == NULL), or persistent: a grid sized to the resident
 // workgroups pulls tile indices from the device counter `work` (cleared by a kernel before the
 // launch) until the schedule is exhausted; every workgroup reaches the exit test after each tile.
+// Occupancy bounds: three waves per SIMD (at most 168 VGPRs) for the nodal one-point-per-lane forms,
+// whose 16-column rows would otherwise take two (their spills stay outside the pixel loop, around the
+// per-block FP64 totals); four for the plain element form.
 template <int PPL, int WAVES, int RB, bool TAN, bool SCALAR, bool GRID>
-__global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ? 4 : 1) void k_field32c(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ? 4
+                                        : (!GRID && PPL == 1) ? 3 : 1) void k_field32c(const Tile* __restrict__ tiles,
                                                          int64_t n_tiles,
                                                          const BoundaryDev* __restrict__ bnd,
                                                          const float* __restrict__ pixf,
@@ -399,7 +433,7 @@ __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ?
                                                          const int32_t* __restrict__ idx,
                                                          int32_t* __restrict__ work,
                                                          double* __restrict__ acc) {
-    __shared__ float4 sB[3][RB][kCols / 4];
+    __shared__ float4 sB[3][RB][block_cols<GRID>() / 4];
     __shared__ float4 sC[GRID ? kCols : 1], sR[GRID ? RB : 1];
     if (!work) {
         field32c_tile<PPL, WAVES, RB, TAN, SCALAR, GRID>(tiles[blockIdx.x], bnd, pixf, gposf, geo, lam, N, idx, acc,
@@ -418,8 +452,8 @@ __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ?
     }
 }
 
-// The instantiated shapes (points per lane, waves per workgroup, rows of the LDS pixel block of
-// kCols columns); shapes whose tangent variant would spill registers to scratch are left out.
+// The instantiated shapes (points per lane, waves per workgroup, rows of the LDS pixel block); the
+// shape's pixel count is rows x kCols whatever the block's width.
 #define DBIE_F32_SHAPES(X) \
     X(1, 2, 32)            \
     X(1, 4, 32)            \
