@@ -50,6 +50,12 @@ template <bool GRID>
 constexpr int block_cols() { return GRID ? kCols : 2 * kCols; }
 static_assert(block_cols<false>() % 4 == 0 && block_cols<true>() % 4 == 0, "rows are read as float4");
 
+// Where the 21 FP64 totals of the nodal tangent form with one point per lane live: in LDS (one
+// column per lane, 168 bytes), so that its 16-column rows fit three waves per SIMD without spilling
+// registers to scratch memory.
+template <int PPL, bool TAN, bool GRID>
+constexpr bool lds_totals() { return TAN && !GRID && PPL == 1; }
+
 template <int PPL, bool TAN>
 struct PointState {
     float xn[PPL], xf[PPL], yn[PPL], yf[PPL], w2[PPL];
@@ -235,7 +241,8 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
                                               const float* __restrict__ pixf, const float4* __restrict__ gposf,
                                               const Geo& geo, const double* __restrict__ lam, int64_t N,
                                               const int32_t* __restrict__ idx, double* __restrict__ acc,
-                                              float4 (*sB)[RB][block_cols<GRID>() / 4], float4* sC, float4* sR) {
+                                              float4 (*sB)[RB][block_cols<GRID>() / 4], float4* sC, float4* sR,
+                                              double* __restrict__ sT) {
     constexpr int NT = 64 * WAVES;
     constexpr int KC = block_cols<GRID>();
     constexpr int KQ = KC / 4;              // float4 per row of a plane of an LDS block
@@ -310,12 +317,17 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
     const bool any_near = amin <= amax;
     const bool need_fract = !(rv_w < 255.0f);
 
-    double tot[PPL][NA];
+    // the FP64 totals: in registers, or (LT) in the lane's own LDS column sT[r * NT + tid]
+    constexpr bool LT = lds_totals<PPL, TAN, GRID>();
+    double tot[LT ? 1 : PPL][LT ? 1 : NA];
     float part[PPL][NA];
 #pragma unroll
     for (int j = 0; j < PPL; ++j)
 #pragma unroll
-        for (int r = 0; r < NA; ++r) tot[j][r] = 0.0;
+        for (int r = 0; r < NA; ++r) {
+            if (LT) sT[r * NT + tid] = 0.0;
+            else tot[LT ? 0 : j][LT ? 0 : r] = 0.0;
+        }
 
     const float4* P = reinterpret_cast<const float4*>(pixf + bd.pixf_off);
     // LDS blocks of RB rows (every block holds at least one row) over strips of KC columns (the last
@@ -401,7 +413,10 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 #pragma unroll
             for (int j = 0; j < PPL; ++j)
 #pragma unroll
-                for (int r = 0; r < NA; ++r) tot[j][r] += (double)part[j][r];
+                for (int r = 0; r < NA; ++r) {
+                    if (LT) sT[r * NT + tid] += (double)part[j][r];
+                    else tot[LT ? 0 : j][LT ? 0 : r] += (double)part[j][r];
+                }
         }
     }
 #pragma unroll
@@ -411,7 +426,8 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
         for (int r = 0; r < NA; ++r) {
             // rows A1..A3 were summed as -1/3 of their terms
             const double sc = (r < kAccField && (r & 3) != 0) ? -3.0 : 1.0;
-            acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + pid[j]] = sc * tot[j][r];
+            const double v = LT ? sT[r * NT + tid] : tot[LT ? 0 : j][LT ? 0 : r];
+            acc[(((int64_t)blockIdx.z * gridDim.y + trial) * kAcc + r) * N + pid[j]] = sc * v;
         }
     }
 }
@@ -420,8 +436,9 @@ __device__ __forceinline__ void field32c_tile(const Tile t, const BoundaryDev* _
 // workgroups pulls tile indices from the device counter `work` (cleared by a kernel before the
 // launch) until the schedule is exhausted; every workgroup reaches the exit test after each tile.
 // Occupancy bounds: three waves per SIMD (at most 168 VGPRs) for the nodal one-point-per-lane forms,
-// whose 16-column rows would otherwise take two (their spills stay outside the pixel loop, around the
-// per-block FP64 totals); four for the plain element form.
+// whose 16-column rows would otherwise take two (the tangent form fits by keeping its FP64 totals in
+// LDS; with 64-row blocks its LDS allows two workgroups per compute unit, and it runs at two waves
+// per SIMD without spills); four for the plain element form.
 template <int PPL, int WAVES, int RB, bool TAN, bool SCALAR, bool GRID>
 __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ? 4
                                         : (!GRID && PPL == 1) ? 3 : 1) void k_field32c(const Tile* __restrict__ tiles,
@@ -435,9 +452,10 @@ __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ?
                                                          double* __restrict__ acc) {
     __shared__ float4 sB[3][RB][block_cols<GRID>() / 4];
     __shared__ float4 sC[GRID ? kCols : 1], sR[GRID ? RB : 1];
+    __shared__ double sT[lds_totals<PPL, TAN, GRID>() ? kAcc * 64 * WAVES : 1];
     if (!work) {
         field32c_tile<PPL, WAVES, RB, TAN, SCALAR, GRID>(tiles[blockIdx.x], bnd, pixf, gposf, geo, lam, N, idx, acc,
-                                                         sB, sC, sR);
+                                                         sB, sC, sR, sT);
         return;
     }
     __shared__ int next;
@@ -448,7 +466,7 @@ __global__ __launch_bounds__(64 * WAVES, (GRID && !TAN && !SCALAR && PPL == 1) ?
         __syncthreads();
         if (ti >= n_tiles) break;
         field32c_tile<PPL, WAVES, RB, TAN, SCALAR, GRID>(tiles[ti], bnd, pixf, gposf, geo, lam, N, idx, acc, sB,
-                                                         sC, sR);
+                                                         sC, sR, sT);
     }
 }
 
