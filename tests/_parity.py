@@ -5,10 +5,12 @@ of every point, |x_gpu - x_ref| <= c u S, where S is the row's sum of absolute t
 (oracle.field(..., absolute=True)) and u the path's unit roundoff, with c = c0 + 4 t^2 and t the
 point's largest phase max_p |lambda_p| r_max in radians: c0 = 512 for FP64 (recursive sums of
 128-term tiles and of the tile partials, sin/cos and 1/sqrt to a few ulp, the oracle's own rounding),
-c0 = 1024 for FP32C (block sums of 256 FP32 terms, each term to ~10 u); 4 t^2 covers the rounding of
+c0 = 1024 for FP32C (partial sums of up to 512 FP32 terms, each term to ~10 u); 4 t^2 covers the rounding of
 the distance r (relative u, so a phase error t u) times the kernel's sensitivity to the phase (~t),
 in both the path and the oracle. f and g are compared where they are well conditioned: |J| and
-|div B| at least 1e-2 of |grad B| (no cancellation) and f >= 1e-2.
+|div B| at least 1e-2 of |grad B| (no cancellation), f >= 1e-2, and, where the sums of absolute
+terms are known, |B| at least 1e-2 of its own (f and g divide by |B| (Eqs. 8 and 9), so a point where
+the field cancels carries the FP32 rounding of its terms into both).
 """
 import numpy as np
 
@@ -46,12 +48,16 @@ def check_pointwise(out, ref, absref, precision, tmax, label):
     return worst
 
 
-def well_conditioned_fg(B, dB, res):
+def well_conditioned_fg(B, dB, res, aB=None):
+    """Points where f and g are well conditioned; aB: the sums of absolute terms of B, if known."""
     J = np.stack([dB[7] - dB[5], dB[2] - dB[6], dB[3] - dB[1]])
     nJ, nG = np.linalg.norm(J, axis=0), np.linalg.norm(dB, axis=0)
     D_ = np.abs(dB[0] + dB[4] + dB[8])
     okf = np.isfinite(res["f"]) & (nJ >= 1e-2 * nG) & (res["f"] >= 1e-2)
     okg = np.isfinite(res["g"]) & (D_ >= 1e-2 * nG)
+    if aB is not None:
+        okB = np.linalg.norm(B, axis=0) >= 1e-2 * np.linalg.norm(aB, axis=0)
+        okf, okg = okf & okB, okg & okB
     return okf, okg
 
 
@@ -69,7 +75,7 @@ def check_sampled(got, bd, xyz, lam, precision, label, fg=None, tol=None):
     errs["pointwise"] = check_pointwise(got, ref, absref, precision, max_phase(bd, xyz, lam), label)
     if fg is not None:
         res = oracle.residuals(B, dB, bd.h)
-        okf, okg = well_conditioned_fg(B, dB, res)
+        okf, okg = well_conditioned_fg(B, dB, res, aB)
         errs["f"] = rel(fg[0][okf], res["f"][okf]) if okf.any() else 0.0
         errs["g"] = rel(fg[1][okg], res["g"][okg]) if okg.any() else 0.0
     print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)

@@ -231,19 +231,20 @@ def test_pixel_slices_match_one_slice_and_the_oracle(G, precision):
         assert rel(outs[0][k].cpu(), ref) <= (1e-5 if precision == "fp32c" else 1e-10), k
 
 
-@pytest.mark.parametrize("G", [0, 2])
+@pytest.mark.parametrize("G,nx", [(0, 77), (0, 71), (2, 77)])
 @pytest.mark.parametrize("tile_pixels", [128, 256, 512])
-def test_every_pixel_block_height_matches_the_oracle(tile_pixels, G):
-    """LDS pixel blocks of 16, 32 and 64 rows x 8 columns (the 64-row block stages two HBM blocks, the
-    16-row block half of one) on a 77 x 45 magnetogram, whose 45 rows (44 grid rows with elements)
-    leave a ragged last block for every height; points below 2 pixels (masked near field) and beyond
-    the magnetogram; one and three pixel slices and the persistent form; the passes with and without
-    tangents and the single-lambda pass. Every run equals the oracle (nodal rule: relative L2 and the
-    pointwise bound at every point; elements: relative L2) and the 32-row blocks up to the FP32
-    rounding of the regrouped block sums."""
+def test_every_pixel_block_height_matches_the_oracle(tile_pixels, G, nx):
+    """LDS pixel blocks of 16, 32 and 64 rows (16 columns wide on the nodal grid, staged from two
+    8-column HBM strips; 8 on the element grid) on an nx x 45 magnetogram, whose 45 rows (44 grid rows
+    with elements) leave a ragged last block for every height; 71 columns make an odd number of
+    8-column strips, so the last nodal block holds one strip and zeros. Points below 2 pixels (masked
+    near field) and beyond the magnetogram; one and three pixel slices and the persistent form; the
+    passes with and without tangents and the single-lambda pass. Every run equals the oracle (nodal
+    rule: relative L2 and the pointwise bound at every point; elements: relative L2) and the 32-row
+    blocks up to the FP32 rounding of the regrouped block sums."""
     from workloads import Boundary
     rng = np.random.default_rng(53)
-    nx, ny = 77, 45
+    ny = 45
     B0 = rng.normal(size=(3, ny, nx)).astype(np.float32).astype(np.float64)
     n = 1500
     xyz = np.stack([rng.uniform(-2, nx + 1, n), rng.uniform(-2, ny + 1, n), rng.uniform(0.4, 30, n)])
