@@ -401,7 +401,7 @@ hipError_t launch_quad_transpose(const BoundaryDev& bd, const double* gW, const 
 struct F32Shape {
     int32_t ppl;      // points per lane
     int32_t waves;    // waves per workgroup
-    int32_t tp;       // pixels per LDS block
+    int32_t tp;       // kCols x the rows of the LDS pixel block (nodal blocks are 2 kCols wide)
     int32_t persist;  // 1: persistent grid pulling tiles from a device counter
 };
 
