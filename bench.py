@@ -56,7 +56,7 @@ def cpu_baseline(w, n_sample, seed=7):
     from workloads import z_stratified_subsample
     bd = w.boundaries[0]
     idx = z_stratified_subsample(w.xyz, n_sample, seed)
-    # one worker per host core, at most 16 (the GPU machine's CPU share)
+    # one worker per host core, at most 16 (the host CPUs one GPU is allotted)
     cores = min(os.cpu_count() or 1, 16)
     chunks = np.array_split(idx, cores * 4)
     jobs = [(bd.B0, bd.x0, bd.y0, bd.h, w.xyz[:, c], w.lam[:, c]) for c in chunks if c.size]
